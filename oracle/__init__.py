@@ -47,6 +47,7 @@ class _Params(C.Structure):
         ("sor_omega", C.c_double), ("sor_tol", C.c_double), ("sor_max_sweeps", C.c_int32),
         ("weno_eps", C.c_double), ("rescale", C.c_int32), ("fd_enable", C.c_int32),
         ("q_literal", C.c_int32), ("eps_n", C.c_double), ("recolour_literal", C.c_int32),
+        ("fd_eps", C.c_double), ("upwind_eps", C.c_double),
     ]
 
 
@@ -123,7 +124,7 @@ def params_struct(p: dict) -> _Params:
         for a in range(3):
             s.wall_u[w][a] = p["wall_u"][w][a]
     for k in ("rhoR0", "rhoB0", "muR0", "muB0", "alphaR", "beta", "sigma0", "E0", "psi_inf",
-              "sigma_min_ratio", "Ds", "Db", "ra", "rd", "sor_omega", "sor_tol", "weno_eps", "eps_n"):
+              "sigma_min_ratio", "Ds", "Db", "ra", "rd", "sor_omega", "sor_tol", "weno_eps", "eps_n", "fd_eps", "upwind_eps"):
         setattr(s, k, float(p[k]))
     for k in ("source_mode", "sor_max_sweeps", "rescale", "fd_enable", "q_literal", "recolour_literal"):
         setattr(s, k, int(p[k]))

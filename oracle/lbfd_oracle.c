@@ -50,6 +50,8 @@ typedef struct {
     int32_t q_literal;        /* 3-D correction factor: 0 = [1 - 3 cs^2] (reading), 1 = printed [1 - cs^2] */
     double eps_n;             /* regularisation of the normal where |grad rhoN| -> 0 */
     int32_t recolour_literal; /* eq 11 weight: 0 = local rest equilibrium per unit density (reading), 1 = lattice w_i */
+    double fd_eps;          /* background added to the FD weights G = |grad rhoN| and X = 1 - rhoN */
+    double upwind_eps;      /* |u_a| at or below this takes both one-sided WENO differences by halves */
 } orc_params;
 
 typedef struct {
@@ -157,7 +159,7 @@ typedef struct orc_state {
     double *F[3], *u[3], *sv, *ku[2][3], *dku[2][3];
     /* work arrays of the FD stage */
     double *rhoN1, *G1, *g1[3], *X0, *X1, *Psi[3], *Phi[3], *divPsi, *divPhi;
-    double *S, *B, *rhsP, *rhsF, *tmp;
+    double *S, *B, *rhsP, *rhsF, *tmp, *Gw;
     double *dump_fdag;        /* when set, the LB stage also stores f_dag here (Q x N) */
 } orc_state;
 
@@ -549,7 +551,9 @@ static void lb_stage(orc_state *s)
 /* WENO3 convective derivative of eqs 25-27 along every axis:
    out = sum_a [H+(u_a) D-_a Psi_a + H-(u_a) D+_a Psi_a], with
    H+ = u^+/|u|, H- = |u^-|/|u|. Reading: the printed u^-/|u| is negative for
-   u < 0; its magnitude is meant. At u_a = 0 both are 1/2. */
+   u < 0; its magnitude is meant. Reading: where |u_a| <= upwind_eps (and at
+   u_a = 0, where the printed form is 0/0) both are 1/2, so that the upwind
+   choice never rests on the sign of a velocity at the level of rounding. */
 static void op_weno_div(const orc_state *s, double *const *Psi, double *const *u, double *out)
 {
     double eps = s->p.weno_eps;
@@ -575,7 +579,7 @@ static void op_weno_div(const orc_state *s, double *const *Psi, double *const *u
 #undef DP
 #undef DD
             double ua = u[a][n], hp, hm;
-            if (ua == 0.0) { hp = 0.5; hm = 0.5; }
+            if (fabs(ua) <= s->p.upwind_eps) { hp = 0.5; hm = 0.5; }
             else { hp = fmax(ua, 0.0) / fabs(ua); hm = fabs(fmin(ua, 0.0)) / fabs(ua); }
             acc += hp * Dm + hm * Dp;
         }
@@ -665,6 +669,14 @@ static int op_solve(const orc_state *s, const double *W, double Dc, const double
     return result;
 }
 
+/* Weight of a node in the surfactant equations. Reading: the delta function
+   |grad rhoN|/2 and the indicator (1 - rhoN)/2 of eqs 20-21 carry a small
+   uniform background fd_eps, so that psi (phi) stays defined where the
+   weight itself vanishes. Without it, the weights of the tanh tails shrink
+   as the interface sharpens, psi = (G psi)/G grows like G^t/G^{t+1} step
+   after step and the source G j feeds it back until overflow. */
+static double fd_weight(const orc_state *s, double w) { return w + s->p.fd_eps; }
+
 /* Conserved integrand of eqs 20-21, summed serially in node order. */
 static double total_surfactant(const orc_state *s, const double *G, const double *X, const double *psi,
                                const double *phi)
@@ -691,14 +703,15 @@ static int fd_stage(orc_state *s)
     for (long n = 0; n < N; ++n) {
         double G2 = 0.0;
         for (int a = 0; a < D; ++a) G2 += s->g1[a][n] * s->g1[a][n];
-        s->G1[n] = sqrt(G2);
-        s->X1[n] = 1.0 - s->rhoN1[n];
-        s->X0[n] = 1.0 - s->rhoN[n];
+        s->G1[n] = fd_weight(s, sqrt(G2));
+        s->X1[n] = fd_weight(s, 1.0 - s->rhoN1[n]);
+        s->X0[n] = fd_weight(s, 1.0 - s->rhoN[n]);
+        s->Gw[n] = fd_weight(s, s->G[n]);
     }
     /* fluxes Psi = psi |grad rhoN| u and Phi = phi (1 - rhoN) u at time t */
     for (int a = 0; a < D; ++a)
         for (long n = 0; n < N; ++n) {
-            s->Psi[a][n] = s->psi[n] * s->G[n] * s->u[a][n];
+            s->Psi[a][n] = s->psi[n] * s->Gw[n] * s->u[a][n];
             s->Phi[a][n] = s->phi[n] * s->X0[n] * s->u[a][n];
         }
     op_weno_div(s, s->Psi, s->u, s->divPsi);
@@ -707,16 +720,16 @@ static int fd_stage(orc_state *s)
         double psi = s->psi[n], phi = s->phi[n];
         double jj = p->source_mode == 1 ? p->ra * p->psi_inf * phi
                                         : p->ra * phi * (p->psi_inf - psi) - p->rd * psi; /* eq 22 */
-        s->S[n] = -s->divPsi[n] + s->G[n] * jj;
-        s->B[n] = -s->divPhi[n] - s->G[n] * jj;
+        s->S[n] = -s->divPsi[n] + s->Gw[n] * jj;
+        s->B[n] = -s->divPhi[n] - s->Gw[n] * jj;
     }
     /* explicit half of the diffusion, then the right-hand sides of eqs 23/24 */
-    op_diffusion(s, s->G, s->psi, s->rhsP);
+    op_diffusion(s, s->Gw, s->psi, s->rhsP);
     op_diffusion(s, s->X0, s->phi, s->rhsF);
     for (long n = 0; n < N; ++n) {
         double eS = s->step == 0 ? s->S[n] : 1.5 * s->S[n] - 0.5 * s->Sprev[n];
         double eB = s->step == 0 ? s->B[n] : 1.5 * s->B[n] - 0.5 * s->Bprev[n];
-        s->rhsP[n] = s->G[n] * s->psi[n] + 0.5 * p->Ds * s->rhsP[n] + eS;
+        s->rhsP[n] = s->Gw[n] * s->psi[n] + 0.5 * p->Ds * s->rhsP[n] + eS;
         s->rhsF[n] = s->X0[n] * s->phi[n] + 0.5 * p->Db * s->rhsF[n] + eB;
     }
     /* implicit half: psi, phi at t+1, initial guess the values at t */
@@ -770,7 +783,7 @@ orc_state *orc_create(const orc_params *p)
     A(s->psi, N); A(s->phi, N); A(s->Sprev, N); A(s->Bprev, N);
     A(s->rhoR, N); A(s->rhoB, N); A(s->rho, N); A(s->rhoN, N); A(s->G, N); A(s->kappa, N); A(s->sv, N);
     A(s->rhoN1, N); A(s->G1, N); A(s->X0, N); A(s->X1, N); A(s->divPsi, N); A(s->divPhi, N);
-    A(s->S, N); A(s->B, N); A(s->rhsP, N); A(s->rhsF, N); A(s->tmp, N);
+    A(s->S, N); A(s->B, N); A(s->rhsP, N); A(s->rhsF, N); A(s->tmp, N); A(s->Gw, N);
     for (int a = 0; a < 3; ++a) {
         A(s->j[a], N); A(s->g[a], N); A(s->nrm[a], N); A(s->gpsi[a], N); A(s->F[a], N); A(s->u[a], N);
         A(s->g1[a], N); A(s->Psi[a], N); A(s->Phi[a], N);
@@ -786,7 +799,7 @@ void orc_destroy(orc_state *s)
     if (!s) return;
     double **all[] = {&s->fR, &s->fB, &s->fR2, &s->fB2, &s->psi, &s->phi, &s->Sprev, &s->Bprev,
                       &s->rhoR, &s->rhoB, &s->rho, &s->rhoN, &s->G, &s->kappa, &s->sv, &s->rhoN1, &s->G1,
-                      &s->X0, &s->X1, &s->divPsi, &s->divPhi, &s->S, &s->B, &s->rhsP, &s->rhsF, &s->tmp};
+                      &s->X0, &s->X1, &s->divPsi, &s->divPhi, &s->S, &s->B, &s->rhsP, &s->rhsF, &s->tmp, &s->Gw};
     for (size_t i = 0; i < sizeof(all) / sizeof(all[0]); ++i) free(*all[i]);
     for (int a = 0; a < 3; ++a) {
         free(s->j[a]); free(s->g[a]); free(s->nrm[a]); free(s->gpsi[a]); free(s->F[a]); free(s->u[a]);
@@ -834,8 +847,8 @@ int orc_init(orc_state *s, const orc_init_spec *in)
     s->drift_pre = 0.0;
     s->sweeps[0] = s->sweeps[1] = 0;
     force_stage(s);
-    for (long n = 0; n < N; ++n) s->X0[n] = 1.0 - s->rhoN[n];
-    s->M0 = total_surfactant(s, s->G, s->X0, s->psi, s->phi);
+    for (long n = 0; n < N; ++n) { s->X0[n] = fd_weight(s, 1.0 - s->rhoN[n]); s->Gw[n] = fd_weight(s, s->G[n]); }
+    s->M0 = total_surfactant(s, s->Gw, s->X0, s->psi, s->phi);
     return ORC_OK;
 }
 
@@ -932,9 +945,9 @@ int orc_observables(orc_state *s, orc_obs *o)
     if (!s || !o) return ORC_EINVAL;
     memset(o, 0, sizeof(*o));
     force_stage(s);
-    for (long n = 0; n < s->N; ++n) s->X0[n] = 1.0 - s->rhoN[n];
+    for (long n = 0; n < s->N; ++n) { s->X0[n] = fd_weight(s, 1.0 - s->rhoN[n]); s->Gw[n] = fd_weight(s, s->G[n]); }
     o->step = s->step;
-    o->total_surf = total_surfactant(s, s->G, s->X0, s->psi, s->phi);
+    o->total_surf = total_surfactant(s, s->Gw, s->X0, s->psi, s->phi);
     o->drift_pre = s->drift_pre;
     o->sor_sweeps[0] = s->sweeps[0];
     o->sor_sweeps[1] = s->sweeps[1];

@@ -1,0 +1,1510 @@
+// lbfd.hip -- MI355X (gfx950) solver for the hybrid lattice-Boltzmann
+// colour-gradient / finite-difference method for two-phase flow with soluble
+// surfactants (Ba, Liu, Li, Yang; arXiv 2311.15242), behind the C ABI of lbfd.h.
+//
+// Per time step n -> n+1 the stream carries:
+//   collide  MRT collision with correction and forcing terms (eqs 1-4, App. A),
+//            recolouring descriptor (eqs 11-12), push propagation with
+//            half-way bounce-back (eq 13)
+//   macro    rho^R, rho^B, rhoN (eq 6) and momentum of step n+1
+//   geom     |grad rhoN| and the normal at n+1 (below eq 6)
+//   fd       WENO3 convection (eqs 25-27), sources (eq 22), explicit half of
+//            the diffusion (eq 28) and the Crank-Nicolson right-hand sides
+//            (eqs 23-24)
+//   sor      red-black SOR sweeps of the two implicit systems (Sec 2.2)
+//   total    FP64 deterministic sum of the conserved surfactant and the
+//            rescaling factor (applied lazily by every later reader)
+//   force    curvature (eq 7), equation of state (eq 8), interfacial force
+//            (eq 9), buoyancy (Sec 3.4) and velocity (eq 10) of step n+1
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbfd.h"
+#include "lbfd_kernels.h"
+
+namespace lbfd {
+
+constexpr int BX = 64, BY = 4;          // one wavefront spans 64 consecutive x
+constexpr int NRED = 19;                 // observable partial sums per block
+
+struct InitDev {
+    int n;
+    double cx[16], cy[16], cz[16], r[16];
+    double width, psi0, phi0_out, phi0_in, shear_rate;
+};
+
+// ============================================================== initial state
+
+// Colour field and per-colour equilibria of the initial state at one node.
+template <int LAT, class R>
+__device__ void init_node(const KP<R> &k, const InitDev &in, int x, int y, int z, R &rN, R *fR, R *fB, R *u0)
+{
+    using L = Lat<LAT>;
+    double best = -1.0;
+    for (int d = 0; d < in.n; ++d) {
+        double dx = x - in.cx[d], dy = y - in.cy[d], dz = L::D == 3 ? z - in.cz[d] : 0.0;
+        double v = tanh(2.0 * (in.r[d] - sqrt(dx * dx + dy * dy + dz * dz)) / in.width);
+        if (d == 0 || v > best) best = v;
+    }
+    rN = (R)best;
+    R rR = k.rhoR0 * (R(1) + rN) / R(2), rB = k.rhoB0 * (R(1) - rN) / R(2);
+    u0[0] = (R)(in.shear_rate * (y - 0.5 * (k.ny - 1)));
+    u0[1] = 0;
+    u0[2] = 0;
+    // f^k = M^-1 m^{k,eq}(rho^k, alpha^k, u0): the moments below are eq 37 / eq 40
+    for (int c = 0; c < 2; ++c) {
+        R rho = c == 0 ? rR : rB, m[QMAX];
+        R al = k.alpha[c];
+        R ux = u0[0], uy = u0[1], uz = u0[2], u2 = ux * ux + uy * uy + uz * uz;
+        if constexpr (L::D == 2) {
+            m[0] = rho; m[1] = rho * (R(-3.6) * al - R(0.4) + R(3) * u2); m[2] = rho * (R(5.4) * al - R(1.4) - R(3) * u2);
+            m[3] = rho * ux; m[4] = rho * (R(-1.8) * al - R(0.2)) * ux; m[5] = rho * uy;
+            m[6] = rho * (R(-1.8) * al - R(0.2)) * uy; m[7] = rho * (ux * ux - uy * uy); m[8] = rho * ux * uy;
+        } else {
+            R pk = rho * k.cs2[c];
+            m[0] = rho; m[1] = rho * ux; m[2] = rho * uy; m[3] = rho * uz; m[4] = R(3) * pk + rho * u2;
+            m[5] = rho * (R(2) * ux * ux - uy * uy - uz * uz); m[6] = rho * (uy * uy - uz * uz);
+            m[7] = rho * ux * uy; m[8] = rho * ux * uz; m[9] = rho * uy * uz;
+            m[10] = pk * uy; m[11] = pk * ux; m[12] = pk * uz; m[13] = pk * ux; m[14] = pk * uz; m[15] = pk * uy;
+            R b = R(1) - al - u2;
+            m[16] = rho * (b + R(2) * (ux * ux + uy * uy)) / R(6);
+            m[17] = rho * (b + R(2) * (ux * ux + uz * uz)) / R(6);
+            m[18] = rho * (b + R(2) * (uy * uy + uz * uz)) / R(6);
+        }
+        R *out = c == 0 ? fR : fB;
+        for (int i = 0; i < L::Q; ++i) {
+            R a = 0;
+            for (int r = 0; r < L::Q; ++r) a += R(L::MINV[i][r]) * m[r];
+            out[i] = a;
+        }
+    }
+}
+
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_init_a(KP<typename P::R> k, InitDev in)
+{
+    using R = typename P::R;
+    using L = Lat<LAT>;
+    Node nd = node_id(k);
+    if (!nd.ok) return;
+    const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
+    R rN0, fR[QMAX], fB[QMAX], u0[3];
+    init_node<LAT, R>(k, in, nd.x, nd.y, nd.z, rN0, fR, fB, u0);
+    R rR = 0, rB = 0, j[3] = {0, 0, 0};
+    for (int i = 0; i < L::Q; ++i) {
+        rR += fR[i];
+        rB += fB[i];
+        for (int d = 0; d < L::D; ++d) j[d] += (fR[i] + fB[i]) * R(L::E[i][d]);
+    }
+    R rr = rR / k.rhoR0, bb = rB / k.rhoB0;
+    R *mac = k.fld.mac[k.lev];
+    mac[n] = rR;
+    mac[N + n] = rB;
+    mac[2 * N + n] = (rr - bb) / (rr + bb);
+    for (int d = 0; d < L::D; ++d) mac[(3 + d) * N + n] = j[d];
+    // descriptor of the (virtual) step -1 that produced f^0: reference data only
+    R *ds = k.fld.desc[1 - k.lev];
+    R rho = rR + rB;
+    ds[n] = rR / rho;
+    for (int d = 0; d < L::D; ++d) ds[(1 + d) * N + n] = 0;
+    if constexpr (P::DEV) {
+        ds[(1 + L::D) * N + n] = rho;
+        for (int d = 0; d < L::D; ++d) ds[(2 + L::D + d) * N + n] = j[d] / rho;
+    }
+    k.fld.psi[k.pc][n] = (R)in.psi0;
+    k.fld.phi[k.pc][n] = rN0 < R(0) ? (R)in.phi0_out : (R)in.phi0_in;
+    k.fld.Sp[n] = 0;
+    k.fld.Bp[n] = 0;
+}
+
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_init_b(KP<typename P::R> k, InitDev in)
+{
+    using R = typename P::R;
+    using S = typename P::S;
+    using L = Lat<LAT>;
+    Node nd = node_id(k);
+    if (!nd.ok) return;
+    const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
+    R rN0, fR[QMAX], fB[QMAX], u0[3];
+    init_node<LAT, R>(k, in, nd.x, nd.y, nd.z, rN0, fR, fB, u0);
+    S *f = (S *)k.fld.f[k.fc];
+    const R *ds = k.fld.desc[1 - k.lev];
+    for (int j = 0; j < L::Q; ++j) {
+        R v = fR[j] + fB[j];
+        if constexpr (P::DEV) {
+            int pre;
+            long long src = source_of<LAT, R>(k, nd.x, nd.y, nd.z, j, pre);
+            R us[3] = {0, 0, 0};
+            for (int d = 0; d < L::D; ++d) us[d] = ds[(2 + L::D + d) * N + src];
+            v -= reference<LAT, R>(k, j, ds[(1 + L::D) * N + src], ds[src], us);
+            f[(long long)j * N + n] = from_real<S>(v);
+        } else {
+            f[(long long)j * N + n] = v;
+        }
+    }
+}
+
+// State import from FP64 arrays (device copies): pass a writes the macroscopic
+// fields and the decoding descriptor, pass b stores the populations.
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void k_import_a(KP<typename P::R> k, const double *f, const double *rR_,
+                                                 const double *rB_, const double *psi, const double *phi,
+                                                 const double *Sp, const double *Bp)
+{
+    using R = typename P::R;
+    using L = Lat<LAT>;
+    Node nd = node_id(k);
+    if (!nd.ok) return;
+    const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
+    R rR = (R)rR_[n], rB = (R)rB_[n], j[3] = {0, 0, 0};
+    for (int i = 0; i < L::Q; ++i)
+        for (int d = 0; d < L::D; ++d) j[d] += (R)f[i * N + n] * R(L::E[i][d]);
+    R rr = rR / k.rhoR0, bb = rB / k.rhoB0;
+    R *mac = k.fld.mac[k.lev];
+    mac[n] = rR;
+    mac[N + n] = rB;
+    mac[2 * N + n] = (rr - bb) / (rr + bb);
+    for (int d = 0; d < L::D; ++d) mac[(3 + d) * N + n] = j[d];
+    R *ds = k.fld.desc[1 - k.lev];
+    R rho = rR + rB;
+    ds[n] = rR / rho;
+    for (int d = 0; d < L::D; ++d) ds[(1 + d) * N + n] = 0;
+    if constexpr (P::DEV) {
+        ds[(1 + L::D) * N + n] = rho;
+        for (int d = 0; d < L::D; ++d) ds[(2 + L::D + d) * N + n] = j[d] / rho;
+    }
+    k.fld.psi[k.pc][n] = (R)psi[n];
+    k.fld.phi[k.pc][n] = (R)phi[n];
+    k.fld.Sp[n] = Sp ? (R)Sp[n] : R(0);
+    k.fld.Bp[n] = Bp ? (R)Bp[n] : R(0);
+}
+
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_import_b(KP<typename P::R> k, const double *f)
+{
+    using R = typename P::R;
+    using S = typename P::S;
+    using L = Lat<LAT>;
+    Node nd = node_id(k);
+    if (!nd.ok) return;
+    const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
+    S *fo = (S *)k.fld.f[k.fc];
+    const R *ds = k.fld.desc[1 - k.lev];
+    for (int j = 0; j < L::Q; ++j) {
+        R v = (R)f[j * N + n];
+        if constexpr (P::DEV) {
+            int pre;
+            long long src = source_of<LAT, R>(k, nd.x, nd.y, nd.z, j, pre);
+            R us[3] = {0, 0, 0};
+            for (int d = 0; d < L::D; ++d) us[d] = ds[(2 + L::D + d) * N + src];
+            v -= reference<LAT, R>(k, j, ds[(1 + L::D) * N + src], ds[src], us);
+            fo[(long long)j * N + n] = from_real<S>(v);
+        } else {
+            fo[(long long)j * N + n] = v;
+        }
+    }
+}
+
+// ============================================================== geometry
+
+// |grad rhoN| and the regularised normal n = -grad rhoN / sqrt(|grad rhoN|^2 + eps^2)
+// of the time level `level` (below eq 6).
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_geom(KP<typename P::R> k, int level)
+{
+    using R = typename P::R;
+    using L = Lat<LAT>;
+    Node nd = node_id(k);
+    if (!nd.ok) return;
+    const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
+    const R *rN = k.fld.mac[level] + 2 * N;
+    R g[3], G2 = 0;
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) {
+        g[a] = lat_deriv<LAT, R>(k, rN, R(1), nd.x, nd.y, nd.z, a, -1);
+        G2 += g[a] * g[a];
+    }
+    k.fld.G[level][n] = sqrt(G2);
+    R den = sqrt(G2 + k.eps_n * k.eps_n);
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) k.fld.nrm[a * N + n] = den > R(0) ? -g[a] / den : R(0);
+}
+
+// ============================================================== forces
+
+// Curvature (eq 7), modified Langmuir EOS (eq 8), interfacial force with the
+// Marangoni term (eq 9), buoyancy (Sec 3.4), total force and velocity (eq 10)
+// at the current time level.
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_force(KP<typename P::R> k)
+{
+    using R = typename P::R;
+    using L = Lat<LAT>;
+    constexpr int D = L::D;
+    Node nd = node_id(k);
+    if (!nd.ok) return;
+    const int x = nd.x, y = nd.y, z = nd.z;
+    const long long N = k.N, n = lin(k, x, y, z);
+    const R *mac = k.fld.mac[k.lev];
+    const R s = (R)k.fld.sc->scale;
+    const R *psiA = k.fld.psi[k.pc];
+    R g[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, nv[3] = {0, 0, 0}, kappa = 0, G2 = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        g[a] = lat_deriv<LAT, R>(k, mac + 2 * N, R(1), x, y, z, a, -1);
+        G2 += g[a] * g[a];
+        kappa -= lat_deriv<LAT, R>(k, k.fld.nrm + a * N, R(1), x, y, z, a, a);
+        gp[a] = lat_deriv<LAT, R>(k, psiA, s, x, y, z, a, -1);
+        nv[a] = k.fld.nrm[a * N + n];
+    }
+    const R G = sqrt(G2);
+    const R psi = s * psiA[n];
+    R Fs[3] = {0, 0, 0};
+    if (k.E0 == R(0)) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) Fs[a] = R(-0.5) * k.sigma0 * kappa * g[a];
+    } else if (psi < k.cmc) {
+        R sigma = k.sigma0 * (R(1) + k.E0 * log(R(1) - psi / k.psi_inf));
+        R ndg = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) ndg += nv[a] * gp[a];
+        R mar = R(0.5) * G * k.sigma0 * k.E0 / (k.psi_inf - psi);
+#pragma unroll
+        for (int a = 0; a < D; ++a) Fs[a] = R(-0.5) * sigma * kappa * g[a] - mar * (gp[a] - ndg * nv[a]);
+    } else {
+#pragma unroll
+        for (int a = 0; a < D; ++a) Fs[a] = R(-0.5) * k.sigma_min * kappa * g[a];
+    }
+    const R rho = mac[n] + mac[N + n];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        R Fa = Fs[a] + (rho - k.rhoB0) * k.grav[a];
+        k.fld.F[a * N + n] = Fa;
+        k.fld.u[a * N + n] = (mac[(3 + a) * N + n] + R(0.5) * Fa) / rho;
+    }
+}
+
+// ============================================================== collision
+
+// MRT collision in moment space (eqs 1-4 with the equilibria, corrections and
+// relaxation rates of Appendix A), the recolouring descriptor of eqs 11-12,
+// and push propagation (eq 13) into the other population buffer.
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<typename P::R> k)
+{
+    using R = typename P::R;
+    using S = typename P::S;
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q, D = L::D;
+    Node nd = node_id(k);
+    if (!nd.ok) return;
+    const int x = nd.x, y = nd.y, z = nd.z;
+    const long long N = k.N, n = lin(k, x, y, z);
+    const S *fin = (const S *)k.fld.f[k.fc];
+    S *fout = (S *)k.fld.f[1 - k.fc];
+    const R *mac = k.fld.mac[k.lev];
+    const R *dprev = k.fld.desc[1 - k.lev];
+    R *dnew = k.fld.desc[k.lev];
+
+    R f[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        long long src = 0;
+        if constexpr (P::DEV) {
+            int pre;
+            src = source_of<LAT, R>(k, x, y, z, j, pre);
+        }
+        f[j] = load_pop<LAT, P>(k, fin, n, j, src, dprev);
+    }
+    const R rR = mac[n], rB = mac[N + n], rN = mac[2 * N + n];
+    const R rho = rR + rB;
+    R u[3] = {0, 0, 0}, F[3] = {0, 0, 0}, g[3] = {0, 0, 0}, G2 = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        u[d] = k.fld.u[d * N + n];
+        F[d] = k.fld.F[d * N + n];
+        g[d] = lat_deriv<LAT, R>(k, mac + 2 * N, R(1), x, y, z, d, -1);
+        G2 += g[d] * g[d];
+    }
+    // relaxation rate of the viscous moments (eq 43 and the mu-s_v relation)
+    const R inv_mu = (R(1) + rN) / (R(2) * k.muR0) + (R(1) - rN) / (R(2) * k.muB0);
+    const R pk = rR * k.cs2[0] + rB * k.cs2[1];
+    const R sv = R(1) / ((R(1) / inv_mu) / pk + R(0.5));
+
+    // m = M f
+    R m[Q];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+        R a = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            if (L::M[r][i] != 0) a += R(L::M[r][i]) * f[i];
+        m[r] = a;
+    }
+    // equilibria summed over colours (eq 37 / eq 40)
+    R meq[Q], C[Q];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) { meq[r] = 0; C[r] = 0; }
+    const R ux = u[0], uy = u[1], uz = u[2], u2 = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const R rk = c == 0 ? rR : rB;
+        const R al = k.alpha[c];
+        if constexpr (D == 2) {
+            meq[0] += rk; meq[1] += rk * (R(-3.6) * al - R(0.4) + R(3) * u2);
+            meq[2] += rk * (R(5.4) * al - R(1.4) - R(3) * u2);
+            meq[3] += rk * ux; meq[4] += rk * (R(-1.8) * al - R(0.2)) * ux;
+            meq[5] += rk * uy; meq[6] += rk * (R(-1.8) * al - R(0.2)) * uy;
+            meq[7] += rk * (ux * ux - uy * uy); meq[8] += rk * ux * uy;
+        } else {
+            const R pc = rk * k.cs2[c];
+            meq[0] += rk; meq[1] += rk * ux; meq[2] += rk * uy; meq[3] += rk * uz;
+            meq[4] += R(3) * pc + rk * u2; meq[5] += rk * (R(2) * ux * ux - uy * uy - uz * uz);
+            meq[6] += rk * (uy * uy - uz * uz); meq[7] += rk * ux * uy; meq[8] += rk * ux * uz;
+            meq[9] += rk * uy * uz; meq[10] += pc * uy; meq[11] += pc * ux; meq[12] += pc * uz;
+            meq[13] += pc * ux; meq[14] += pc * uz; meq[15] += pc * uy;
+            const R b = R(1) - al - u2;
+            meq[16] += rk * (b + R(2) * (ux * ux + uy * uy)) / R(6);
+            meq[17] += rk * (b + R(2) * (ux * ux + uz * uz)) / R(6);
+            meq[18] += rk * (b + R(2) * (uy * uy + uz * uz)) / R(6);
+        }
+    }
+    // correction terms C^k with Q_a = qcoef_k d_a(rho^k u_a) (Appendix A)
+    if (k.qon) {
+        const R *uvec = k.fld.u;
+        R Qa[2][3] = {{0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            R acc0 = 0, acc1 = 0;
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                if (L::OPP[i] < i || L::E[i][a] == 0) continue;
+                R s1, s2;
+                long long p = nb(k, x, y, z, L::E[i][0], L::E[i][1], L::E[i][2], a, s1);
+                long long q = nb(k, x, y, z, -L::E[i][0], -L::E[i][1], -L::E[i][2], a, s2);
+                R up = s1 * uvec[a * N + p], uq = s2 * uvec[a * N + q];
+                R we = R(L::W[i] * L::E[i][a]);
+                acc0 += we * (mac[p] * up - mac[q] * uq);
+                acc1 += we * (mac[N + p] * up - mac[N + q] * uq);
+            }
+            Qa[0][a] = k.qcoef[0] * R(3) * acc0;
+            Qa[1][a] = k.qcoef[1] * R(3) * acc1;
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if constexpr (D == 2) {
+                C[1] += R(3) * Qa[c][0] + R(3) * Qa[c][1];
+                C[7] += Qa[c][0] - Qa[c][1];
+            } else {
+                C[4] += Qa[c][0] + Qa[c][1] + Qa[c][2];
+                C[5] += R(2) * Qa[c][0] - Qa[c][1] - Qa[c][2];
+                C[6] += Qa[c][1] - Qa[c][2];
+            }
+        }
+    }
+    // forcing term in velocity space (eq 4 integrand), projected with M
+    R Fi[Q];
+    const R uF = ux * F[0] + uy * F[1] + uz * F[2];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        R eF = 0, eu = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) { eF += R(L::E[i][d]) * F[d]; eu += R(L::E[i][d]) * u[d]; }
+        Fi[i] = R(L::W[i]) * (R(3) * (eF - uF) + R(9) * eu * eF);
+    }
+    // dm = -S (m - meq) + (I - S/2)(C + F_m); f_dag = f + M^-1 dm (eqs 1-3)
+    R dm[Q];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+        R Fm = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            if (L::M[r][i] != 0) Fm += R(L::M[r][i]) * Fi[i];
+        R sr;
+        if constexpr (D == 2) {
+            sr = r == 1 ? R(1.25) : r == 2 ? R(1.14) : (r == 4 || r == 6) ? R(1.6) : (r >= 7) ? sv : R(0);
+        } else {
+            sr = (r >= 5 && r <= 9) ? sv : R(1);
+        }
+        dm[r] = -sr * (m[r] - meq[r]) + (R(1) - R(0.5) * sr) * (C[r] + Fm);
+    }
+    // recolouring descriptor (eqs 11-12): colour share and c = beta rho^R rho^B / rho g/|g|
+    const R a = rR / rho;
+    const R Gm = sqrt(G2);
+    const R cf = Gm > R(0) ? k.beta * (rR * rB / rho) / Gm : R(0);
+    dnew[n] = a;
+#pragma unroll
+    for (int d = 0; d < D; ++d) dnew[(1 + d) * N + n] = cf * g[d];
+    R us[3] = {0, 0, 0};
+    if constexpr (P::DEV) {
+        dnew[(1 + D) * N + n] = rho;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            us[d] = u[d] + R(0.5) * F[d] / rho;
+            dnew[(2 + D + d) * N + n] = us[d];
+        }
+    }
+    // propagation with periodic wrap or half-way bounce-back
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        R v = f[i];
+#pragma unroll
+        for (int r = 0; r < Q; ++r)
+            if (L::MINV[i][r] != 0.0) v += R(L::MINV[i][r]) * dm[r];
+        int c[3] = {x + L::E[i][0], y + L::E[i][1], z + L::E[i][2]};
+        const int lim[3] = {k.nx, k.ny, k.nz};
+        int wall = -1;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+            if (wall < 0 && k.bc[ax] && (c[ax] < 0 || c[ax] >= lim[ax])) wall = 2 * ax + (c[ax] >= lim[ax] ? 1 : 0);
+        long long dest;
+        int j;
+        if (wall >= 0) {
+            R eu = R(L::E[i][0]) * k.wall_u[wall][0] + R(L::E[i][1]) * k.wall_u[wall][1] +
+                   R(L::E[i][2]) * k.wall_u[wall][2];
+            v -= R(2) * R(L::W[i]) * rho * eu * R(3);
+            j = L::OPP[i];
+            dest = n;
+        } else {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) c[ax] = c[ax] < 0 ? c[ax] + lim[ax] : (c[ax] >= lim[ax] ? c[ax] - lim[ax] : c[ax]);
+            j = i;
+            dest = lin(k, c[0], c[1], c[2]);
+        }
+        if constexpr (P::DEV) {
+            v -= reference<LAT, R>(k, j, rho, a, us);
+            fout[(long long)j * N + dest] = from_real<S>(v);
+        } else {
+            fout[(long long)j * N + dest] = v;
+        }
+    }
+}
+
+// ============================================================== macroscopic fields
+
+// rho^R, rho^B of the streamed populations, rebuilt from the recolouring
+// descriptors of the nodes they left (eq 11 summed over arrivals), the colour
+// function (eq 6) and the momentum sum f e, into mac of the next level.
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<typename P::R> k)
+{
+    using R = typename P::R;
+    using S = typename P::S;
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q, D = L::D;
+    Node nd = node_id(k);
+    if (!nd.ok) return;
+    const int x = nd.x, y = nd.y, z = nd.z;
+    const long long N = k.N, n = lin(k, x, y, z);
+    const S *fin = (const S *)k.fld.f[1 - k.fc];
+    const R *ds = k.fld.desc[k.lev];
+    R rR = 0, rB = 0, j[3] = {0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        int pre;
+        long long src = source_of<LAT, R>(k, x, y, z, q, pre);
+        R fq = load_pop<LAT, P>(k, fin, n, q, src, ds);
+        R as = ds[src], ec = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) ec += R(L::E[pre][d]) * ds[(1 + d) * N + src];
+        R wgt = k.recolour_literal ? R(L::W[q]) : as * k.rest[0][q] + (R(1) - as) * k.rest[1][q];
+        R r = wgt * ec;
+        rR += as * fq + r;
+        rB += (R(1) - as) * fq - r;
+#pragma unroll
+        for (int d = 0; d < D; ++d) j[d] += fq * R(L::E[q][d]);
+    }
+    R *mac = k.fld.mac[1 - k.lev];
+    R rr = rR / k.rhoR0, bb = rB / k.rhoB0;
+    mac[n] = rR;
+    mac[N + n] = rB;
+    mac[2 * N + n] = (rr - bb) / (rr + bb);
+#pragma unroll
+    for (int d = 0; d < D; ++d) mac[(3 + d) * N + n] = j[d];
+}
+
+// ============================================================== finite differences
+
+// WENO3 one-sided differences of eqs 26-27 at the centre of a 5-point line.
+template <class R> __device__ __forceinline__ void weno_pair(const R *P, R eps, R &Dm, R &Dp)
+{
+    // P[0..4] = Psi at i-2..i+2
+    R d_2 = P[1] - P[0], d_1 = P[2] - P[1], d0 = P[3] - P[2], d1 = P[4] - P[3];
+    R dd_1 = P[2] - R(2) * P[1] + P[0], dd0 = P[3] - R(2) * P[2] + P[1], dd1 = P[4] - R(2) * P[3] + P[2];
+    R rm = (eps + dd_1 * dd_1) / (eps + dd0 * dd0);
+    R wm = R(1) / (R(1) + R(2) * rm * rm);
+    Dm = R(0.5) * ((d_1 + d0) - wm * (d_2 - R(2) * d_1 + d0));
+    R rp = (eps + dd1 * dd1) / (eps + dd0 * dd0);
+    R wp = R(1) / (R(1) + R(2) * rp * rp);
+    Dp = R(0.5) * ((d_1 + d0) - wp * (d1 - R(2) * d0 + d_1));
+}
+
+// Explicit part of the modified Crank-Nicolson step (eqs 20-28): WENO3
+// convection of Psi = psi G u and Phi = phi X u, adsorption source, AB2 (or
+// Euler at the first step), explicit half of the diffusion; writes the
+// right-hand sides, S^n and B^n, and the rescaled initial guess of the solve.
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typename P::R> k)
+{
+    using R = typename P::R;
+    using L = Lat<LAT>;
+    constexpr int D = L::D;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+        DevScalars *sc = k.fld.sc;
+        sc->rmax[0] = sc->rmax[1] = 0ull;
+        for (int s = 0; s < MAX_SWEEPS; ++s) sc->res[0][s] = sc->res[1][s] = 0ull;
+    }
+    Node nd = node_id(k);
+    if (!nd.ok) return;
+    const int x = nd.x, y = nd.y, z = nd.z;
+    const long long N = k.N, n = lin(k, x, y, z);
+    const R s = (R)k.fld.sc->scale;
+    const R *psiA = k.fld.psi[k.pc], *phiA = k.fld.phi[k.pc];
+    const R *G0 = k.fld.G[k.lev];
+    const R *rN0 = k.fld.mac[k.lev] + 2 * N;
+    const R *uv = k.fld.u;
+    R divP = 0, divF = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        R Pp[5], Pf[5];
+#pragma unroll
+        for (int o = -2; o <= 2; ++o) {
+            int dd[3] = {0, 0, 0};
+            dd[a] = o;
+            R sg;
+            long long q = nb(k, x, y, z, dd[0], dd[1], dd[2], a, sg);
+            R ua = uv[a * N + q];
+            Pp[o + 2] = sg * ((s * psiA[q]) * (G0[q] + k.fd_eps) * ua);
+            Pf[o + 2] = sg * ((s * phiA[q]) * ((R(1) - rN0[q]) + k.fd_eps) * ua);
+        }
+        R Dm, Dp, ua = uv[a * N + n], hp, hm;
+        if (fabs(ua) <= k.upwind_eps) { hp = R(0.5); hm = R(0.5); }
+        else { hp = fmax(ua, R(0)) / fabs(ua); hm = fabs(fmin(ua, R(0))) / fabs(ua); }
+        weno_pair(Pp, k.weno_eps, Dm, Dp);
+        divP += hp * Dm + hm * Dp;
+        weno_pair(Pf, k.weno_eps, Dm, Dp);
+        divF += hp * Dm + hm * Dp;
+    }
+    const R psi = s * psiA[n], phi = s * phiA[n];
+    // weights of eqs 20-21 with the background support
+    const R Gn = G0[n] + k.fd_eps, Xn = (R(1) - rN0[n]) + k.fd_eps;
+    const R jj = k.source_mode == 1 ? k.ra * k.psi_inf * phi : k.ra * phi * (k.psi_inf - psi) - k.rd * psi;
+    const R Sn = -divP + Gn * jj, Bn = -divF - Gn * jj;
+    const R eS = k.step == 0 ? Sn : R(1.5) * Sn - R(0.5) * k.fld.Sp[n];
+    const R eB = k.step == 0 ? Bn : R(1.5) * Bn - R(0.5) * k.fld.Bp[n];
+    // diffusion operator of eq 28 with half-point weights, as printed
+    R swP = 0, swcP = 0, swF = 0, swcF = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int o = -1; o <= 1; o += 2) {
+            int dd[3] = {0, 0, 0};
+            dd[a] = o;
+            R sg;
+            long long q = nb(k, x, y, z, dd[0], dd[1], dd[2], -1, sg);
+            R wP = R(0.5) * (Gn + (G0[q] + k.fd_eps));
+            R wF = R(0.5) * (Xn + ((R(1) - rN0[q]) + k.fd_eps));
+            swcP += wP * (s * psiA[q]);
+            swP += wP;
+            swcF += wF * (s * phiA[q]);
+            swF += wF;
+        }
+    k.fld.rhsP[n] = Gn * psi + R(0.5) * k.Ds * (swcP - swP * psi) + eS;
+    k.fld.rhsF[n] = Xn * phi + R(0.5) * k.Db * (swcF - swF * phi) + eB;
+    k.fld.Sp[n] = Sn;
+    k.fld.Bp[n] = Bn;
+    k.fld.psi[1 - k.pc][n] = psi;
+    k.fld.phi[1 - k.pc][n] = phi;
+}
+
+// One colour half of a red-black SOR sweep of both implicit systems
+// [W - (Dc/2) L_W] chi = rhs with W = G^{n+1} (psi) and X^{n+1} (phi). Rows
+// with a zero diagonal are decoupled and keep their value. The residual of the
+// row before its update feeds a per-sweep maximum; a sweep whose previous
+// maximum is within tolerance returns at once.
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<typename P::R> k, int color, int sweep)
+{
+    using R = typename P::R;
+    using L = Lat<LAT>;
+    constexpr int D = L::D;
+    DevScalars *sc = k.fld.sc;
+    bool conv[2];
+#pragma unroll
+    for (int fi = 0; fi < 2; ++fi)
+        conv[fi] = sweep > 0 && bits_to_double(sc->res[fi][sweep - 1]) <= (double)k.tol * bits_to_double(sc->rmax[fi]);
+    if (conv[0] && conv[1]) return;
+    Node nd = node_id(k);
+    const int x = nd.x, y = nd.y, z = nd.z;
+    const bool act = nd.ok && (((x + y + z) & 1) == color);
+    const long long N = k.N;
+    const long long n = act ? lin(k, x, y, z) : 0;
+    const R *G1 = k.fld.G[1 - k.lev];
+    const R *rN1 = k.fld.mac[1 - k.lev] + 2 * N;
+    double rloc[2] = {0, 0}, bloc[2] = {0, 0};
+#pragma unroll
+    for (int fi = 0; fi < 2; ++fi) {
+        if (conv[fi] || !act) continue;
+        R *chi = fi == 0 ? k.fld.psi[1 - k.pc] : k.fld.phi[1 - k.pc];
+        const R rhs = fi == 0 ? k.fld.rhsP[n] : k.fld.rhsF[n];
+        const R hd = R(0.5) * (fi == 0 ? k.Ds : k.Db);
+        const R Wn = (fi == 0 ? G1[n] : R(1) - rN1[n]) + k.fd_eps;
+        R diag = Wn, off = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int o = -1; o <= 1; o += 2) {
+                int dd[3] = {0, 0, 0};
+                dd[a] = o;
+                R sg;
+                long long q = nb(k, x, y, z, dd[0], dd[1], dd[2], -1, sg);
+                if (q == n) continue;
+                R Wq = (fi == 0 ? G1[q] : R(1) - rN1[q]) + k.fd_eps;
+                R wf = hd * (R(0.5) * (Wn + Wq));
+                diag += wf;
+                off += wf * chi[q];
+            }
+        if (diag > R(0)) {
+            R c0 = chi[n];
+            rloc[fi] = fabs((double)(rhs - (diag * c0 - off)));
+            bloc[fi] = fabs((double)rhs);
+            chi[n] = (R(1) - k.omega) * c0 + k.omega * (rhs + off) / diag;
+        }
+    }
+    // wavefront maxima, one atomic per wavefront (all lanes take part)
+    const bool lane0 = ((threadIdx.x + threadIdx.y * blockDim.x) & 63) == 0;
+#pragma unroll
+    for (int fi = 0; fi < 2; ++fi) {
+        if (conv[fi]) continue;
+        double r = wave_max(rloc[fi]);
+        if (lane0) atomic_max_nonneg(&sc->res[fi][sweep], r);
+        if (sweep == 0) {
+            double b = wave_max(bloc[fi]);
+            if (lane0) atomic_max_nonneg(&sc->rmax[fi], b);
+        }
+    }
+}
+
+// Sweep counts of the last solve; LBFD_ESOR when a system never met its tolerance.
+template <class R> __global__ void k_sor_done(KP<R> k, int nsw)
+{
+    DevScalars *sc = k.fld.sc;
+    for (int fi = 0; fi < 2; ++fi) {
+        int K = nsw;
+        for (int s = 1; s < nsw; ++s)
+            if (bits_to_double(sc->res[fi][s - 1]) <= (double)k.tol * bits_to_double(sc->rmax[fi])) { K = s; break; }
+        sc->sweeps[fi] = K;
+        if (K == nsw && !(bits_to_double(sc->res[fi][nsw - 1]) <= (double)k.tol * bits_to_double(sc->rmax[fi])))
+            if (sc->status == 0) sc->status = LBFD_ESOR;
+    }
+}
+
+// ============================================================== reductions
+
+template <int NV> __device__ __forceinline__ void block_sum_store(double (&v)[NV], double *out)
+{
+    __shared__ double sh[NV][256];
+    const int t = threadIdx.x + threadIdx.y * blockDim.x;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sh[i][t] = v[i];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) sh[i][t] += sh[i][t + w];
+        __syncthreads();
+    }
+    if (t == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) out[i] = sh[i][0];
+}
+
+// Per-block FP64 sums of G psi + X phi (the conserved integrand of eqs 20-21)
+// at `level`, psi/phi from buffer `buf` times `mult`.
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void k_total_part(KP<typename P::R> k, int level, int buf, double mult)
+{
+    using R = typename P::R;
+    Node nd = node_id(k);
+    double v[1] = {0.0};
+    if (nd.ok) {
+        const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
+        double G = (double)(k.fld.G[level][n] + k.fd_eps);
+        double X = (double)((R(1) - k.fld.mac[level][2 * N + n]) + k.fd_eps);
+        double ps = mult * (double)k.fld.psi[buf][n], ph = mult * (double)k.fld.phi[buf][n];
+        v[0] = G * ps + X * ph;
+    }
+    const long long b = blockIdx.x + gridDim.x * ((long long)blockIdx.y + gridDim.y * (long long)blockIdx.z);
+    block_sum_store<1>(v, k.fld.part + b);
+}
+
+// Final sum of the block partials in a fixed order. mode 0: record the
+// rescaling target; mode 1: record the total after a solve and set the factor
+// that restores the target (Sec 2.2), flagging a non-finite total.
+template <class R> __global__ void k_total_final(KP<R> k, long long nblocks, int mode)
+{
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
+    double a = 0.0;
+    for (long long b = t; b < nblocks; b += 256) a += k.fld.part[b];
+    sh[t] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        DevScalars *sc = k.fld.sc;
+        double M = sh[0];
+        if (mode == 0) {
+            sc->M0 = M;
+            sc->Mlast = M;
+            sc->drift_pre = 0.0;
+            sc->scale = 1.0;
+        } else {
+            sc->Mlast = M;
+            sc->drift_pre = sc->M0 != 0.0 ? (M - sc->M0) / sc->M0 : 0.0;
+            sc->scale = (k.rescale && sc->M0 != 0.0 && M != 0.0) ? sc->M0 / M : 1.0;
+            if (!isfinite(M) && sc->status == 0) sc->status = LBFD_ENONFINITE;
+        }
+    }
+}
+
+// Observables, pass 0: sums and extrema; pass 1: central second moments.
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void k_obs_part(KP<typename P::R> k, int pass, double cx, double cy, double cz)
+{
+    using R = typename P::R;
+    using L = Lat<LAT>;
+    Node nd = node_id(k);
+    double v[NRED];
+    for (int i = 0; i < NRED; ++i) v[i] = 0.0;
+    v[17] = INFINITY;
+    v[18] = -INFINITY;
+    if (nd.ok) {
+        const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
+        const double s = k.fld.sc->scale;
+        const auto *mac = k.fld.mac[k.lev];
+        double rR = mac[n], rB = mac[N + n], rN = mac[2 * N + n];
+        double w = 0.5 * (1.0 + rN);
+        double c[3] = {(double)nd.x, (double)nd.y, (double)nd.z};
+        if (pass == 0) {
+            double G = k.fld.G[k.lev][n];
+            double ps = s * (double)k.fld.psi[k.pc][n], ph = s * (double)k.fld.phi[k.pc][n];
+            double Gw = (double)(k.fld.G[k.lev][n] + k.fd_eps);
+            double Xw = (double)((R(1) - mac[2 * N + n]) + k.fd_eps);
+            v[0] = rR;
+            v[1] = rB;
+            v[2] = Gw * ps + Xw * ph;
+            if (rN >= 0.0) {
+                v[3] = 1.0;
+                for (int d = 0; d < L::D; ++d) v[4 + d] = k.fld.u[d * N + n];
+            }
+            v[7] = w;
+            for (int d = 0; d < 3; ++d) v[8 + d] = w * c[d];
+            v[11] = G;
+            v[12] = G * ps;
+            double pr = rR * (double)k.cs2[0] + rB * (double)k.cs2[1];
+            if (rN > 0.99) { v[13] = pr; v[14] = 1.0; }
+            if (rN < -0.99) { v[15] = pr; v[16] = 1.0; }
+            if (fabs(rN) <= 0.5) { v[17] = ps; v[18] = ps; }
+        } else {
+            double d0 = c[0] - cx, d1 = c[1] - cy, d2 = c[2] - cz;
+            v[0] = w * d0 * d0; v[1] = w * d1 * d1; v[2] = w * d2 * d2;
+            v[3] = w * d0 * d1; v[4] = w * d0 * d2; v[5] = w * d1 * d2;
+        }
+    }
+    // block reduction: sums for 0..16, min for 17, max for 18
+    __shared__ double sh[NRED][256];
+    const int t = threadIdx.x + threadIdx.y * blockDim.x;
+    for (int i = 0; i < NRED; ++i) sh[i][t] = v[i];
+    __syncthreads();
+    for (int wdt = 128; wdt > 0; wdt >>= 1) {
+        if (t < wdt) {
+            for (int i = 0; i < 17; ++i) sh[i][t] += sh[i][t + wdt];
+            sh[17][t] = fmin(sh[17][t], sh[17][t + wdt]);
+            sh[18][t] = fmax(sh[18][t], sh[18][t + wdt]);
+        }
+        __syncthreads();
+    }
+    const long long b = blockIdx.x + gridDim.x * ((long long)blockIdx.y + gridDim.y * (long long)blockIdx.z);
+    if (t == 0)
+        for (int i = 0; i < NRED; ++i) k.fld.part[b * NRED + i] = sh[i][0];
+}
+
+__global__ void k_obs_final(const double *part, long long nblocks, double *out)
+{
+    __shared__ double sh[NRED][256];
+    const int t = threadIdx.x;
+    double v[NRED];
+    for (int i = 0; i < NRED; ++i) v[i] = 0.0;
+    v[17] = INFINITY;
+    v[18] = -INFINITY;
+    for (long long b = t; b < nblocks; b += 256) {
+        for (int i = 0; i < 17; ++i) v[i] += part[b * NRED + i];
+        v[17] = fmin(v[17], part[b * NRED + 17]);
+        v[18] = fmax(v[18], part[b * NRED + 18]);
+    }
+    for (int i = 0; i < NRED; ++i) sh[i][t] = v[i];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            for (int i = 0; i < 17; ++i) sh[i][t] += sh[i][t + w];
+            sh[17][t] = fmin(sh[17][t], sh[17][t + w]);
+            sh[18][t] = fmax(sh[18][t], sh[18][t + w]);
+        }
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int i = 0; i < NRED; ++i) out[i] = sh[i][0];
+}
+
+// FP64 export of one field of the current state into a device buffer.
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_export(KP<typename P::R> k, int field, double *out)
+{
+    using R = typename P::R;
+    using S = typename P::S;
+    using L = Lat<LAT>;
+    Node nd = node_id(k);
+    if (!nd.ok) return;
+    const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
+    const R *mac = k.fld.mac[k.lev];
+    const double s = k.fld.sc->scale;
+    switch (field) {
+    case LBFD_FIELD_F: {
+        const S *f = (const S *)k.fld.f[k.fc];
+        for (int j = 0; j < L::Q; ++j) {
+            int pre;
+            long long src = P::DEV ? source_of<LAT, R>(k, nd.x, nd.y, nd.z, j, pre) : 0;
+            out[j * N + n] = (double)load_pop<LAT, P>(k, f, n, j, src, k.fld.desc[1 - k.lev]);
+        }
+        break;
+    }
+    case LBFD_FIELD_RHOR: out[n] = mac[n]; break;
+    case LBFD_FIELD_RHOB: out[n] = mac[N + n]; break;
+    case LBFD_FIELD_RHON: out[n] = mac[2 * N + n]; break;
+    case LBFD_FIELD_U: for (int d = 0; d < L::D; ++d) out[d * N + n] = k.fld.u[d * N + n]; break;
+    case LBFD_FIELD_FORCE: for (int d = 0; d < L::D; ++d) out[d * N + n] = k.fld.F[d * N + n]; break;
+    case LBFD_FIELD_PSI: out[n] = s * (double)k.fld.psi[k.pc][n]; break;
+    case LBFD_FIELD_PHI: out[n] = s * (double)k.fld.phi[k.pc][n]; break;
+    case LBFD_FIELD_G: out[n] = k.fld.G[k.lev][n]; break;
+    case LBFD_FIELD_SPREV: out[n] = k.fld.Sp[n]; break;
+    case LBFD_FIELD_BPREV: out[n] = k.fld.Bp[n]; break;
+    default: break;
+    }
+}
+
+}  // namespace lbfd
+
+// ================================================================== host runtime
+
+using namespace lbfd;
+
+namespace {
+
+enum KernelClass { KC_COLLIDE = 0, KC_MACRO, KC_GEOM, KC_FD, KC_SOR, KC_TOTAL, KC_FORCE, KC_OTHER, KC_COUNT };
+const char *kKernelNames[KC_COUNT] = {"collide", "macro", "geom", "fd", "sor", "total", "force", "other"};
+
+struct ProfRec { int kc; hipEvent_t a, b; };
+
+}  // namespace
+
+struct lbfd_handle {
+    lbfd_params p;
+    int Q, D;
+    long long N;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    int fc, pc;
+    long long step;
+    KP<double> kd;
+    KP<float> kf;
+    dim3 grid, block;
+    long long nblocks;
+    int sweeps_launch;
+    bool prof;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+    double *obs_out;  // device, NRED doubles (inside the workspace)
+};
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+bool is_dev(int prec) { return prec == LBFD_FP16DEV || prec == LBFD_BF16DEV; }
+size_t pop_bytes(int prec) { return prec == LBFD_FP64 ? 8 : prec == LBFD_FP32 ? 4 : 2; }
+size_t real_bytes(int prec) { return prec == LBFD_FP64 ? 8 : 4; }
+
+struct Layout {
+    size_t f[2], mac[2], desc[2], G[2], nrm, u, F, psi[2], phi[2], Sp, Bp, rhsP, rhsF, part, sc, obs, total;
+};
+
+Layout layout(const lbfd_params *p)
+{
+    Layout L{};
+    const int Q = p->lattice == LBFD_D3Q19 ? 19 : 9, D = p->lattice == LBFD_D3Q19 ? 3 : 2;
+    const long long N = (long long)p->nx * p->ny * p->nz;
+    const size_t sp = pop_bytes(p->precision), sr = real_bytes(p->precision);
+    const int ndesc = 1 + D + (is_dev(p->precision) ? 1 + D : 0);
+    const long long nblocks = (long long)((p->nx + BX - 1) / BX) * ((p->ny + BY - 1) / BY) * p->nz;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
+    for (int b = 0; b < 2; ++b) L.f[b] = take(sp * Q * N);
+    for (int b = 0; b < 2; ++b) L.mac[b] = take(sr * (3 + D) * N);
+    for (int b = 0; b < 2; ++b) L.desc[b] = take(sr * ndesc * N);
+    for (int b = 0; b < 2; ++b) L.G[b] = take(sr * N);
+    L.nrm = take(sr * D * N);
+    L.u = take(sr * D * N);
+    L.F = take(sr * D * N);
+    for (int b = 0; b < 2; ++b) L.psi[b] = take(sr * N);
+    for (int b = 0; b < 2; ++b) L.phi[b] = take(sr * N);
+    L.Sp = take(sr * N);
+    L.Bp = take(sr * N);
+    L.rhsP = take(sr * N);
+    L.rhsF = take(sr * N);
+    L.part = take(sizeof(double) * NRED * (size_t)nblocks);
+    L.sc = take(sizeof(DevScalars));
+    L.obs = take(sizeof(double) * NRED);
+    L.total = o;
+    return L;
+}
+
+int check_params(const lbfd_params *p)
+{
+    if (!p) return LBFD_EINVAL;
+    if (p->lattice != LBFD_D2Q9 && p->lattice != LBFD_D3Q19) return LBFD_EINVAL;
+    if (p->precision < LBFD_FP64 || p->precision > LBFD_BF16DEV) return LBFD_EINVAL;
+    if (p->nx < 4 || p->ny < 4) return LBFD_EINVAL;
+    if (p->lattice == LBFD_D2Q9 ? p->nz != 1 : p->nz < 4) return LBFD_EINVAL;
+    if ((long long)p->nx * p->ny * p->nz > (1LL << 31)) return LBFD_EINVAL;
+    if (!(p->rhoR0 > 0 && p->rhoB0 > 0 && p->muR0 > 0 && p->muB0 > 0)) return LBFD_EINVAL;
+    if (!(p->alphaR > 0 && p->alphaR < 1)) return LBFD_EINVAL;
+    double alphaB = 1.0 - (p->rhoR0 / p->rhoB0) * (1.0 - p->alphaR);
+    if (!(alphaB > 0 && alphaB < 1)) return LBFD_EINVAL;
+    if (!(p->psi_inf > 0) || p->E0 < 0 || p->sigma0 < 0) return LBFD_EINVAL;
+    if (p->sor_max_sweeps < 1 || p->sor_max_sweeps > MAX_SWEEPS) return LBFD_EINVAL;
+    if (!(p->sor_omega > 0 && p->sor_omega < 2)) return LBFD_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (p->bc[a] != LBFD_PERIODIC && p->bc[a] != LBFD_WALL) return LBFD_EINVAL;
+    if (p->lattice == LBFD_D2Q9 && p->bc[2] != LBFD_PERIODIC) return LBFD_EINVAL;
+    return LBFD_OK;
+}
+
+// Rest equilibrium per unit density of a colour with sound-speed parameter al,
+// M^-1 m^eq(1, al, 0) written out from eq 37 / eq 40 at u = 0.
+template <class Tab> void rest_weights(double al, double cs2, double *out)
+{
+    double m[QMAX] = {0};
+    if (Tab::D == 2) {
+        m[0] = 1.0; m[1] = -3.6 * al - 0.4; m[2] = 5.4 * al - 1.4;
+    } else {
+        m[0] = 1.0; m[4] = 3.0 * cs2;
+        for (int r = 16; r < 19; ++r) m[r] = (1.0 - al) / 6.0;
+    }
+    for (int i = 0; i < Tab::Q; ++i) {
+        double a = 0.0;
+        for (int r = 0; r < Tab::Q; ++r) a += Tab::MINV[i][r] * m[r];
+        out[i] = a;
+    }
+}
+
+template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const Layout &Lo)
+{
+    const bool three = p->lattice == LBFD_D3Q19;
+    k.nx = p->nx; k.ny = p->ny; k.nz = p->nz;
+    k.N = (long long)p->nx * p->ny * p->nz;
+    for (int a = 0; a < 3; ++a) k.bc[a] = p->bc[a];
+    for (int w = 0; w < 6; ++w)
+        for (int a = 0; a < 3; ++a) k.wall_u[w][a] = (R)p->wall_u[w][a];
+    k.rhoR0 = (R)p->rhoR0; k.rhoB0 = (R)p->rhoB0; k.muR0 = (R)p->muR0; k.muB0 = (R)p->muB0;
+    // Appendix A: (cs^k)^2 = 0.6 (1 - alpha^k) (2-D), 0.5 (1 - alpha^k) (3-D); eq 42 for alpha^B
+    double al[2] = {p->alphaR, 1.0 - (p->rhoR0 / p->rhoB0) * (1.0 - p->alphaR)};
+    double cs2[2], qc[2];
+    for (int c = 0; c < 2; ++c) {
+        cs2[c] = (three ? 0.5 : 0.6) * (1.0 - al[c]);
+        qc[c] = three ? (p->q_literal ? 1.0 - cs2[c] : 1.0 - 3.0 * cs2[c]) : 1.8 * al[c] - 0.8;
+        k.alpha[c] = (R)al[c];
+        k.cs2[c] = (R)cs2[c];
+        k.qcoef[c] = (R)qc[c];
+    }
+    k.qon = (qc[0] != 0.0 || qc[1] != 0.0) ? 1 : 0;
+    double rest[2][QMAX] = {{0}};
+    for (int c = 0; c < 2; ++c) {
+        if (three) rest_weights<D3Q19Tables>(al[c], cs2[c], rest[c]);
+        else rest_weights<D2Q9Tables>(al[c], cs2[c], rest[c]);
+        for (int i = 0; i < QMAX; ++i) k.rest[c][i] = (R)rest[c][i];
+    }
+    k.beta = (R)p->beta;
+    k.recolour_literal = p->recolour_literal;
+    k.sigma0 = (R)p->sigma0; k.E0 = (R)p->E0; k.psi_inf = (R)p->psi_inf;
+    k.sigma_min = (R)(p->sigma_min_ratio * p->sigma0);
+    k.cmc = (R)(p->E0 > 0 ? p->psi_inf * (1.0 - std::exp(-(1.0 - p->sigma_min_ratio) / p->E0)) : p->psi_inf);
+    k.Ds = (R)p->Ds; k.Db = (R)p->Db; k.ra = (R)p->ra; k.rd = (R)p->rd;
+    k.source_mode = p->source_mode;
+    for (int a = 0; a < 3; ++a) k.grav[a] = (R)p->gravity[a];
+    k.omega = (R)p->sor_omega;
+    k.tol = (R)p->sor_tol;
+    k.weno_eps = (R)p->weno_eps;
+    k.eps_n = (R)p->eps_n;
+    k.fd_eps = (R)p->fd_eps;
+    k.upwind_eps = (R)p->upwind_eps;
+    k.rescale = p->rescale;
+    k.lev = 0; k.fc = 0; k.pc = 0; k.step = 0;
+    Fields<R> &F = k.fld;
+    for (int b = 0; b < 2; ++b) {
+        F.f[b] = ws + Lo.f[b];
+        F.mac[b] = (R *)(ws + Lo.mac[b]);
+        F.desc[b] = (R *)(ws + Lo.desc[b]);
+        F.G[b] = (R *)(ws + Lo.G[b]);
+        F.psi[b] = (R *)(ws + Lo.psi[b]);
+        F.phi[b] = (R *)(ws + Lo.phi[b]);
+    }
+    F.nrm = (R *)(ws + Lo.nrm);
+    F.u = (R *)(ws + Lo.u);
+    F.F = (R *)(ws + Lo.F);
+    F.Sp = (R *)(ws + Lo.Sp);
+    F.Bp = (R *)(ws + Lo.Bp);
+    F.rhsP = (R *)(ws + Lo.rhsP);
+    F.rhsF = (R *)(ws + Lo.rhsF);
+    F.part = (double *)(ws + Lo.part);
+    F.sc = (DevScalars *)(ws + Lo.sc);
+}
+
+hipEvent_t pool_get(lbfd_handle *h)
+{
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+struct Timer {
+    lbfd_handle *h;
+    int kc;
+    hipEvent_t a = nullptr;
+    Timer(lbfd_handle *h_, int kc_) : h(h_), kc(kc_)
+    {
+        if (h->prof) {
+            a = pool_get(h);
+            hipEventRecord(a, h->stream);
+        }
+    }
+    ~Timer()
+    {
+        if (h->prof) {
+            hipEvent_t b = pool_get(h);
+            hipEventRecord(b, h->stream);
+            h->recs.push_back(ProfRec{kc, a, b});
+        }
+    }
+};
+
+#define LAUNCH(KC, KERNEL, GRID, BLOCK, ...)                                          \
+    do {                                                                              \
+        Timer _t(h, KC);                                                              \
+        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, h->stream, __VA_ARGS__);           \
+    } while (0)
+
+template <int LAT, class P> struct Impl {
+    using R = typename P::R;
+
+    static KP<R> &kp(lbfd_handle *h)
+    {
+        if constexpr (sizeof(R) == 8) return h->kd;
+        else return h->kf;
+    }
+
+    static void sync_levels(lbfd_handle *h)
+    {
+        KP<R> &k = kp(h);
+        k.lev = (int)(h->step & 1);
+        k.fc = h->fc;
+        k.pc = h->pc;
+        k.step = h->step;
+    }
+
+    static void totals(lbfd_handle *h, int level, int buf, double mult, int mode)
+    {
+        KP<R> &k = kp(h);
+        LAUNCH(KC_TOTAL, (k_total_part<LAT, P>), h->grid, h->block, k, level, buf, mult);
+        LAUNCH(KC_TOTAL, (k_total_final<R>), dim3(1), dim3(256), k, h->nblocks, mode);
+    }
+
+    static void derived(lbfd_handle *h)
+    {
+        // geometry and forces of the current level, and (at set-up) the target total
+        KP<R> &k = kp(h);
+        sync_levels(h);
+        LAUNCH(KC_GEOM, (k_geom<LAT, P>), h->grid, h->block, k, k.lev);
+        LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
+    }
+
+    static int init(lbfd_handle *h, const InitDev &in)
+    {
+        h->step = 0;
+        h->fc = 0;
+        h->pc = 0;
+        sync_levels(h);
+        KP<R> &k = kp(h);
+        LAUNCH(KC_OTHER, (k_init_a<LAT, P>), h->grid, h->block, k, in);
+        LAUNCH(KC_OTHER, (k_init_b<LAT, P>), h->grid, h->block, k, in);
+        LAUNCH(KC_GEOM, (k_geom<LAT, P>), h->grid, h->block, k, k.lev);
+        clear_scalars(h);
+        totals(h, k.lev, k.pc, 1.0, 0);
+        LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
+        return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    static void clear_scalars(lbfd_handle *h)
+    {
+        DevScalars z;
+        std::memset(&z, 0, sizeof(z));
+        z.scale = 1.0;
+        hipMemcpyAsync(kp(h).fld.sc, &z, sizeof(z), hipMemcpyHostToDevice, h->stream);
+        hipStreamSynchronize(h->stream);
+    }
+
+    static int set_state(lbfd_handle *h, const double *f, const double *rR, const double *rB, const double *psi,
+                         const double *phi, const double *Sp, const double *Bp, long long step, double M0)
+    {
+        const long long N = h->N;
+        const size_t nd = (size_t)(h->Q + 6) * N;
+        double *d = nullptr;
+        if (hipMalloc(&d, nd * sizeof(double)) != hipSuccess) return LBFD_EHIP;
+        double *df = d, *drR = d + h->Q * N, *drB = drR + N, *dps = drB + N, *dph = dps + N, *dS = dph + N,
+               *dB = dS + N;
+        hipMemcpyAsync(df, f, sizeof(double) * h->Q * N, hipMemcpyHostToDevice, h->stream);
+        hipMemcpyAsync(drR, rR, sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
+        hipMemcpyAsync(drB, rB, sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
+        hipMemcpyAsync(dps, psi, sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
+        hipMemcpyAsync(dph, phi, sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
+        if (Sp) hipMemcpyAsync(dS, Sp, sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
+        if (Bp) hipMemcpyAsync(dB, Bp, sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
+        h->step = step;
+        h->fc = 0;
+        h->pc = 0;
+        clear_scalars(h);
+        sync_levels(h);
+        KP<R> &k = kp(h);
+        LAUNCH(KC_OTHER, (k_import_a<LAT, P>), h->grid, h->block, k, df, drR, drB, dps, dph, Sp ? dS : nullptr,
+               Bp ? dB : nullptr);
+        LAUNCH(KC_OTHER, (k_import_b<LAT, P>), h->grid, h->block, k, df);
+        derived(h);
+        DevScalars z;
+        std::memset(&z, 0, sizeof(z));
+        z.scale = 1.0;
+        z.M0 = M0;
+        z.Mlast = M0;
+        hipMemcpyAsync(k.fld.sc, &z, sizeof(z), hipMemcpyHostToDevice, h->stream);
+        hipError_t e = hipStreamSynchronize(h->stream);
+        hipFree(d);
+        return e == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    static int step(lbfd_handle *h, long long nsteps)
+    {
+        KP<R> &k = kp(h);
+        for (long long t = 0; t < nsteps; ++t) {
+            sync_levels(h);
+            LAUNCH(KC_COLLIDE, (k_collide<LAT, P>), h->grid, h->block, k);
+            LAUNCH(KC_MACRO, (k_macro<LAT, P>), h->grid, h->block, k);
+            LAUNCH(KC_GEOM, (k_geom<LAT, P>), h->grid, h->block, k, 1 - k.lev);
+            if (h->p.fd_enable) {
+                LAUNCH(KC_FD, (k_fd<LAT, P>), h->grid, h->block, k);
+                for (int s = 0; s < h->sweeps_launch; ++s) {
+                    LAUNCH(KC_SOR, (k_sor<LAT, P>), h->grid, h->block, k, 0, s);
+                    LAUNCH(KC_SOR, (k_sor<LAT, P>), h->grid, h->block, k, 1, s);
+                }
+                LAUNCH(KC_OTHER, (k_sor_done<R>), dim3(1), dim3(1), k, h->sweeps_launch);
+                totals(h, 1 - k.lev, 1 - k.pc, 1.0, 1);
+                h->pc = 1 - h->pc;
+            }
+            h->fc = 1 - h->fc;
+            h->step += 1;
+            sync_levels(h);
+            LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
+        }
+        return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    static int observables(lbfd_handle *h, lbfd_obs *o)
+    {
+        KP<R> &k = kp(h);
+        sync_levels(h);
+        double r0[NRED], r1[NRED];
+        LAUNCH(KC_OTHER, (k_obs_part<LAT, P>), h->grid, h->block, k, 0, 0.0, 0.0, 0.0);
+        LAUNCH(KC_OTHER, k_obs_final, dim3(1), dim3(256), k.fld.part, h->nblocks, h->obs_out);
+        hipMemcpyAsync(r0, h->obs_out, sizeof(r0), hipMemcpyDeviceToHost, h->stream);
+        DevScalars sc;
+        hipMemcpyAsync(&sc, k.fld.sc, sizeof(sc), hipMemcpyDeviceToHost, h->stream);
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return LBFD_EHIP;
+        std::memset(o, 0, sizeof(*o));
+        o->step = h->step;
+        o->mass_R = r0[0];
+        o->mass_B = r0[1];
+        o->total_surf = r0[2];
+        o->nsum = r0[3];
+        for (int d = 0; d < 3; ++d) o->velocity[d] = r0[3] > 0 ? r0[4 + d] / r0[3] : 0.0;
+        o->wsum = r0[7];
+        for (int d = 0; d < 3; ++d) o->centroid[d] = r0[7] > 0 ? r0[8 + d] / r0[7] : 0.0;
+        o->psi_av = r0[11] > 0 ? r0[12] / r0[11] : 0.0;
+        o->p_in = r0[14] > 0 ? r0[13] / r0[14] : 0.0;
+        o->p_out = r0[16] > 0 ? r0[15] / r0[16] : 0.0;
+        o->psi_min = r0[17];
+        o->psi_max = r0[18];
+        LAUNCH(KC_OTHER, (k_obs_part<LAT, P>), h->grid, h->block, k, 1, o->centroid[0], o->centroid[1],
+               o->centroid[2]);
+        LAUNCH(KC_OTHER, k_obs_final, dim3(1), dim3(256), k.fld.part, h->nblocks, h->obs_out);
+        hipMemcpyAsync(r1, h->obs_out, sizeof(r1), hipMemcpyDeviceToHost, h->stream);
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return LBFD_EHIP;
+        for (int i = 0; i < 6; ++i) o->second[i] = r0[7] > 0 ? r1[i] / r0[7] : 0.0;
+        o->drift_pre = sc.drift_pre;
+        o->sor_sweeps[0] = sc.sweeps[0];
+        o->sor_sweeps[1] = sc.sweeps[1];
+        o->status = sc.status;
+        o->deformation = deformation(o->second, h->D);
+        return sc.status;
+    }
+
+    static double deformation(const double *m, int D)
+    {
+        // eigenvalues of the symmetric 2x2 or 3x3 second-moment tensor; axes ~ sqrt
+        double lmax, lmin;
+        if (D == 2) {
+            double tr = m[0] + m[1], df = m[0] - m[1];
+            double r = std::sqrt(0.25 * df * df + m[3] * m[3]);
+            lmax = 0.5 * tr + r;
+            lmin = 0.5 * tr - r;
+        } else {
+            double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5];
+            double q = (a + b + c) / 3.0;
+            double p1 = d * d + e * e + f * f;
+            double p2 = (a - q) * (a - q) + (b - q) * (b - q) + (c - q) * (c - q) + 2.0 * p1;
+            double pp = std::sqrt(p2 / 6.0);
+            if (pp == 0.0) { lmax = lmin = q; }
+            else {
+                double B[6] = {(a - q) / pp, (b - q) / pp, (c - q) / pp, d / pp, e / pp, f / pp};
+                double detB = B[0] * (B[1] * B[2] - B[5] * B[5]) - B[3] * (B[3] * B[2] - B[5] * B[4]) +
+                              B[4] * (B[3] * B[5] - B[1] * B[4]);
+                double rr = detB / 2.0;
+                double phi = rr <= -1 ? M_PI / 3.0 : rr >= 1 ? 0.0 : std::acos(rr) / 3.0;
+                lmax = q + 2.0 * pp * std::cos(phi);
+                lmin = q + 2.0 * pp * std::cos(phi + 2.0 * M_PI / 3.0);
+            }
+        }
+        double L = std::sqrt(std::fmax(lmax, 0.0)), B = std::sqrt(std::fmax(lmin, 0.0));
+        return L + B > 0 ? (L - B) / (L + B) : 0.0;
+    }
+
+    static int read_field(lbfd_handle *h, int field, double *host, size_t count)
+    {
+        int comps = field == LBFD_FIELD_F ? h->Q : (field == LBFD_FIELD_U || field == LBFD_FIELD_FORCE) ? h->D : 1;
+        switch (field) {
+        case LBFD_FIELD_F: case LBFD_FIELD_RHOR: case LBFD_FIELD_RHOB: case LBFD_FIELD_RHON: case LBFD_FIELD_U:
+        case LBFD_FIELD_PSI: case LBFD_FIELD_PHI: case LBFD_FIELD_FORCE: case LBFD_FIELD_G:
+        case LBFD_FIELD_SPREV: case LBFD_FIELD_BPREV: break;
+        default: return LBFD_EINVAL;
+        }
+        if (count != (size_t)comps * (size_t)h->N || !host) return LBFD_EINVAL;
+        double *d = nullptr;
+        if (hipMalloc(&d, count * sizeof(double)) != hipSuccess) return LBFD_EHIP;
+        sync_levels(h);
+        LAUNCH(KC_OTHER, (k_export<LAT, P>), h->grid, h->block, kp(h), field, d);
+        hipMemcpyAsync(host, d, count * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        hipError_t e = hipStreamSynchronize(h->stream);
+        hipFree(d);
+        return e == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+};
+
+struct Dispatch {
+    int (*init)(lbfd_handle *, const InitDev &);
+    int (*set_state)(lbfd_handle *, const double *, const double *, const double *, const double *, const double *,
+                     const double *, const double *, long long, double);
+    int (*step)(lbfd_handle *, long long);
+    int (*observables)(lbfd_handle *, lbfd_obs *);
+    int (*read_field)(lbfd_handle *, int, double *, size_t);
+};
+
+template <int LAT, class P> Dispatch make_dispatch()
+{
+    return Dispatch{&Impl<LAT, P>::init, &Impl<LAT, P>::set_state, &Impl<LAT, P>::step, &Impl<LAT, P>::observables,
+                    &Impl<LAT, P>::read_field};
+}
+
+Dispatch dispatch_for(int lat, int prec)
+{
+    if (lat == LBFD_D2Q9) {
+        switch (prec) {
+        case LBFD_FP64: return make_dispatch<0, PrecF64>();
+        case LBFD_FP32: return make_dispatch<0, PrecF32>();
+        case LBFD_FP16DEV: return make_dispatch<0, PrecF16>();
+        default: return make_dispatch<0, PrecB16>();
+        }
+    }
+    switch (prec) {
+    case LBFD_FP64: return make_dispatch<1, PrecF64>();
+    case LBFD_FP32: return make_dispatch<1, PrecF32>();
+    case LBFD_FP16DEV: return make_dispatch<1, PrecF16>();
+    default: return make_dispatch<1, PrecB16>();
+    }
+}
+
+int sticky_status(lbfd_handle *h)
+{
+    DevScalars sc;
+    const DevScalars *d = h->p.precision == LBFD_FP64 ? h->kd.fld.sc : h->kf.fld.sc;
+    if (hipMemcpyAsync(&sc, d, sizeof(sc), hipMemcpyDeviceToHost, h->stream) != hipSuccess) return LBFD_EHIP;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return LBFD_EHIP;
+    return sc.status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbfd_workspace_bytes(const lbfd_params *p, size_t *bytes)
+{
+    int st = check_params(p);
+    if (st != LBFD_OK) return st;
+    if (!bytes) return LBFD_EINVAL;
+    *bytes = layout(p).total;
+    return LBFD_OK;
+}
+
+int lbfd_create(const lbfd_params *p, void *d_workspace, size_t bytes, void *stream, lbfd_handle **out)
+{
+    if (!out) return LBFD_EINVAL;
+    *out = nullptr;
+    int st = check_params(p);
+    if (st != LBFD_OK) return st;
+    Layout Lo = layout(p);
+    if (!d_workspace || bytes < Lo.total) return LBFD_EWORKSPACE;
+    if (((uintptr_t)d_workspace & 255) != 0) return LBFD_EWORKSPACE;
+    lbfd_handle *h = new (std::nothrow) lbfd_handle();
+    if (!h) return LBFD_ENOMEM;
+    h->p = *p;
+    h->Q = p->lattice == LBFD_D3Q19 ? 19 : 9;
+    h->D = p->lattice == LBFD_D3Q19 ? 3 : 2;
+    h->N = (long long)p->nx * p->ny * p->nz;
+    h->stream = (hipStream_t)stream;
+    h->ws = (char *)d_workspace;
+    h->ws_bytes = bytes;
+    h->fc = h->pc = 0;
+    h->step = 0;
+    h->block = dim3(BX, BY, 1);
+    h->grid = dim3((p->nx + BX - 1) / BX, (p->ny + BY - 1) / BY, p->nz);
+    h->nblocks = (long long)h->grid.x * h->grid.y * h->grid.z;
+    h->sweeps_launch = p->sor_max_sweeps;
+    h->prof = false;
+    fill_kp(h->kd, p, h->ws, Lo);
+    fill_kp(h->kf, p, h->ws, Lo);
+    h->obs_out = (double *)(h->ws + Lo.obs);
+    *out = h;
+    return LBFD_OK;
+}
+
+int lbfd_init_fields(lbfd_handle *h, const lbfd_init *in)
+{
+    if (!h || !in || in->n < 0 || in->n > 16 || !(in->width > 0)) return LBFD_EINVAL;
+    InitDev d;
+    d.n = in->n;
+    for (int i = 0; i < 16; ++i) { d.cx[i] = in->cx[i]; d.cy[i] = in->cy[i]; d.cz[i] = in->cz[i]; d.r[i] = in->r[i]; }
+    d.width = in->width;
+    d.psi0 = in->psi0;
+    d.phi0_out = in->phi0_out;
+    d.phi0_in = in->phi0_in;
+    d.shear_rate = in->shear_rate;
+    if (!(in->psi0 >= 0 && in->psi0 < h->p.psi_inf)) return LBFD_EINVAL;
+    return dispatch_for(h->p.lattice, h->p.precision).init(h, d);
+}
+
+int lbfd_set_state(lbfd_handle *h, const double *f, const double *rhoR, const double *rhoB, const double *psi,
+                   const double *phi, const double *Sprev, const double *Bprev, int64_t step, double M0)
+{
+    if (!h || !f || !rhoR || !rhoB || !psi || !phi || step < 0) return LBFD_EINVAL;
+    return dispatch_for(h->p.lattice, h->p.precision).set_state(h, f, rhoR, rhoB, psi, phi, Sprev, Bprev, step, M0);
+}
+
+int lbfd_step(lbfd_handle *h, int64_t n)
+{
+    if (!h || n < 0) return LBFD_EINVAL;
+    return dispatch_for(h->p.lattice, h->p.precision).step(h, n);
+}
+
+int lbfd_observables(lbfd_handle *h, lbfd_obs *out)
+{
+    if (!h || !out) return LBFD_EINVAL;
+    return dispatch_for(h->p.lattice, h->p.precision).observables(h, out);
+}
+
+int lbfd_read_field(lbfd_handle *h, int32_t field, double *host, size_t count)
+{
+    if (!h) return LBFD_EINVAL;
+    int st = dispatch_for(h->p.lattice, h->p.precision).read_field(h, field, host, count);
+    if (st != LBFD_OK) return st;
+    return sticky_status(h);
+}
+
+int lbfd_profile(lbfd_handle *h, int32_t enable)
+{
+    if (!h) return LBFD_EINVAL;
+    hipStreamSynchronize(h->stream);
+    for (auto &r : h->recs) { h->pool.push_back(r.a); h->pool.push_back(r.b); }
+    h->recs.clear();
+    h->prof = enable != 0;
+    return LBFD_OK;
+}
+
+int lbfd_profile_read(lbfd_handle *h, int32_t max_kernels, const char **names, double *ms, int64_t *launches,
+                      int32_t *n_kernels)
+{
+    if (!h || !n_kernels) return LBFD_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return LBFD_EHIP;
+    double acc[KC_COUNT] = {0};
+    int64_t cnt[KC_COUNT] = {0};
+    for (auto &r : h->recs) {
+        float t = 0.f;
+        hipEventElapsedTime(&t, r.a, r.b);
+        acc[r.kc] += t;
+        cnt[r.kc] += 1;
+    }
+    int nk = KC_COUNT < max_kernels ? KC_COUNT : max_kernels;
+    for (int i = 0; i < nk; ++i) {
+        if (names) names[i] = kKernelNames[i];
+        if (ms) ms[i] = acc[i];
+        if (launches) launches[i] = cnt[i];
+    }
+    *n_kernels = nk;
+    return LBFD_OK;
+}
+
+void lbfd_destroy(lbfd_handle *h)
+{
+    if (!h) return;
+    hipStreamSynchronize(h->stream);
+    for (auto &r : h->recs) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+    for (auto e : h->pool) hipEventDestroy(e);
+    delete h;
+}
+
+const char *lbfd_strerror(int s)
+{
+    switch (s) {
+    case LBFD_OK: return "ok";
+    case LBFD_EINVAL: return "invalid argument or parameter";
+    case LBFD_ENOMEM: return "host allocation failed";
+    case LBFD_EHIP: return "HIP runtime error";
+    case LBFD_ENONFINITE: return "non-finite total surfactant";
+    case LBFD_ESOR: return "SOR did not reach its tolerance within sor_max_sweeps";
+    case LBFD_EWORKSPACE: return "device workspace missing, misaligned or too small";
+    case LBFD_EUNSUPPORTED: return "unsupported combination";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,236 @@
+"""Python binding of the C ABI in include/lbfd.h (argument marshalling only).
+
+Every step of the solver runs in the HIP kernels of liblbfd.so. PyTorch only
+provides the device workspace (one uint8 tensor) and the stream. If the
+library is missing this module raises; there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+LBFD_OK, LBFD_EINVAL, LBFD_ENOMEM, LBFD_EHIP, LBFD_ENONFINITE, LBFD_ESOR, LBFD_EWORKSPACE = 0, -1, -2, -3, -4, -5, -6
+PRECISION = {"fp64": 0, "fp32": 1, "fp16dev": 2, "bf16dev": 3}
+FIELDS = dict(f=0, rhoR=3, rhoB=4, rhoN=5, u=6, psi=7, phi=8, force=9, G=10, Sprev=11, Bprev=12)
+EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_init_fields", "lbfd_set_state", "lbfd_step",
+            "lbfd_observables", "lbfd_read_field", "lbfd_profile", "lbfd_profile_read", "lbfd_destroy",
+            "lbfd_strerror"]
+
+
+class LbfdError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int32), ("precision", C.c_int32),
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("bc", C.c_int32 * 3), ("wall_u", (C.c_double * 3) * 6),
+        ("rhoR0", C.c_double), ("rhoB0", C.c_double), ("muR0", C.c_double), ("muB0", C.c_double),
+        ("alphaR", C.c_double), ("beta", C.c_double), ("sigma0", C.c_double), ("E0", C.c_double),
+        ("psi_inf", C.c_double), ("sigma_min_ratio", C.c_double),
+        ("Ds", C.c_double), ("Db", C.c_double), ("ra", C.c_double), ("rd", C.c_double),
+        ("source_mode", C.c_int32), ("gravity", C.c_double * 3),
+        ("sor_omega", C.c_double), ("sor_tol", C.c_double), ("sor_max_sweeps", C.c_int32),
+        ("weno_eps", C.c_double), ("rescale", C.c_int32), ("fd_enable", C.c_int32),
+        ("q_literal", C.c_int32), ("eps_n", C.c_double), ("recolour_literal", C.c_int32),
+        ("fd_eps", C.c_double), ("upwind_eps", C.c_double),
+    ]
+
+
+class Init(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("cx", C.c_double * 16), ("cy", C.c_double * 16), ("cz", C.c_double * 16),
+        ("r", C.c_double * 16), ("width", C.c_double), ("psi0", C.c_double),
+        ("phi0_out", C.c_double), ("phi0_in", C.c_double), ("shear_rate", C.c_double),
+    ]
+
+
+class Obs(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("mass_R", C.c_double), ("mass_B", C.c_double),
+        ("total_surf", C.c_double), ("drift_pre", C.c_double),
+        ("velocity", C.c_double * 3), ("centroid", C.c_double * 3), ("second", C.c_double * 6),
+        ("wsum", C.c_double), ("nsum", C.c_double), ("psi_av", C.c_double),
+        ("psi_min", C.c_double), ("psi_max", C.c_double), ("p_in", C.c_double), ("p_out", C.c_double),
+        ("deformation", C.c_double), ("sor_sweeps", C.c_int32 * 2), ("status", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def load(build_if_missing: bool = False):
+    """Load liblbfd.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = _build.LIB
+    if not os.path.exists(path):
+        if not build_if_missing:
+            raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+        _build.build()
+    L = C.CDLL(path)
+    P, vp, dp = C.POINTER, C.c_void_p, C.POINTER(C.c_double)
+    L.lbfd_workspace_bytes.argtypes = [P(Params), P(C.c_size_t)]
+    L.lbfd_create.argtypes = [P(Params), vp, C.c_size_t, vp, P(vp)]
+    L.lbfd_init_fields.argtypes = [vp, P(Init)]
+    L.lbfd_set_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, C.c_int64, C.c_double]
+    L.lbfd_step.argtypes = [vp, C.c_int64]
+    L.lbfd_observables.argtypes = [vp, P(Obs)]
+    L.lbfd_read_field.argtypes = [vp, C.c_int32, dp, C.c_size_t]
+    L.lbfd_profile.argtypes = [vp, C.c_int32]
+    L.lbfd_profile_read.argtypes = [vp, C.c_int32, P(C.c_char_p), dp, P(C.c_int64), P(C.c_int32)]
+    L.lbfd_destroy.argtypes = [vp]
+    L.lbfd_destroy.restype = None
+    L.lbfd_strerror.argtypes = [C.c_int]
+    L.lbfd_strerror.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    try:
+        return load().lbfd_strerror(int(status)).decode()
+    except ImportError:
+        return "library not loaded"
+
+
+def _check(status, what):
+    if status != LBFD_OK:
+        raise LbfdError(status, what)
+
+
+def params_struct(p: dict) -> Params:
+    s = Params()
+    s.lattice = int(p["lattice"])
+    s.precision = PRECISION[p.get("precision", "fp64")]
+    s.nx, s.ny, s.nz = int(p["nx"]), int(p["ny"]), int(p["nz"])
+    for a in range(3):
+        s.bc[a] = int(p["bc"][a])
+        s.gravity[a] = float(p["gravity"][a])
+    for w in range(6):
+        for a in range(3):
+            s.wall_u[w][a] = float(p["wall_u"][w][a])
+    for k in ("rhoR0", "rhoB0", "muR0", "muB0", "alphaR", "beta", "sigma0", "E0", "psi_inf",
+              "sigma_min_ratio", "Ds", "Db", "ra", "rd", "sor_omega", "sor_tol", "weno_eps", "eps_n", "fd_eps", "upwind_eps"):
+        setattr(s, k, float(p[k]))
+    for k in ("source_mode", "sor_max_sweeps", "rescale", "fd_enable", "q_literal", "recolour_literal"):
+        setattr(s, k, int(p[k]))
+    return s
+
+
+def init_struct(q: dict) -> Init:
+    s = Init()
+    s.n = len(q["drops"])
+    for d, (cx, cy, cz, r) in enumerate(q["drops"]):
+        s.cx[d], s.cy[d], s.cz[d], s.r[d] = cx, cy, cz, r
+    s.width, s.psi0, s.phi0_out, s.phi0_in = q["width"], q["psi0"], q["phi0_out"], q["phi0_in"]
+    s.shear_rate = q.get("shear_rate", 0.0)
+    return s
+
+
+def workspace_bytes(params: dict) -> int:
+    n = C.c_size_t()
+    _check(load().lbfd_workspace_bytes(C.byref(params_struct(params)), C.byref(n)), "lbfd_workspace_bytes")
+    return int(n.value)
+
+
+class Solver:
+    """One solver instance on one device: ``Solver(params).init_fields(init).step(n)``.
+
+    Fields come back as FP64 numpy arrays of shape (nz, ny, nx), with a leading
+    Q or D axis for populations and vectors."""
+
+    def __init__(self, params: dict, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.p = dict(params)
+        self._ps = params_struct(self.p)
+        L = load()
+        nbytes = workspace_bytes(self.p)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        ptr = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L.lbfd_create(C.byref(self._ps), C.c_void_p(ptr), C.c_size_t(nbytes),
+                             C.c_void_p(self.stream.cuda_stream), C.byref(h)), "lbfd_create")
+        self.h = h
+        self.Q = 19 if self.p["lattice"] == 1 else 9
+        self.D = 3 if self.p["lattice"] == 1 else 2
+        self.shape = (int(self.p["nz"]), int(self.p["ny"]), int(self.p["nx"]))
+        self.N = int(np.prod(self.shape))
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.lbfd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def init_fields(self, init: dict):
+        _check(load().lbfd_init_fields(self.h, C.byref(init_struct(init))), "lbfd_init_fields")
+        return self
+
+    def set_state(self, f, rhoR, rhoB, psi, phi, Sprev=None, Bprev=None, step=0, M0=0.0):
+        arrs = []
+
+        def ptr(a, count):
+            if a is None:
+                return None
+            b = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+            assert b.size == count
+            arrs.append(b)
+            return b.ctypes.data_as(C.POINTER(C.c_double))
+        N = self.N
+        _check(load().lbfd_set_state(self.h, ptr(f, self.Q * N), ptr(rhoR, N), ptr(rhoB, N), ptr(psi, N),
+                                     ptr(phi, N), ptr(Sprev, N), ptr(Bprev, N), int(step), float(M0)),
+               "lbfd_set_state")
+        return self
+
+    def step(self, n: int = 1):
+        _check(load().lbfd_step(self.h, int(n)), "lbfd_step")
+        return self
+
+    def observables(self, check=True) -> dict:
+        o = Obs()
+        st = load().lbfd_observables(self.h, C.byref(o))
+        if check:
+            _check(st, "lbfd_observables")
+        return dict(step=o.step, mass_R=o.mass_R, mass_B=o.mass_B, total_surf=o.total_surf,
+                    drift_pre=o.drift_pre, velocity=list(o.velocity), centroid=list(o.centroid),
+                    second=list(o.second), wsum=o.wsum, nsum=o.nsum, psi_av=o.psi_av, psi_min=o.psi_min,
+                    psi_max=o.psi_max, p_in=o.p_in, p_out=o.p_out, deformation=o.deformation,
+                    sor_sweeps=list(o.sor_sweeps), status=o.status)
+
+    def field(self, name: str) -> np.ndarray:
+        c = self.Q if name == "f" else self.D if name in ("u", "force") else 1
+        out = np.zeros(c * self.N, dtype=np.float64)
+        _check(load().lbfd_read_field(self.h, FIELDS[name], out.ctypes.data_as(C.POINTER(C.c_double)),
+                                      out.size), f"lbfd_read_field({name})")
+        return out.reshape((c,) + self.shape) if c > 1 else out.reshape(self.shape)
+
+    def profile(self, enable: bool):
+        _check(load().lbfd_profile(self.h, 1 if enable else 0), "lbfd_profile")
+
+    def profile_read(self) -> dict:
+        names = (C.c_char_p * 16)()
+        ms = np.zeros(16)
+        cnt = np.zeros(16, dtype=np.int64)
+        nk = C.c_int32()
+        _check(load().lbfd_profile_read(self.h, 16, names, ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                        cnt.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(nk)), "lbfd_profile_read")
+        return {names[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(nk.value)}

@@ -73,7 +73,7 @@ def meq(rho, u, alpha, cs2, D):
                      rho * (base + 2 * (uy * uy + uz * uz)) / 6])
 
 
-def weno_div(Psi, u, D, eps):
+def weno_div(Psi, u, D, eps, upwind_eps=0.0):
     out = np.zeros_like(Psi[0])
     for a in range(D):
         d = np.zeros(3, dtype=int)
@@ -90,7 +90,8 @@ def weno_div(Psi, u, D, eps):
         Dm = 0.5 * (dp[-1] + dp[0]) - 0.5 * wm * (dp[-2] - 2 * dp[-1] + dp[0])
         Dp = 0.5 * (dp[-1] + dp[0]) - 0.5 * wp * (dp[1] - 2 * dp[0] + dp[-1])
         ua = u[a]
-        out = out + np.where(ua > 0, Dm, np.where(ua < 0, Dp, 0.5 * (Dm + Dp)))
+        ue = upwind_eps
+        out = out + np.where(ua > ue, Dm, np.where(ua < -ue, Dp, 0.5 * (Dm + Dp)))
     return out
 
 
@@ -196,10 +197,12 @@ def step(p, st):
         return out
     rR1, rB1 = fR1.sum(0), fB1.sum(0)
     rN1 = (rR1 / p["rhoR0"] - rB1 / p["rhoB0"]) / (rR1 / p["rhoR0"] + rB1 / p["rhoB0"])
-    G1 = np.sqrt((grad(rN1, e, w, D) ** 2).sum(0))
-    X0, X1 = 1 - rN, 1 - rN1
-    divPsi = weno_div(psi * G * u, u, D, p["weno_eps"])
-    divPhi = weno_div(phi * X0 * u, u, D, p["weno_eps"])
+    eps = p.get("fd_eps", 0.0)
+    G1 = np.sqrt((grad(rN1, e, w, D) ** 2).sum(0)) + eps
+    X0, X1 = 1 - rN + eps, 1 - rN1 + eps
+    G = G + eps
+    divPsi = weno_div(psi * G * u, u, D, p["weno_eps"], p.get("upwind_eps", 0.0))
+    divPhi = weno_div(phi * X0 * u, u, D, p["weno_eps"], p.get("upwind_eps", 0.0))
     if p["source_mode"] == 1:
         jj = p["ra"] * pinf * phi
     else:

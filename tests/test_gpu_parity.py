@@ -1,0 +1,195 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 mode must match the oracle within 1e-12 after one step and 1e-10 after
+many (relative max-norm per field); mixed modes are checked against the FP64
+oracle at the tolerances stated per test. Inputs are the seeded synthetic
+workloads of ``workloads`` at sizes the oracle finishes in seconds, spanning
+several 64 x 4 thread tiles with ragged edges, plus the full-size 3-D column.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.parity import rel, say, state_errors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbfd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2311_15242_amd import lbfd as L
+
+    L.load()
+    return L
+
+
+def run_pair(L, p, q, steps):
+    s = L.Solver(p).init_fields(q)
+    o = oracle.Oracle(dict(p, precision="fp64")).init(q)
+    if steps:
+        s.step(steps)
+        o.step(steps)
+    return s, o
+
+
+CASES_2D = {
+    # ragged tiles: 70 x 37 is not a multiple of the 64 x 4 block
+    "droplet70x37": lambda prec: W.droplet_adsorption(n=70, radius=11.0, precision=prec, ny=37),
+    "shear96x64": lambda prec: W.shear_droplet(nx=96, ny=64, radius=14.0, precision=prec, Ca=0.3),
+    "bubble2d48x80": lambda prec: W.bubble_rise(nx=48, ny=80, nz=1, radius=8.0, lattice=W.D2Q9, precision=prec),
+}
+CASES_3D = {
+    "bubble3d24x20x32": lambda prec: W.bubble_rise(nx=24, ny=20, nz=32, radius=6.0, precision=prec),
+    "droplet3d_periodic20": lambda prec: W.make(
+        dict(lattice=W.D3Q19, nx=20, ny=20, nz=20, sigma0=0.01, E0=0.5, Ds=0.05, Db=0.05, precision=prec),
+        dict(drops=[(9.5, 9.5, 9.5, 6.0)], width=3.0, psi0=0.1, phi0_out=0.05, phi0_in=0.0)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES_2D) + list(CASES_3D))
+def test_init_matches_oracle_fp64(lbfd, case):
+    say(f"[init fp64] {case}")
+    p, q = (CASES_2D.get(case) or CASES_3D[case])("fp64")
+    s, o = run_pair(lbfd, p, q, 0)
+    errs = state_errors(s, o, names=("f", "rhoR", "rhoB", "rhoN", "u", "Gpsi", "Xphi"))
+    say(errs)
+    assert max(errs.values()) < 1e-13, errs
+    assert rel(s.field("force"), o.field("force")) < 1e-12
+
+
+@pytest.mark.parametrize("case", list(CASES_2D) + list(CASES_3D))
+def test_one_step_fp64(lbfd, case):
+    say(f"[1 step fp64] {case}")
+    p, q = (CASES_2D.get(case) or CASES_3D[case])("fp64")
+    s, o = run_pair(lbfd, p, q, 1)
+    errs = state_errors(s, o)
+    say(errs)
+    assert max(errs.values()) < 1e-12, errs
+
+
+@pytest.mark.parametrize("case,steps", [("droplet70x37", 200), ("shear96x64", 200), ("bubble2d48x80", 200),
+                                        ("bubble3d24x20x32", 40), ("droplet3d_periodic20", 40)])
+def test_many_steps_fp64(lbfd, case, steps):
+    say(f"[{steps} steps fp64] {case}")
+    p, q = (CASES_2D.get(case) or CASES_3D[case])("fp64")
+    s, o = run_pair(lbfd, p, q, steps)
+    errs = state_errors(s, o)
+    say(errs)
+    assert max(errs.values()) < 1e-10, errs
+    ob, oo = s.observables(), o.observables()
+    assert ob["status"] == 0
+    for k in ("mass_R", "mass_B", "total_surf", "psi_av", "p_in", "p_out"):
+        assert abs(ob[k] - oo[k]) <= 1e-10 * max(abs(oo[k]), 1e-300), k
+    for a in range(3):
+        assert abs(ob["centroid"][a] - oo["centroid"][a]) <= 1e-10 * max(abs(oo["centroid"][a]), 1.0)
+    assert abs(ob["total_surf"] - o.initial_total) <= 1e-12 * o.initial_total
+
+
+def random_state_pair(L, lat, n, seed, prec="fp64"):
+    p = W.finalize(dict(lattice=lat, nx=n, ny=n + 3, nz=n if lat == W.D3Q19 else 1, Ds=0.1, Db=0.3,
+                        rhoR0=0.5, muR0=0.05, gravity=[1e-5, -2e-5, 1e-5], precision=prec))
+    o = oracle.Oracle(dict(p, precision="fp64"))
+    L_ = o.lattice()
+    fR, fB = W.random_state((L_["Q"], o.N), L_["w"], seed, amp=0.02)
+    psi = W.random_scalar(o.N, seed + 1, 0.0, 0.95)
+    phi = W.random_scalar(o.N, seed + 2, 0.0, 0.1)
+    Sp = W.random_scalar(o.N, seed + 3, -1e-3, 1e-3)
+    Bp = W.random_scalar(o.N, seed + 4, -1e-3, 1e-3)
+    for name, v in (("fR", fR), ("fB", fB), ("psi", psi), ("phi", phi), ("Sprev", Sp), ("Bprev", Bp)):
+        o.set_field(name, v)
+    o.set_clock(1, 1.0)
+    s = L.Solver(p).set_state(fR + fB, fR.sum(0), fB.sum(0), psi, phi, Sp, Bp, step=1, M0=1.0)
+    return s, o
+
+
+@pytest.mark.parametrize("lat,n", [(W.D2Q9, 13), (W.D3Q19, 7)])
+def test_random_state_steps_fp64(lbfd, lat, n):
+    """Random two-phase states (all branches of eq 9, unequal densities and
+    sound speeds, body force) stepped on both sides."""
+    say(f"[random state fp64] lattice {lat} n {n}")
+    s, o = random_state_pair(lbfd, lat, n, 11)
+    errs0 = state_errors(s, o)
+    assert max(errs0.values()) < 1e-14, errs0
+    for k in range(3):
+        s.step(1)
+        o.step(1)
+        errs = state_errors(s, o)
+        say(k, errs)
+        assert max(errs.values()) < 1e-11, errs
+
+
+def test_adsorption_droplet_full_size_fp64(lbfd):
+    """The stationary-droplet adsorption workload at its full size (D2Q9,
+    128 x 128, R = 25), 500 steps, FP64: parity and conservation."""
+    say("[droplet128 fp64 500 steps]")
+    p, q = W.droplet_adsorption()
+    s, o = run_pair(lbfd, p, q, 500)
+    errs = state_errors(s, o)
+    say(errs)
+    assert max(errs.values()) < 1e-10, errs
+    ob = s.observables()
+    assert abs(ob["total_surf"] - o.initial_total) <= 1e-12 * o.initial_total
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-3), ("fp16dev", 1e-3), ("bf16dev", 1e-3)])
+def test_mixed_precision_vs_fp64_oracle(lbfd, prec, tol):
+    """Reduced-precision modes against the FP64 oracle (same parameters) on the
+    shear workload (reduced grid, 200 steps): velocity and the interface
+    concentration within 1e-3 relative. The psi error is set by the FP32
+    solver tolerance (1e-6 relative residual), the velocity error by the
+    population storage."""
+    say(f"[mixed {prec}] shear96x64 200 steps")
+    p, q = CASES_2D["shear96x64"](prec)
+    s = lbfd.Solver(p).init_fields(q)
+    M0 = s.observables()["total_surf"]
+    o = oracle.Oracle(dict(p, precision="fp64")).init(q)
+    s.step(200)
+    o.step(200)
+    errs = state_errors(s, o, names=("u", "rhoN", "Gpsi", "Xphi"))
+    say(errs)
+    assert errs["u"] < tol and errs["Gpsi"] < tol, errs
+    ob = s.observables()
+    assert ob["status"] == 0
+    # each side conserves its own total (FP64 sums of FP32 weights on the GPU)
+    assert abs(ob["total_surf"] - M0) <= 1e-12 * M0
+    assert abs(M0 - o.initial_total) <= 1e-6 * o.initial_total
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-3), ("bf16dev", 1e-3)])
+def test_bubble_column_full_size_sampled(lbfd, prec, tol):
+    """The 3-D column at its full size (D3Q19, 128 x 128 x 384, density ratio
+    10) in the launch configuration the benchmark times: two steps against the
+    oracle."""
+    say(f"[bubble128x128x384 {prec} 2 steps]")
+    p, q = W.bubble_rise(precision=prec)
+    s, o = run_pair(lbfd, p, q, 2)
+    errs = state_errors(s, o, names=("u", "rhoN", "Gpsi", "Xphi"))
+    say(errs)
+    assert max(errs.values()) < tol, errs
+
+
+def test_sor_failure_is_reported(lbfd):
+    """One sweep with a zero tolerance cannot converge: the step reports ESOR."""
+    say("[ESOR]")
+    p, q = W.droplet_adsorption(n=32, radius=8.0, sor_max_sweeps=1, sor_tol=0.0)
+    s = lbfd.Solver(p).init_fields(q).step(1)
+    ob = s.observables(check=False)
+    assert ob["status"] == lbfd.LBFD_ESOR
+
+
+def test_nonfinite_is_reported(lbfd):
+    say("[ENONFINITE]")
+    p, q = W.droplet_adsorption(n=32, radius=8.0)
+    s = lbfd.Solver(p).init_fields(q)
+    psi = s.field("psi")
+    psi[0, 16, 16] = np.nan
+    f, rR, rB = s.field("f"), s.field("rhoR"), s.field("rhoB")
+    s.set_state(f, rR, rB, psi, s.field("phi"), step=0, M0=1.0)
+    s.step(1)
+    ob = s.observables(check=False)
+    assert ob["status"] == lbfd.LBFD_ENONFINITE

@@ -31,8 +31,10 @@ BASE_PARAMS = dict(
     sigma0=0.01, E0=0.5, psi_inf=1.0, sigma_min_ratio=0.1,
     Ds=0.02, Db=0.02, ra=0.1, rd=0.05, source_mode=0,
     gravity=[0.0, 0.0, 0.0],
-    sor_omega=1.2, sor_tol=1e-13, sor_max_sweeps=500,
+    sor_omega=1.2, sor_tol=1e-13, sor_max_sweeps=60,
     weno_eps=1e-6, rescale=1, fd_enable=1, q_literal=0, eps_n=1e-12, recolour_literal=0,
+    fd_eps=1e-10,                # background support of the FD weights (FP32 modes: 1e-6)
+    upwind_eps=1e-12,            # |u| band in which the WENO upwind weights are 1/2 each
     precision="fp64",
 )
 
@@ -49,6 +51,8 @@ def finalize(params: dict) -> dict:
         p["nz"] = 1
     if p["precision"] != "fp64" and "sor_tol" not in params:
         p["sor_tol"] = 1e-6
+    if p["precision"] != "fp64" and "fd_eps" not in params:
+        p["fd_eps"] = 1e-6
     return p
 
 
@@ -68,8 +72,8 @@ def droplet_adsorption(n=128, radius=25.0, precision="fp64", literal_c=False, **
                   muR0=1.0 / 6.0, muB0=1.0 / 6.0, sigma0=0.01, E0=0.5, psi_inf=1.0,
                   Ds=0.02, Db=0.02, ra=0.1, rd=0.05, precision=precision)
     params.update(over)
-    c = (n - 1) / 2.0
-    init = dict(drops=[(c, c, 0.0, radius)], width=3.0, psi0=0.0,
+    ny = params.get("ny", n)
+    init = dict(drops=[((n - 1) / 2.0, (ny - 1) / 2.0, 0.0, radius)], width=3.0, psi0=0.0,
                 phi0_out=0.1 if literal_c else 0.05, phi0_in=0.0)
     return make(params, init)
 
