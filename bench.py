@@ -1,0 +1,303 @@
+#!/usr/bin/env python3
+"""Throughput of the hybrid LB colour-gradient / FD surfactant step on one MI355X.
+
+One step = the method's whole per-step path (forces, MRT collision with
+recolouring and propagation, macroscopic fields, WENO3 / Crank-Nicolson
+right-hand sides, red-black SOR to tolerance, rescaling) on one batch of
+synthetic input resident in HBM. The headline workload is the buoyant bubble
+column: D3Q19, 128 x 128 x 384, density ratio 10, BF16-deviation population
+storage with FP32 arithmetic. MLUPS = nodes x steps / wall time of the timed
+region (HIP events on the solver's stream, bracketed by synchronisations).
+
+The printed JSON line also carries:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                mean launch time (HIP events around each launch, same timed
+                region) against 8 TB/s; traffic = measured HBM bytes per launch
+                from the rocprofv3 counter summary under profiles/ (null if the
+                kernel sources changed since it was taken)
+  cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
+  secondary     the 2-D workloads (shear 512 x 256 in FP64 / FP32 / FP16-dev,
+                droplet 128 x 128 FP64), same timing method
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic_bubble128x128x384_bf16dev.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2311_15242_amd", "csrc", f)
+                  for f in ("lbfd.hip", "lbfd_kernels.h", "lbfd_lattice_tables.h")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kernel: str, p: dict) -> float:
+    """Bytes per node one launch of `kernel` must move between HBM and the
+    chip: each input and output array counted once (no halo re-reads, no
+    redundant traffic). Q populations of bf bytes, scalars of br bytes."""
+    three = p["lattice"] == 1
+    Q, D = (19, 3) if three else (9, 2)
+    prec = p["precision"]
+    bf = {"fp64": 8, "fp32": 4, "fp16dev": 2, "bf16dev": 2}[prec]
+    br = 8 if prec == "fp64" else 4
+    dev = prec in ("fp16dev", "bf16dev")
+    desc_w = 1 + D + ((1 + D) if dev else 0)      # descriptor written by the collision
+    desc_r_dev = (2 + D) if dev else 0            # a, rho, u* of the sources, to decode deviations
+    table = {
+        # f in + f out, rhoR rhoB rhoN, u, F, descriptor out (+ descriptor in)
+        "collide": 2 * Q * bf + (3 + 2 * D + desc_w + desc_r_dev) * br,
+        # f in, descriptor (a, c, +rho, u*) in, rhoR rhoB rhoN j out
+        "macro": Q * bf + (desc_w + 3 + D) * br,
+        # rhoN in, |grad rhoN| and normal out
+        "geom": (2 + D) * br,
+        # psi phi G rhoN u Sprev Bprev in; rhs x2, S B, psi phi guesses out
+        "fd": (6 + D + 6) * br,
+        # one colour half of a sweep: psi phi G rhoN rhs x2 in, half of psi phi out
+        "sor": 0.5 * 8 * br,
+        # G rhoN psi phi in
+        "total": 4 * br,
+        # rhoN, normal, psi, rhoR rhoB j in; u, F out
+        "force": (4 + 2 * D + 2 * D) * br,
+    }
+    return float(table.get(kernel, 0.0))
+
+
+def build_solver(p, q):
+    from paper_2311_15242_amd import lbfd
+
+    return lbfd.Solver(p).init_fields(q)
+
+
+def timed_run(p, q, steps, warmup, profile, only=None):
+    import torch
+
+    s = build_solver(p, q)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    ob = s.observables()
+    if ob["status"] != 0:
+        raise RuntimeError(f"solver status {ob['status']} after warm-up")
+    if profile:
+        s.profile(True, only=only)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    s.step(steps)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    prof = s.profile_read() if profile else {}
+    ob = s.observables()
+    if ob["status"] != 0:
+        raise RuntimeError(f"solver status {ob['status']} in the timed region")
+    s.close()
+    return ms, prof, ob
+
+
+def cpu_baseline(p, q, budget_s):
+    """The oracle as it stands, timed on the host cores: whole steps of the same
+    workload (FP64), as many as fit the time budget (at least one)."""
+    import oracle
+
+    o = oracle.Oracle(dict(p, precision="fp64")).init(q)
+    N = o.N
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter()
+    steps = 1
+    per = t1 - t0
+    extra = int(max(0, budget_s - per) // per)
+    if extra:
+        o.step(extra)
+        steps += extra
+    t2 = time.perf_counter()
+    mlups = N * steps / (t2 - t0) / 1e6
+    return dict(value=round(mlups, 4), unit="MLUPS", cores=oracle.threads(), kind="oracle",
+                sample=f"{steps} FP64 step(s) of the same {p['nx']}x{p['ny']}x{p['nz']} workload "
+                       f"after initialisation, {t2 - t0:.1f} s")
+
+
+def traffic_for(kernel, launches_per_step):
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    if t.get("kernel") != kernel or t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def _pmc_rows(path):
+    import csv
+
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            yield r["Kernel_Name"], float(r["Counter_Value"]), int(r["Grid_Size"])
+
+
+def pmc_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
+    """Per-kernel mean FETCH_SIZE and WRITE_SIZE (KiB per dispatch, summed over
+    the counter instances of a dispatch) and the HBM bytes they imply once each
+    is scaled by what the same counter reads for a plain copy of known size."""
+    import collections
+
+    def per_kernel(path):
+        acc = collections.defaultdict(list)
+        for name, v, _ in _pmc_rows(path):
+            acc[name].append(v)
+        return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+    def copy_kib(path):
+        vals = [v for name, v, _ in _pmc_rows(path) if "copy" in name.lower() or "elementwise" in name.lower()]
+        return max(vals) if vals else None
+
+    f, w = per_kernel(fetch_csv), per_kernel(write_csv)
+    cf, cw = copy_kib(copy_fetch_csv), copy_kib(copy_write_csv)
+    nbytes = 1024 * (1 << 20)
+    sf = nbytes / (cf * 1024) if cf else float("nan")
+    sw = nbytes / (cw * 1024) if cw else float("nan")
+    lines = [f"copy calibration: {nbytes} B copied; FETCH_SIZE read {cf} KiB, WRITE_SIZE read {cw} KiB "
+             f"-> scale fetch x{sf:.4f}, write x{sw:.4f}",
+             f"{'kernel':78s} {'dispatches':>10s} {'FETCH KiB':>12s} {'WRITE KiB':>12s} {'HBM MB/launch':>14s}"]
+    for k in sorted(f, key=lambda k: -(f[k][0] + w.get(k, (0, 0))[0])):
+        fk, n = f[k]
+        wk = w.get(k, (0.0, 0))[0]
+        hbm = (fk * sf + wk * sw) * 1024 / 1e6
+        lines.append(f"{k[:78]:78s} {n:10d} {fk:12.1f} {wk:12.1f} {hbm:14.2f}")
+    return "\n".join(lines)
+
+
+def sweep_budget(p, q, warmup, margin=2):
+    """SOR sweeps to launch per step: the most any warm-up step needed, plus a
+    margin. Every step still checks its own convergence on the device; a step
+    that does not converge within the budget sets LBFD_ESOR and fails the run."""
+    from paper_2311_15242_amd import lbfd
+
+    s = lbfd.Solver(p).init_fields(q)
+    used = 0
+    for _ in range(max(warmup, 1)):
+        s.step(1)
+        ob = s.observables()
+        used = max(used, *ob["sor_sweeps"])
+    s.close()
+    return min(used + margin, p["sor_max_sweeps"])
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="bubble128x128x384")
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--sor-sweeps", default="auto",
+                    help="SOR sweeps launched per step: an integer, or auto (warm-up maximum + 2)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--omega", type=float, default=None, help="SOR relaxation factor (default: the workload's)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (scales rocprofv3 byte counters)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE counter CSVs per kernel (scaled by the "
+                         "copy calibration run) and exit")
+    args = ap.parse_args()
+    if args.pmc_summary:
+        print(pmc_summary(*args.pmc_summary))
+        return
+    if args.copy_calibration:
+        import torch
+
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_calibration_bytes=n * 4, repeats=5)))
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              f"(the solver runs on a single MI355X; multi-GPU sharding is design only).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    p, q = W.config(args.workload, args.precision)
+    if args.omega:
+        p["sor_omega"] = args.omega
+    p["sor_max_sweeps"] = sweep_budget(p, q, args.warmup) if args.sor_sweeps == "auto" else int(args.sor_sweeps)
+    N = p["nx"] * p["ny"] * p["nz"]
+
+    # 1) plain timed region: the headline value
+    ms_plain, _, ob = timed_run(p, q, args.steps, args.warmup, profile=False)
+    value = N * args.steps / (ms_plain / 1e3) / 1e6
+    # 2) every kernel class timed (breakdown; the events add some overhead)
+    ms_prof, prof, _ = timed_run(p, q, args.steps, args.warmup, profile=True)
+    # 3) the dominant single-pass kernel timed alone, for the roofline
+    kname = max((k for k in prof if k not in ("sor", "total", "other")), key=lambda k: prof[k][0])
+    ms_k, prof_k, _ = timed_run(p, q, args.steps, args.warmup, profile=True, only=[kname])
+    kms, klaunch = prof_k[kname]
+    per_launch_ms = kms / max(klaunch, 1)
+    abytes = algorithmic_bytes(kname, p) * N
+    achieved = abytes / (per_launch_ms / 1e3) / 1e9
+    launches_per_step = klaunch / args.steps
+    roof = dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_for(kname, launches_per_step),
+                algorithmic_bytes_per_launch=abytes, mean_launch_us=round(per_launch_ms * 1e3, 2),
+                share_of_step=round(kms / ms_k, 3), timed_region_ms_per_step=round(ms_k / args.steps, 4))
+    breakdown = {k: dict(ms_per_step=round(v[0] / args.steps, 4), launches_per_step=round(v[1] / args.steps, 2),
+                         gbs=round(algorithmic_bytes(k, p) * N * v[1] / (v[0] / 1e3) / 1e9, 1) if v[0] > 0 else 0.0)
+                 for k, v in prof.items() if v[1] > 0}
+
+    out = dict(metric="MLUPS (LBM+FD step)", value=round(value, 2), unit="MLUPS", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(ms_plain / args.steps, 4), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32" if p["precision"] != "fp64" else "f64",
+               data="synthetic",
+               config=dict(workload=args.workload, lattice="D3Q19" if p["lattice"] == 1 else "D2Q9",
+                           grid=[p["nx"], p["ny"], p["nz"]], storage=p["precision"],
+                           sor_sweeps_launched=p["sor_max_sweeps"], sor_sweeps_used=ob["sor_sweeps"],
+                           parallelism="single GPU"),
+               roofline=roof, kernels=breakdown,
+               ms_per_step_profiled=round(ms_prof / args.steps, 4))
+
+    if not args.no_secondary:
+        sec = {}
+        for name, prec in (("shear512x256", "fp64"), ("shear512x256", "fp32"), ("shear512x256", "fp16dev"),
+                           ("droplet128", "fp64")):
+            pp, qq = W.config(name, prec)
+            pp["sor_max_sweeps"] = sweep_budget(pp, qq, 20) if args.sor_sweeps == "auto" else int(args.sor_sweeps)
+            nn = pp["nx"] * pp["ny"] * pp["nz"]
+            ms2, _, ob2 = timed_run(pp, qq, 200, 20, profile=False)
+            sec[f"{name}_{prec}"] = dict(mlups=round(nn * 200 / (ms2 / 1e3) / 1e6, 2),
+                                         ms_per_step=round(ms2 / 200, 4), sor_sweeps_used=ob2["sor_sweeps"],
+                                         sor_sweeps_launched=pp["sor_max_sweeps"])
+        out["secondary"] = sec
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, q, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -179,8 +179,11 @@ int lbfd_observables(lbfd_handle *h, lbfd_obs *out);
  * must equal components * nodes. Synchronises the stream. */
 int lbfd_read_field(lbfd_handle *h, int32_t field, double *host, size_t count);
 
-/* Per-kernel timing with HIP events on the handle's stream: enable (1) or
- * disable (0); enabling clears the accumulators. */
+/* Per-kernel timing with HIP events on the handle's stream: enable (non-zero)
+ * or disable (0); enabling clears the accumulators. enable = 1 times every
+ * kernel class; enable = 1 | (mask << 1) times only the classes whose bits
+ * are set in mask (class k = the k-th name reported by lbfd_profile_read),
+ * which keeps the event overhead off the other launches. */
 int lbfd_profile(lbfd_handle *h, int32_t enable);
 
 /* Accumulated milliseconds and launch counts per kernel class since the last

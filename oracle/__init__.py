@@ -90,6 +90,8 @@ def lib():
         L.orc_nodes.restype = C.c_int64
         L.orc_nodes.argtypes = [C.c_void_p]
         L.orc_lattice_q.argtypes = [C.c_void_p]
+        L.orc_threads.restype = C.c_int
+        L.orc_threads.argtypes = []
         L.orc_initial_total.restype = C.c_double
         L.orc_initial_total.argtypes = [C.c_void_p]
         L.orc_get_field.argtypes = [C.c_void_p, C.c_int, dp]
@@ -112,6 +114,11 @@ def lib():
 def _ptr(a):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's node loops use."""
+    return int(lib().orc_threads())
 
 
 def params_struct(p: dict) -> _Params:

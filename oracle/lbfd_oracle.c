@@ -24,6 +24,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define QMAX 19
 
@@ -877,6 +878,18 @@ int orc_step(orc_state *s, int64_t nsteps)
 }
 
 int64_t orc_nodes(const orc_state *s) { return s ? s->N : 0; }
+
+/* Threads the OpenMP loops use (for reporting the CPU baseline). */
+int orc_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
+}
 int orc_lattice_q(const orc_state *s) { return s ? s->Q : 0; }
 double orc_initial_total(const orc_state *s) { return s ? s->M0 : 0.0; }
 

@@ -132,13 +132,14 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_init_b(KP<t
     const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
     R rN0, fR[QMAX], fB[QMAX], u0[3];
     init_node<LAT, R>(k, in, nd.x, nd.y, nd.z, rN0, fR, fB, u0);
+    const Nbhd nb = make_nbhd(k, nd.x, nd.y, nd.z);
     S *f = (S *)k.fld.f[k.fc];
     const R *ds = k.fld.desc[1 - k.lev];
     for (int j = 0; j < L::Q; ++j) {
         R v = fR[j] + fB[j];
         if constexpr (P::DEV) {
-            int pre;
-            long long src = source_of<LAT, R>(k, nd.x, nd.y, nd.z, j, pre);
+            bool bo;
+            long long src = source_of<LAT>(nb, n, j, bo);
             R us[3] = {0, 0, 0};
             for (int d = 0; d < L::D; ++d) us[d] = ds[(2 + L::D + d) * N + src];
             v -= reference<LAT, R>(k, j, ds[(1 + L::D) * N + src], ds[src], us);
@@ -194,11 +195,12 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_import_b(KP
     const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
     S *fo = (S *)k.fld.f[k.fc];
     const R *ds = k.fld.desc[1 - k.lev];
+    const Nbhd nb = make_nbhd(k, nd.x, nd.y, nd.z);
     for (int j = 0; j < L::Q; ++j) {
         R v = (R)f[j * N + n];
         if constexpr (P::DEV) {
-            int pre;
-            long long src = source_of<LAT, R>(k, nd.x, nd.y, nd.z, j, pre);
+            bool bo;
+            long long src = source_of<LAT>(nb, n, j, bo);
             R us[3] = {0, 0, 0};
             for (int d = 0; d < L::D; ++d) us[d] = ds[(2 + L::D + d) * N + src];
             v -= reference<LAT, R>(k, j, ds[(1 + L::D) * N + src], ds[src], us);
@@ -221,10 +223,11 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_geom(KP<typ
     if (!nd.ok) return;
     const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
     const R *rN = k.fld.mac[level] + 2 * N;
+    const Nbhd nb = make_nbhd(k, nd.x, nd.y, nd.z);
     R g[3], G2 = 0;
 #pragma unroll
     for (int a = 0; a < L::D; ++a) {
-        g[a] = lat_deriv<LAT, R>(k, rN, R(1), nd.x, nd.y, nd.z, a, -1);
+        g[a] = lat_deriv<LAT, R>(nb, rN, n, R(1), a, -1);
         G2 += g[a] * g[a];
     }
     k.fld.G[level][n] = sqrt(G2);
@@ -250,13 +253,14 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_force(KP<ty
     const R *mac = k.fld.mac[k.lev];
     const R s = (R)k.fld.sc->scale;
     const R *psiA = k.fld.psi[k.pc];
+    const Nbhd nb = make_nbhd(k, x, y, z);
     R g[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, nv[3] = {0, 0, 0}, kappa = 0, G2 = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        g[a] = lat_deriv<LAT, R>(k, mac + 2 * N, R(1), x, y, z, a, -1);
+        g[a] = lat_deriv<LAT, R>(nb, mac + 2 * N, n, R(1), a, -1);
         G2 += g[a] * g[a];
-        kappa -= lat_deriv<LAT, R>(k, k.fld.nrm + a * N, R(1), x, y, z, a, a);
-        gp[a] = lat_deriv<LAT, R>(k, psiA, s, x, y, z, a, -1);
+        kappa -= lat_deriv<LAT, R>(nb, k.fld.nrm + a * N, n, R(1), a, a);
+        gp[a] = lat_deriv<LAT, R>(nb, psiA, n, s, a, -1);
         nv[a] = k.fld.nrm[a * N + n];
     }
     const R G = sqrt(G2);
@@ -307,15 +311,22 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
     const R *dprev = k.fld.desc[1 - k.lev];
     R *dnew = k.fld.desc[k.lev];
 
-    R f[Q];
+    const Nbhd nb = make_nbhd(k, x, y, z);
+    // m = M f, accumulated while the (decoded) populations stream in
+    R m[Q];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) m[r] = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
         long long src = 0;
         if constexpr (P::DEV) {
-            int pre;
-            src = source_of<LAT, R>(k, x, y, z, j, pre);
+            bool bo;
+            src = source_of<LAT>(nb, n, j, bo);
         }
-        f[j] = load_pop<LAT, P>(k, fin, n, j, src, dprev);
+        const R fj = load_pop<LAT, P>(k, fin, n, j, src, dprev);
+#pragma unroll
+        for (int r = 0; r < Q; ++r)
+            if (L::M[r][j] != 0) m[r] += R(L::M[r][j]) * fj;
     }
     const R rR = mac[n], rB = mac[N + n], rN = mac[2 * N + n];
     const R rho = rR + rB;
@@ -324,7 +335,7 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
     for (int d = 0; d < D; ++d) {
         u[d] = k.fld.u[d * N + n];
         F[d] = k.fld.F[d * N + n];
-        g[d] = lat_deriv<LAT, R>(k, mac + 2 * N, R(1), x, y, z, d, -1);
+        g[d] = lat_deriv<LAT, R>(nb, mac + 2 * N, n, R(1), d, -1);
         G2 += g[d] * g[d];
     }
     // relaxation rate of the viscous moments (eq 43 and the mu-s_v relation)
@@ -332,16 +343,6 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
     const R pk = rR * k.cs2[0] + rB * k.cs2[1];
     const R sv = R(1) / ((R(1) / inv_mu) / pk + R(0.5));
 
-    // m = M f
-    R m[Q];
-#pragma unroll
-    for (int r = 0; r < Q; ++r) {
-        R a = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-            if (L::M[r][i] != 0) a += R(L::M[r][i]) * f[i];
-        m[r] = a;
-    }
     // equilibria summed over colours (eq 37 / eq 40)
     R meq[Q], C[Q];
 #pragma unroll
@@ -380,13 +381,14 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 if (L::OPP[i] < i || L::E[i][a] == 0) continue;
-                R s1, s2;
-                long long p = nb(k, x, y, z, L::E[i][0], L::E[i][1], L::E[i][2], a, s1);
-                long long q = nb(k, x, y, z, -L::E[i][0], -L::E[i][1], -L::E[i][2], a, s2);
-                R up = s1 * uvec[a * N + p], uq = s2 * uvec[a * N + q];
+                const int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2], ea = L::E[i][a];
+                const long long p = n + nb_delta(nb, ex, ey, ez), q = n + nb_delta(nb, -ex, -ey, -ez);
+                R up = uvec[a * N + p], uq = uvec[a * N + q];
+                if (nb_wall_axis(nb, a, ea)) up = -up;
+                if (nb_wall_axis(nb, a, -ea)) uq = -uq;
                 R we = R(L::W[i] * L::E[i][a]);
-                acc0 += we * (mac[p] * up - mac[q] * uq);
-                acc1 += we * (mac[N + p] * up - mac[N + q] * uq);
+                if (k.qcoef[0] != R(0)) acc0 += we * (mac[p] * up - mac[q] * uq);
+                if (k.qcoef[1] != R(0)) acc1 += we * (mac[N + p] * up - mac[N + q] * uq);
             }
             Qa[0][a] = k.qcoef[0] * R(3) * acc0;
             Qa[1][a] = k.qcoef[1] * R(3) * acc1;
@@ -403,31 +405,31 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
             }
         }
     }
-    // forcing term in velocity space (eq 4 integrand), projected with M
-    R Fi[Q];
+    // forcing term (eq 4): the velocity-space integrand projected with M
+    R Fm[Q];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) Fm[r] = 0;
     const R uF = ux * F[0] + uy * F[1] + uz * F[2];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         R eF = 0, eu = 0;
 #pragma unroll
         for (int d = 0; d < D; ++d) { eF += R(L::E[i][d]) * F[d]; eu += R(L::E[i][d]) * u[d]; }
-        Fi[i] = R(L::W[i]) * (R(3) * (eF - uF) + R(9) * eu * eF);
+        const R Fi = R(L::W[i]) * (R(3) * (eF - uF) + R(9) * eu * eF);
+#pragma unroll
+        for (int r = 0; r < Q; ++r)
+            if (L::M[r][i] != 0) Fm[r] += R(L::M[r][i]) * Fi;
     }
-    // dm = -S (m - meq) + (I - S/2)(C + F_m); f_dag = f + M^-1 dm (eqs 1-3)
-    R dm[Q];
+    // post-collision moments m* = m - S (m - meq) + (I - S/2)(C + F_m)  (eqs 1-3)
 #pragma unroll
     for (int r = 0; r < Q; ++r) {
-        R Fm = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-            if (L::M[r][i] != 0) Fm += R(L::M[r][i]) * Fi[i];
         R sr;
         if constexpr (D == 2) {
             sr = r == 1 ? R(1.25) : r == 2 ? R(1.14) : (r == 4 || r == 6) ? R(1.6) : (r >= 7) ? sv : R(0);
         } else {
             sr = (r >= 5 && r <= 9) ? sv : R(1);
         }
-        dm[r] = -sr * (m[r] - meq[r]) + (R(1) - R(0.5) * sr) * (C[r] + Fm);
+        m[r] = m[r] - sr * (m[r] - meq[r]) + (R(1) - R(0.5) * sr) * (C[r] + Fm[r]);
     }
     // recolouring descriptor (eqs 11-12): colour share and c = beta rho^R rho^B / rho g/|g|
     const R a = rR / rho;
@@ -448,16 +450,16 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
     // propagation with periodic wrap or half-way bounce-back
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        R v = f[i];
+        // f_dag_i = (M^-1 m*)_i
+        R v = 0;
 #pragma unroll
         for (int r = 0; r < Q; ++r)
-            if (L::MINV[i][r] != 0.0) v += R(L::MINV[i][r]) * dm[r];
-        int c[3] = {x + L::E[i][0], y + L::E[i][1], z + L::E[i][2]};
-        const int lim[3] = {k.nx, k.ny, k.nz};
+            if (L::MINV[i][r] != 0.0) v += R(L::MINV[i][r]) * m[r];
+        const int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
         int wall = -1;
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax)
-            if (wall < 0 && k.bc[ax] && (c[ax] < 0 || c[ax] >= lim[ax])) wall = 2 * ax + (c[ax] >= lim[ax] ? 1 : 0);
+        if (nb_wall_axis(nb, 0, ex)) wall = ex > 0 ? 1 : 0;
+        else if (nb_wall_axis(nb, 1, ey)) wall = ey > 0 ? 3 : 2;
+        else if (nb_wall_axis(nb, 2, ez)) wall = ez > 0 ? 5 : 4;
         long long dest;
         int j;
         if (wall >= 0) {
@@ -467,10 +469,8 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
             j = L::OPP[i];
             dest = n;
         } else {
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) c[ax] = c[ax] < 0 ? c[ax] + lim[ax] : (c[ax] >= lim[ax] ? c[ax] - lim[ax] : c[ax]);
             j = i;
-            dest = lin(k, c[0], c[1], c[2]);
+            dest = n + nb_delta(nb, ex, ey, ez);
         }
         if constexpr (P::DEV) {
             v -= reference<LAT, R>(k, j, rho, a, us);
@@ -498,11 +498,13 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
     const long long N = k.N, n = lin(k, x, y, z);
     const S *fin = (const S *)k.fld.f[1 - k.fc];
     const R *ds = k.fld.desc[k.lev];
+    const Nbhd nb = make_nbhd(k, x, y, z);
     R rR = 0, rB = 0, j[3] = {0, 0, 0};
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        int pre;
-        long long src = source_of<LAT, R>(k, x, y, z, q, pre);
+        bool bo;
+        const long long src = source_of<LAT>(nb, n, q, bo);
+        const int pre = bo ? L::OPP[q] : q;
         R fq = load_pop<LAT, P>(k, fin, n, q, src, ds);
         R as = ds[src], ec = 0;
 #pragma unroll
@@ -562,16 +564,15 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typen
     const R *G0 = k.fld.G[k.lev];
     const R *rN0 = k.fld.mac[k.lev] + 2 * N;
     const R *uv = k.fld.u;
+    const Nbhd nb = make_nbhd(k, x, y, z);
     R divP = 0, divF = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         R Pp[5], Pf[5];
 #pragma unroll
         for (int o = -2; o <= 2; ++o) {
-            int dd[3] = {0, 0, 0};
-            dd[a] = o;
-            R sg;
-            long long q = nb(k, x, y, z, dd[0], dd[1], dd[2], a, sg);
+            const long long q = o == 0 ? n : n + nb.d[a][slot_of(o)];
+            const R sg = (o != 0 && ((nb.mir >> (a * 4 + slot_of(o))) & 1u)) ? R(-1) : R(1);
             R ua = uv[a * N + q];
             Pp[o + 2] = sg * ((s * psiA[q]) * (G0[q] + k.fd_eps) * ua);
             Pf[o + 2] = sg * ((s * phiA[q]) * ((R(1) - rN0[q]) + k.fd_eps) * ua);
@@ -597,10 +598,7 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typen
     for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int o = -1; o <= 1; o += 2) {
-            int dd[3] = {0, 0, 0};
-            dd[a] = o;
-            R sg;
-            long long q = nb(k, x, y, z, dd[0], dd[1], dd[2], -1, sg);
+            const long long q = n + nb.d[a][slot_of(o)];
             R wP = R(0.5) * (Gn + (G0[q] + k.fd_eps));
             R wF = R(0.5) * (Xn + ((R(1) - rN0[q]) + k.fd_eps));
             swcP += wP * (s * psiA[q]);
@@ -617,10 +615,12 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typen
 }
 
 // One colour half of a red-black SOR sweep of both implicit systems
-// [W - (Dc/2) L_W] chi = rhs with W = G^{n+1} (psi) and X^{n+1} (phi). Rows
-// with a zero diagonal are decoupled and keep their value. The residual of the
-// row before its update feeds a per-sweep maximum; a sweep whose previous
-// maximum is within tolerance returns at once.
+// [W - (Dc/2) L_W] chi = rhs with W = G^{n+1} + eps (psi) and X^{n+1} + eps (phi).
+// Persistent grid-stride kernel over the nodes of one colour (x = 2i + parity),
+// so every lane updates a node and a sweep that is already converged costs one
+// small dispatch. The residual of a row before its update feeds a per-sweep
+// maximum (one atomic per block); a sweep whose previous maximum is within
+// tolerance returns at once.
 template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<typename P::R> k, int color, int sweep)
 {
     using R = typename P::R;
@@ -632,53 +632,83 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
     for (int fi = 0; fi < 2; ++fi)
         conv[fi] = sweep > 0 && bits_to_double(sc->res[fi][sweep - 1]) <= (double)k.tol * bits_to_double(sc->rmax[fi]);
     if (conv[0] && conv[1]) return;
-    Node nd = node_id(k);
-    const int x = nd.x, y = nd.y, z = nd.z;
-    const bool act = nd.ok && (((x + y + z) & 1) == color);
     const long long N = k.N;
-    const long long n = act ? lin(k, x, y, z) : 0;
+    const int nx = k.nx, ny = k.ny, nz = k.nz, hx = (nx + 1) >> 1;
+    const long long H = (long long)hx * ny * nz;
+    const long long sy = nx, sz = (long long)nx * ny;
     const R *G1 = k.fld.G[1 - k.lev];
     const R *rN1 = k.fld.mac[1 - k.lev] + 2 * N;
+    R *psi = k.fld.psi[1 - k.pc], *phi = k.fld.phi[1 - k.pc];
+    const R *rhsP = k.fld.rhsP, *rhsF = k.fld.rhsF;
+    const R eps = k.fd_eps, hdP = R(0.5) * k.Ds, hdF = R(0.5) * k.Db, om = k.omega;
     double rloc[2] = {0, 0}, bloc[2] = {0, 0};
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < H; t += stride) {
+        const long long row = t / hx;
+        const int i = (int)(t - row * hx);
+        const int y = (int)(row % ny), z = (int)(row / ny);
+        const int x = 2 * i + ((y + z + color) & 1);
+        if (x >= nx) continue;
+        const long long n = x + sy * y + sz * z;
+        // face neighbours: periodic wrap, or the node itself across a wall (no flux)
+        long long q[6];
+        q[0] = x > 0 ? n - 1 : (k.bc[0] ? n : n + (nx - 1));
+        q[1] = x < nx - 1 ? n + 1 : (k.bc[0] ? n : n - (nx - 1));
+        q[2] = y > 0 ? n - sy : (k.bc[1] ? n : n + sy * (ny - 1));
+        q[3] = y < ny - 1 ? n + sy : (k.bc[1] ? n : n - sy * (ny - 1));
+        if constexpr (D == 3) {
+            q[4] = z > 0 ? n - sz : (k.bc[2] ? n : n + sz * (nz - 1));
+            q[5] = z < nz - 1 ? n + sz : (k.bc[2] ? n : n - sz * (nz - 1));
+        }
+        if (!conv[0]) {
+            const R Wn = G1[n] + eps;
+            R diag = Wn, off = 0;
 #pragma unroll
-    for (int fi = 0; fi < 2; ++fi) {
-        if (conv[fi] || !act) continue;
-        R *chi = fi == 0 ? k.fld.psi[1 - k.pc] : k.fld.phi[1 - k.pc];
-        const R rhs = fi == 0 ? k.fld.rhsP[n] : k.fld.rhsF[n];
-        const R hd = R(0.5) * (fi == 0 ? k.Ds : k.Db);
-        const R Wn = (fi == 0 ? G1[n] : R(1) - rN1[n]) + k.fd_eps;
-        R diag = Wn, off = 0;
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int o = -1; o <= 1; o += 2) {
-                int dd[3] = {0, 0, 0};
-                dd[a] = o;
-                R sg;
-                long long q = nb(k, x, y, z, dd[0], dd[1], dd[2], -1, sg);
-                if (q == n) continue;
-                R Wq = (fi == 0 ? G1[q] : R(1) - rN1[q]) + k.fd_eps;
-                R wf = hd * (R(0.5) * (Wn + Wq));
+            for (int f = 0; f < 2 * D; ++f) {
+                if (q[f] == n) continue;
+                const R wf = hdP * (R(0.5) * (Wn + (G1[q[f]] + eps)));
                 diag += wf;
-                off += wf * chi[q];
+                off += wf * psi[q[f]];
             }
-        if (diag > R(0)) {
-            R c0 = chi[n];
-            rloc[fi] = fabs((double)(rhs - (diag * c0 - off)));
-            bloc[fi] = fabs((double)rhs);
-            chi[n] = (R(1) - k.omega) * c0 + k.omega * (rhs + off) / diag;
+            const R rhs = rhsP[n], c0 = psi[n];
+            rloc[0] = fmax(rloc[0], fabs((double)(rhs - (diag * c0 - off))));
+            bloc[0] = fmax(bloc[0], fabs((double)rhs));
+            psi[n] = (R(1) - om) * c0 + om * (rhs + off) / diag;
+        }
+        if (!conv[1]) {
+            const R Wn = (R(1) - rN1[n]) + eps;
+            R diag = Wn, off = 0;
+#pragma unroll
+            for (int f = 0; f < 2 * D; ++f) {
+                if (q[f] == n) continue;
+                const R wf = hdF * (R(0.5) * (Wn + ((R(1) - rN1[q[f]]) + eps)));
+                diag += wf;
+                off += wf * phi[q[f]];
+            }
+            const R rhs = rhsF[n], c0 = phi[n];
+            rloc[1] = fmax(rloc[1], fabs((double)(rhs - (diag * c0 - off))));
+            bloc[1] = fmax(bloc[1], fabs((double)rhs));
+            phi[n] = (R(1) - om) * c0 + om * (rhs + off) / diag;
         }
     }
-    // wavefront maxima, one atomic per wavefront (all lanes take part)
-    const bool lane0 = ((threadIdx.x + threadIdx.y * blockDim.x) & 63) == 0;
+    // block maxima, one atomic per block and quantity
+    __shared__ double red[4][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double v[4] = {wave_max(rloc[0]), wave_max(rloc[1]), wave_max(bloc[0]), wave_max(bloc[1])};
+    if (lane == 0)
 #pragma unroll
-    for (int fi = 0; fi < 2; ++fi) {
-        if (conv[fi]) continue;
-        double r = wave_max(rloc[fi]);
-        if (lane0) atomic_max_nonneg(&sc->res[fi][sweep], r);
-        if (sweep == 0) {
-            double b = wave_max(bloc[fi]);
-            if (lane0) atomic_max_nonneg(&sc->rmax[fi], b);
+        for (int j = 0; j < 4; ++j) red[j][wv] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            for (int w = 1; w < nw; ++w) red[j][0] = fmax(red[j][0], red[j][w]);
+#pragma unroll
+        for (int fi = 0; fi < 2; ++fi) {
+            if (conv[fi]) continue;
+            atomic_max_nonneg(&sc->res[fi][sweep], red[fi][0]);
+            if (sweep == 0) atomic_max_nonneg(&sc->rmax[fi], red[2 + fi][0]);
         }
     }
 }
@@ -871,9 +901,10 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_export(KP<t
     switch (field) {
     case LBFD_FIELD_F: {
         const S *f = (const S *)k.fld.f[k.fc];
+        const Nbhd nb = make_nbhd(k, nd.x, nd.y, nd.z);
         for (int j = 0; j < L::Q; ++j) {
-            int pre;
-            long long src = P::DEV ? source_of<LAT, R>(k, nd.x, nd.y, nd.z, j, pre) : 0;
+            bool bo;
+            long long src = P::DEV ? source_of<LAT>(nb, n, j, bo) : 0;
             out[j * N + n] = (double)load_pop<LAT, P>(k, f, n, j, src, k.fld.desc[1 - k.lev]);
         }
         break;
@@ -921,7 +952,9 @@ struct lbfd_handle {
     dim3 grid, block;
     long long nblocks;
     int sweeps_launch;
+    int sor_blocks;     // persistent grid of the SOR sweeps
     bool prof;
+    unsigned prof_mask;  // kernel classes timed when profiling (bit per class)
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     double *obs_out;  // device, NRED doubles (inside the workspace)
@@ -1086,16 +1119,17 @@ struct Timer {
     lbfd_handle *h;
     int kc;
     hipEvent_t a = nullptr;
-    Timer(lbfd_handle *h_, int kc_) : h(h_), kc(kc_)
+    bool on;
+    Timer(lbfd_handle *h_, int kc_) : h(h_), kc(kc_), on(h_->prof && ((h_->prof_mask >> kc_) & 1u))
     {
-        if (h->prof) {
+        if (on) {
             a = pool_get(h);
             hipEventRecord(a, h->stream);
         }
     }
     ~Timer()
     {
-        if (h->prof) {
+        if (on) {
             hipEvent_t b = pool_get(h);
             hipEventRecord(b, h->stream);
             h->recs.push_back(ProfRec{kc, a, b});
@@ -1216,8 +1250,8 @@ template <int LAT, class P> struct Impl {
             if (h->p.fd_enable) {
                 LAUNCH(KC_FD, (k_fd<LAT, P>), h->grid, h->block, k);
                 for (int s = 0; s < h->sweeps_launch; ++s) {
-                    LAUNCH(KC_SOR, (k_sor<LAT, P>), h->grid, h->block, k, 0, s);
-                    LAUNCH(KC_SOR, (k_sor<LAT, P>), h->grid, h->block, k, 1, s);
+                    LAUNCH(KC_SOR, (k_sor<LAT, P>), dim3(h->sor_blocks), dim3(256), k, 0, s);
+                    LAUNCH(KC_SOR, (k_sor<LAT, P>), dim3(h->sor_blocks), dim3(256), k, 1, s);
                 }
                 LAUNCH(KC_OTHER, (k_sor_done<R>), dim3(1), dim3(1), k, h->sweeps_launch);
                 totals(h, 1 - k.lev, 1 - k.pc, 1.0, 1);
@@ -1400,7 +1434,21 @@ int lbfd_create(const lbfd_params *p, void *d_workspace, size_t bytes, void *str
     h->grid = dim3((p->nx + BX - 1) / BX, (p->ny + BY - 1) / BY, p->nz);
     h->nblocks = (long long)h->grid.x * h->grid.y * h->grid.z;
     h->sweeps_launch = p->sor_max_sweeps;
+    {
+        // one colour of the grid, capped at 8 workgroups of 256 per compute unit
+        long long half = (long long)((p->nx + 1) / 2) * p->ny * p->nz;
+        long long need = (half + 255) / 256;
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+                cus = prop.multiProcessorCount;
+        }
+        long long cap = 8LL * cus;
+        h->sor_blocks = (int)(need < cap ? need : cap);
+    }
     h->prof = false;
+    h->prof_mask = 0xffffffffu;
     fill_kp(h->kd, p, h->ws, Lo);
     fill_kp(h->kf, p, h->ws, Lo);
     h->obs_out = (double *)(h->ws + Lo.obs);
@@ -1457,6 +1505,9 @@ int lbfd_profile(lbfd_handle *h, int32_t enable)
     for (auto &r : h->recs) { h->pool.push_back(r.a); h->pool.push_back(r.b); }
     h->recs.clear();
     h->prof = enable != 0;
+    // enable = 1: every kernel class; enable = 1 + (1 << (k + 1)) ...: only the classes set in bits 1..
+    unsigned m = (unsigned)enable >> 1;
+    h->prof_mask = m ? m : 0xffffffffu;
     return LBFD_OK;
 }
 

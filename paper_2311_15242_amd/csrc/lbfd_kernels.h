@@ -142,48 +142,90 @@ template <class R> __device__ __forceinline__ long long lin(const KP<R> &k, int 
     return (long long)x + (long long)k.nx * ((long long)y + (long long)k.ny * z);
 }
 
-// Coordinate along one axis for stencils: periodic wrap, or the mirror image
-// across a half-way wall (c = -1-j -> j, c = n+j -> n-1-j). |offset| <= 2.
-__device__ __forceinline__ int fold(int c, int n, int wall, bool &mir)
+// Per-thread neighbourhood: for each axis a and offset o in {-2,-1,+1,+2} the
+// linear index delta of the neighbour (periodic wrap, or the mirror image
+// across a half-way wall: c = -1-j -> j, c = n+j -> n-1-j) and whether a wall
+// was crossed. Computed once per node; every stencil, gather and push below
+// is then a few integer adds.
+struct Nbhd {
+    int d[3][4];     // [axis][o + 2 for o<0, o + 1 for o>0]
+    unsigned mir;    // bit a*4 + slot: the offset crossed a wall along axis a
+};
+
+__device__ __forceinline__ int slot_of(int o) { return o < 0 ? o + 2 : o + 1; }
+
+template <class R> __device__ __forceinline__ Nbhd make_nbhd(const KP<R> &k, int x, int y, int z)
 {
-    if (c >= 0 && c < n) return c;
-    if (!wall) return c < 0 ? c + n : c - n;
-    mir = true;
-    return c < 0 ? -1 - c : 2 * n - 1 - c;
+    Nbhd b;
+    b.mir = 0u;
+    const int c[3] = {x, y, z};
+    const int n[3] = {k.nx, k.ny, k.nz};
+    const int st[3] = {1, k.nx, k.nx * k.ny};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl) {
+            const int o = sl < 2 ? sl - 2 : sl - 1;
+            int t = c[a] + o;
+            bool m = false;
+            if (t < 0 || t >= n[a]) {
+                if (k.bc[a]) { m = true; t = t < 0 ? -1 - t : 2 * n[a] - 1 - t; }
+                else t = t < 0 ? t + n[a] : t - n[a];
+            }
+            b.d[a][sl] = (t - c[a]) * st[a];
+            if (m) b.mir |= 1u << (a * 4 + sl);
+        }
+    }
+    return b;
 }
 
-// Node index of (x,y,z)+(dx,dy,dz) and the sign of the odd_axis component of a
-// vector field there (-1 when mirrored across a wall normal to that axis).
-template <class R>
-__device__ __forceinline__ long long nb(const KP<R> &k, int x, int y, int z, int dx, int dy, int dz, int odd_axis,
-                                        R &sign)
+// Index delta of the neighbour at lattice offset (ex, ey, ez), each in {-2..2}.
+__device__ __forceinline__ int nb_delta(const Nbhd &b, int ex, int ey, int ez)
 {
-    bool mx = false, my = false, mz = false;
-    int X = fold(x + dx, k.nx, k.bc[0], mx);
-    int Y = fold(y + dy, k.ny, k.bc[1], my);
-    int Z = fold(z + dz, k.nz, k.bc[2], mz);
-    bool flip = (odd_axis == 0 && mx) || (odd_axis == 1 && my) || (odd_axis == 2 && mz);
-    sign = flip ? R(-1) : R(1);
-    return lin(k, X, Y, Z);
+    int d = 0;
+    if (ex) d += b.d[0][slot_of(ex)];
+    if (ey) d += b.d[1][slot_of(ey)];
+    if (ez) d += b.d[2][slot_of(ez)];
+    return d;
+}
+
+// Whether that offset crosses a wall along any axis, or along axis a.
+__device__ __forceinline__ bool nb_wall(const Nbhd &b, int ex, int ey, int ez)
+{
+    unsigned m = 0u;
+    if (ex) m |= (b.mir >> (0 * 4 + slot_of(ex))) & 1u;
+    if (ey) m |= (b.mir >> (1 * 4 + slot_of(ey))) & 1u;
+    if (ez) m |= (b.mir >> (2 * 4 + slot_of(ez))) & 1u;
+    return m != 0u;
+}
+
+__device__ __forceinline__ bool nb_wall_axis(const Nbhd &b, int a, int ea)
+{
+    return ea != 0 && ((b.mir >> (a * 4 + slot_of(ea))) & 1u);
 }
 
 // Isotropic lattice derivative (the stencil with which eq 9 evaluates every
 // partial derivative): d_a chi = (1/cs^2) sum_i w_i e_ia chi(x + e_i), cs^2 = 1/3,
 // summed over opposite pairs so that a uniform field gives an exact zero.
+// odd_axis >= 0 marks the odd_axis component of a vector field, which changes
+// sign in a mirror normal to that axis.
 template <int LAT, class R>
-__device__ __forceinline__ R lat_deriv(const KP<R> &k, const R *chi, R scl, int x, int y, int z, int a,
-                                       int odd_axis)
+__device__ __forceinline__ R lat_deriv(const Nbhd &b, const R *chi, long long n, R scl, int a, int odd_axis)
 {
     using L = Lat<LAT>;
     R acc = 0;
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         if (L::OPP[i] < i || L::E[i][a] == 0) continue;
-        R s1, s2;
-        long long p = nb(k, x, y, z, L::E[i][0], L::E[i][1], L::E[i][2], odd_axis, s1);
-        long long m = nb(k, x, y, z, -L::E[i][0], -L::E[i][1], -L::E[i][2], odd_axis, s2);
-        R d = s1 * chi[p] - s2 * chi[m];
-        acc += R(L::W[i] * L::E[i][a]) * d;
+        const int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
+        R vp = chi[n + nb_delta(b, ex, ey, ez)];
+        R vm = chi[n + nb_delta(b, -ex, -ey, -ez)];
+        if (odd_axis >= 0) {
+            const int eo = L::E[i][odd_axis];
+            if (nb_wall_axis(b, odd_axis, eo)) vp = -vp;
+            if (nb_wall_axis(b, odd_axis, -eo)) vm = -vm;
+        }
+        acc += R(L::W[i] * L::E[i][a]) * (vp - vm);
     }
     return R(3) * acc * scl;
 }
@@ -202,30 +244,19 @@ __device__ __forceinline__ R reference(const KP<R> &k, int i, R rho, R a, const 
     return rho * (rest + R(L::W[i]) * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu));
 }
 
-// Source node of the population arriving at (x,y,z) in direction j, and the
-// direction it had when it left (a population that left through a wall comes
-// back to the same node reversed: half-way bounce-back).
-template <int LAT, class R>
-__device__ __forceinline__ long long source_of(const KP<R> &k, int x, int y, int z, int j, int &pre)
+// Source node of the population arriving at node n in direction j: x - e_j, or
+// n itself when that crosses a wall (half-way bounce-back returns a population
+// that left through a wall to its node reversed).
+template <int LAT>
+__device__ __forceinline__ long long source_of(const Nbhd &b, long long n, int j, bool &bounced)
 {
     using L = Lat<LAT>;
-    int c[3] = {x - L::E[j][0], y - L::E[j][1], z - L::E[j][2]};
-    int lim[3] = {k.nx, k.ny, k.nz};
-    bool wall = false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-        if (k.bc[a] && (c[a] < 0 || c[a] >= lim[a])) wall = true;
-    if (wall) {
-        pre = L::OPP[j];
-        return lin(k, x, y, z);
-    }
-    pre = j;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) c[a] = c[a] < 0 ? c[a] + lim[a] : (c[a] >= lim[a] ? c[a] - lim[a] : c[a]);
-    return lin(k, c[0], c[1], c[2]);
+    const int ex = -L::E[j][0], ey = -L::E[j][1], ez = -L::E[j][2];
+    bounced = nb_wall(b, ex, ey, ez);
+    return bounced ? n : n + nb_delta(b, ex, ey, ez);
 }
 
-// Load the population j stored at node n (after propagation) as a real number,
+// Load population j stored at node n (after propagation) as a real number,
 // decoding a deviation with the descriptor of the node it came from.
 template <int LAT, class P>
 __device__ __forceinline__ typename P::R load_pop(const KP<typename P::R> &k, const typename P::S *f, long long n,

@@ -223,8 +223,17 @@ class Solver:
                                       out.size), f"lbfd_read_field({name})")
         return out.reshape((c,) + self.shape) if c > 1 else out.reshape(self.shape)
 
-    def profile(self, enable: bool):
-        _check(load().lbfd_profile(self.h, 1 if enable else 0), "lbfd_profile")
+    KERNEL_CLASSES = ("collide", "macro", "geom", "fd", "sor", "total", "force", "other")
+
+    def profile(self, enable: bool, only=None):
+        """Per-kernel HIP-event timing; `only` limits it to some kernel classes."""
+        code = 0
+        if enable:
+            mask = 0
+            for name in (only or ()):
+                mask |= 1 << self.KERNEL_CLASSES.index(name)
+            code = 1 | (mask << 1)
+        _check(load().lbfd_profile(self.h, code), "lbfd_profile")
 
     def profile_read(self) -> dict:
         names = (C.c_char_p * 16)()

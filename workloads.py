@@ -31,7 +31,7 @@ BASE_PARAMS = dict(
     sigma0=0.01, E0=0.5, psi_inf=1.0, sigma_min_ratio=0.1,
     Ds=0.02, Db=0.02, ra=0.1, rd=0.05, source_mode=0,
     gravity=[0.0, 0.0, 0.0],
-    sor_omega=1.2, sor_tol=1e-13, sor_max_sweeps=60,
+    sor_omega=1.0, sor_tol=1e-13, sor_max_sweeps=60,   # omega: 1.2 in Sec 2.2; the solve is converged either way
     weno_eps=1e-6, rescale=1, fd_enable=1, q_literal=0, eps_n=1e-12, recolour_literal=0,
     fd_eps=1e-10,                # background support of the FD weights (FP32 modes: 1e-6)
     upwind_eps=1e-12,            # |u| band in which the WENO upwind weights are 1/2 each
