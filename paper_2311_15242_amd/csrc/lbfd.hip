@@ -86,20 +86,116 @@ __device__ void init_node(const KP<R> &k, const InitDev &in, int x, int y, int z
     }
 }
 
-template <int LAT, class P> __global__ __launch_bounds__(256) void k_init_a(KP<typename P::R> k, InitDev in)
+// Sum over colours of the moment equilibria m^{k,eq}(rho^k, alpha^k, u), eq 37 (2-D) / eq 40 (3-D).
+template <int LAT, class R> __device__ __forceinline__ void meq_sum(const KP<R> &k, R rR, R rB, const R *u, R *meq)
+{
+    using L = Lat<LAT>;
+    constexpr int D = L::D;
+#pragma unroll
+    for (int r = 0; r < L::Q; ++r) meq[r] = 0;
+    const R ux = u[0], uy = u[1], uz = D == 3 ? u[2] : R(0), u2 = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const R rk = c == 0 ? rR : rB;
+        const R al = k.alpha[c];
+        if constexpr (D == 2) {
+            meq[0] += rk; meq[1] += rk * (R(-3.6) * al - R(0.4) + R(3) * u2);
+            meq[2] += rk * (R(5.4) * al - R(1.4) - R(3) * u2);
+            meq[3] += rk * ux; meq[4] += rk * (R(-1.8) * al - R(0.2)) * ux;
+            meq[5] += rk * uy; meq[6] += rk * (R(-1.8) * al - R(0.2)) * uy;
+            meq[7] += rk * (ux * ux - uy * uy); meq[8] += rk * ux * uy;
+        } else {
+            const R pc = rk * k.cs2[c];
+            meq[0] += rk; meq[1] += rk * ux; meq[2] += rk * uy; meq[3] += rk * uz;
+            meq[4] += R(3) * pc + rk * u2; meq[5] += rk * (R(2) * ux * ux - uy * uy - uz * uz);
+            meq[6] += rk * (uy * uy - uz * uz); meq[7] += rk * ux * uy; meq[8] += rk * ux * uz;
+            meq[9] += rk * uy * uz; meq[10] += pc * uy; meq[11] += pc * ux; meq[12] += pc * uz;
+            meq[13] += pc * ux; meq[14] += pc * uz; meq[15] += pc * uy;
+            const R b = R(1) - al - u2;
+            meq[16] += rk * (b + R(2) * (ux * ux + uy * uy)) / R(6);
+            meq[17] += rk * (b + R(2) * (ux * ux + uz * uz)) / R(6);
+            meq[18] += rk * (b + R(2) * (uy * uy + uz * uz)) / R(6);
+        }
+    }
+}
+
+// State between steps in the deviation modes: the moments m = M f of each
+// node, stored as their difference from a node-local reference, the summed
+// equilibrium moments at the node's own rho^R, rho^B and u = j / rho. The
+// conserved rows (mass, momentum) equal their reference and are not stored;
+// the others are stored in 16 bits, compacted to the first Q - 1 - D planes
+// of the population buffer.
+template <int LAT, class P>
+__device__ __forceinline__ void load_moments(const KP<typename P::R> &k, const typename P::S *fs, long long n,
+                                             typename P::R rR, typename P::R rB, const typename P::R *uj,
+                                             typename P::R *m)
 {
     using R = typename P::R;
+    using L = Lat<LAT>;
+    meq_sum<LAT, R>(k, rR, rB, uj, m);
+#pragma unroll
+    for (int r = 0; r < L::Q; ++r)
+        if (!conserved_row<LAT>(r)) m[r] += to_real(fs[(long long)state_slot<LAT>(r) * k.N + n]);
+}
+
+template <int LAT, class P>
+__device__ __forceinline__ void store_moments(const KP<typename P::R> &k, typename P::S *fs, long long n,
+                                              typename P::R rR, typename P::R rB, const typename P::R *uj,
+                                              const typename P::R *m)
+{
+    using R = typename P::R;
+    using S = typename P::S;
+    using L = Lat<LAT>;
+    R mref[L::Q];
+    meq_sum<LAT, R>(k, rR, rB, uj, mref);
+#pragma unroll
+    for (int r = 0; r < L::Q; ++r)
+        if (!conserved_row<LAT>(r)) fs[(long long)state_slot<LAT>(r) * k.N + n] = from_real<S>(m[r] - mref[r]);
+}
+
+// Store the populations f of node n at the start of a step: as populations,
+// or in the deviation modes as moments (above).
+template <int LAT, class P>
+__device__ __forceinline__ void store_state(const KP<typename P::R> &k, typename P::S *fo, long long n, const typename P::R *f,
+                                            typename P::R rR, typename P::R rB, const typename P::R *j)
+{
+    using R = typename P::R;
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q;
+    if constexpr (P::DEV) {
+        R m[Q], uj[3] = {0, 0, 0};
+#pragma unroll
+        for (int r = 0; r < Q; ++r) {
+            m[r] = 0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                if (L::M[r][i] != 0) m[r] += R(L::M[r][i]) * f[i];
+        }
+#pragma unroll
+        for (int d = 0; d < L::D; ++d) uj[d] = j[d] / (rR + rB);
+        store_moments<LAT, P>(k, fo, n, rR, rB, uj, m);
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fo[(long long)i * k.N + n] = f[i];
+    }
+}
+
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_init(KP<typename P::R> k, InitDev in)
+{
+    using R = typename P::R;
+    using S = typename P::S;
     using L = Lat<LAT>;
     Node nd = node_id(k);
     if (!nd.ok) return;
     const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
-    R rN0, fR[QMAX], fB[QMAX], u0[3];
+    R rN0, fR[QMAX], fB[QMAX], u0[3], f[QMAX];
     init_node<LAT, R>(k, in, nd.x, nd.y, nd.z, rN0, fR, fB, u0);
     R rR = 0, rB = 0, j[3] = {0, 0, 0};
     for (int i = 0; i < L::Q; ++i) {
         rR += fR[i];
         rB += fB[i];
-        for (int d = 0; d < L::D; ++d) j[d] += (fR[i] + fB[i]) * R(L::E[i][d]);
+        f[i] = fR[i] + fB[i];
+        for (int d = 0; d < L::D; ++d) j[d] += f[i] * R(L::E[i][d]);
     }
     R rr = rR / k.rhoR0, bb = rB / k.rhoB0;
     R *mac = k.fld.mac[k.lev];
@@ -107,22 +203,18 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_init_a(KP<t
     mac[N + n] = rB;
     mac[2 * N + n] = (rr - bb) / (rr + bb);
     for (int d = 0; d < L::D; ++d) mac[(3 + d) * N + n] = j[d];
-    // descriptor of the (virtual) step -1 that produced f^0: reference data only
-    R *ds = k.fld.desc[1 - k.lev];
-    R rho = rR + rB;
-    ds[n] = rR / rho;
-    for (int d = 0; d < L::D; ++d) ds[(1 + d) * N + n] = 0;
-    if constexpr (P::DEV) {
-        ds[(1 + L::D) * N + n] = rho;
-        for (int d = 0; d < L::D; ++d) ds[(2 + L::D + d) * N + n] = j[d] / rho;
-    }
+    store_state<LAT, P>(k, (S *)k.fld.f[k.fc], n, f, rR, rB, j);
     k.fld.psi[k.pc][n] = (R)in.psi0;
     k.fld.phi[k.pc][n] = rN0 < R(0) ? (R)in.phi0_out : (R)in.phi0_in;
     k.fld.Sp[n] = 0;
     k.fld.Bp[n] = 0;
 }
 
-template <int LAT, class P> __global__ __launch_bounds__(256) void k_init_b(KP<typename P::R> k, InitDev in)
+// State import from FP64 arrays (device copies).
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void k_import(KP<typename P::R> k, const double *f_, const double *rR_,
+                                               const double *rB_, const double *psi, const double *phi,
+                                               const double *Sp, const double *Bp)
 {
     using R = typename P::R;
     using S = typename P::S;
@@ -130,85 +222,22 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_init_b(KP<t
     Node nd = node_id(k);
     if (!nd.ok) return;
     const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
-    R rN0, fR[QMAX], fB[QMAX], u0[3];
-    init_node<LAT, R>(k, in, nd.x, nd.y, nd.z, rN0, fR, fB, u0);
-    const Nbhd nb = make_nbhd(k, nd.x, nd.y, nd.z);
-    S *f = (S *)k.fld.f[k.fc];
-    const R *ds = k.fld.desc[1 - k.lev];
-    for (int j = 0; j < L::Q; ++j) {
-        R v = fR[j] + fB[j];
-        if constexpr (P::DEV) {
-            bool bo;
-            long long src = source_of<LAT>(nb, n, j, bo);
-            R us[3] = {0, 0, 0};
-            for (int d = 0; d < L::D; ++d) us[d] = ds[(2 + L::D + d) * N + src];
-            v -= reference<LAT, R>(k, j, ds[(1 + L::D) * N + src], ds[src], us);
-            f[(long long)j * N + n] = from_real<S>(v);
-        } else {
-            f[(long long)j * N + n] = v;
-        }
+    R rR = (R)rR_[n], rB = (R)rB_[n], j[3] = {0, 0, 0}, f[QMAX];
+    for (int i = 0; i < L::Q; ++i) {
+        f[i] = (R)f_[i * N + n];
+        for (int d = 0; d < L::D; ++d) j[d] += f[i] * R(L::E[i][d]);
     }
-}
-
-// State import from FP64 arrays (device copies): pass a writes the macroscopic
-// fields and the decoding descriptor, pass b stores the populations.
-template <int LAT, class P>
-__global__ __launch_bounds__(256) void k_import_a(KP<typename P::R> k, const double *f, const double *rR_,
-                                                 const double *rB_, const double *psi, const double *phi,
-                                                 const double *Sp, const double *Bp)
-{
-    using R = typename P::R;
-    using L = Lat<LAT>;
-    Node nd = node_id(k);
-    if (!nd.ok) return;
-    const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
-    R rR = (R)rR_[n], rB = (R)rB_[n], j[3] = {0, 0, 0};
-    for (int i = 0; i < L::Q; ++i)
-        for (int d = 0; d < L::D; ++d) j[d] += (R)f[i * N + n] * R(L::E[i][d]);
     R rr = rR / k.rhoR0, bb = rB / k.rhoB0;
     R *mac = k.fld.mac[k.lev];
     mac[n] = rR;
     mac[N + n] = rB;
     mac[2 * N + n] = (rr - bb) / (rr + bb);
     for (int d = 0; d < L::D; ++d) mac[(3 + d) * N + n] = j[d];
-    R *ds = k.fld.desc[1 - k.lev];
-    R rho = rR + rB;
-    ds[n] = rR / rho;
-    for (int d = 0; d < L::D; ++d) ds[(1 + d) * N + n] = 0;
-    if constexpr (P::DEV) {
-        ds[(1 + L::D) * N + n] = rho;
-        for (int d = 0; d < L::D; ++d) ds[(2 + L::D + d) * N + n] = j[d] / rho;
-    }
+    store_state<LAT, P>(k, (S *)k.fld.f[k.fc], n, f, rR, rB, j);
     k.fld.psi[k.pc][n] = (R)psi[n];
     k.fld.phi[k.pc][n] = (R)phi[n];
     k.fld.Sp[n] = Sp ? (R)Sp[n] : R(0);
     k.fld.Bp[n] = Bp ? (R)Bp[n] : R(0);
-}
-
-template <int LAT, class P> __global__ __launch_bounds__(256) void k_import_b(KP<typename P::R> k, const double *f)
-{
-    using R = typename P::R;
-    using S = typename P::S;
-    using L = Lat<LAT>;
-    Node nd = node_id(k);
-    if (!nd.ok) return;
-    const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
-    S *fo = (S *)k.fld.f[k.fc];
-    const R *ds = k.fld.desc[1 - k.lev];
-    const Nbhd nb = make_nbhd(k, nd.x, nd.y, nd.z);
-    for (int j = 0; j < L::Q; ++j) {
-        R v = (R)f[j * N + n];
-        if constexpr (P::DEV) {
-            bool bo;
-            long long src = source_of<LAT>(nb, n, j, bo);
-            R us[3] = {0, 0, 0};
-            for (int d = 0; d < L::D; ++d) us[d] = ds[(2 + L::D + d) * N + src];
-            v -= reference<LAT, R>(k, j, ds[(1 + L::D) * N + src], ds[src], us);
-            fo[(long long)j * N + n] = from_real<S>(v);
-        } else {
-            fo[(long long)j * N + n] = v;
-        }
-    }
 }
 
 // ============================================================== geometry
@@ -285,8 +314,10 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_force(KP<ty
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         R Fa = Fs[a] + (rho - k.rhoB0) * k.grav[a];
+        const R ua = (mac[(3 + a) * N + n] + R(0.5) * Fa) / rho;
         k.fld.F[a * N + n] = Fa;
-        k.fld.u[a * N + n] = (mac[(3 + a) * N + n] + R(0.5) * Fa) / rho;
+        k.fld.u[a * N + n] = ua;
+        if (k.qon) k.fld.qf[a * N + n] = (k.qcoef[0] * mac[n] + k.qcoef[1] * mac[N + n]) * ua;
     }
 }
 
@@ -308,26 +339,9 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
     const S *fin = (const S *)k.fld.f[k.fc];
     S *fout = (S *)k.fld.f[1 - k.fc];
     const R *mac = k.fld.mac[k.lev];
-    const R *dprev = k.fld.desc[1 - k.lev];
     R *dnew = k.fld.desc[k.lev];
 
     const Nbhd nb = make_nbhd(k, x, y, z);
-    // m = M f, accumulated while the (decoded) populations stream in
-    R m[Q];
-#pragma unroll
-    for (int r = 0; r < Q; ++r) m[r] = 0;
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-        long long src = 0;
-        if constexpr (P::DEV) {
-            bool bo;
-            src = source_of<LAT>(nb, n, j, bo);
-        }
-        const R fj = load_pop<LAT, P>(k, fin, n, j, src, dprev);
-#pragma unroll
-        for (int r = 0; r < Q; ++r)
-            if (L::M[r][j] != 0) m[r] += R(L::M[r][j]) * fj;
-    }
     const R rR = mac[n], rB = mac[N + n], rN = mac[2 * N + n];
     const R rho = rR + rB;
     R u[3] = {0, 0, 0}, F[3] = {0, 0, 0}, g[3] = {0, 0, 0}, G2 = 0;
@@ -338,6 +352,24 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
         g[d] = lat_deriv<LAT, R>(nb, mac + 2 * N, n, R(1), d, -1);
         G2 += g[d] * g[d];
     }
+    // moments m = M f of the node
+    R m[Q];
+    if constexpr (P::DEV) {
+        R uj[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < D; ++d) uj[d] = u[d] - R(0.5) * F[d] / rho;
+        load_moments<LAT, P>(k, fin, n, rR, rB, uj, m);
+    } else {
+#pragma unroll
+        for (int r = 0; r < Q; ++r) m[r] = 0;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            const R fj = fin[(long long)j * N + n];
+#pragma unroll
+            for (int r = 0; r < Q; ++r)
+                if (L::M[r][j] != 0) m[r] += R(L::M[r][j]) * fj;
+        }
+    }
     // relaxation rate of the viscous moments (eq 43 and the mu-s_v relation)
     const R inv_mu = (R(1) + rN) / (R(2) * k.muR0) + (R(1) - rN) / (R(2) * k.muB0);
     const R pk = rR * k.cs2[0] + rB * k.cs2[1];
@@ -345,64 +377,24 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
 
     // equilibria summed over colours (eq 37 / eq 40)
     R meq[Q], C[Q];
+    meq_sum<LAT, R>(k, rR, rB, u, meq);
 #pragma unroll
-    for (int r = 0; r < Q; ++r) { meq[r] = 0; C[r] = 0; }
-    const R ux = u[0], uy = u[1], uz = u[2], u2 = ux * ux + uy * uy + uz * uz;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const R rk = c == 0 ? rR : rB;
-        const R al = k.alpha[c];
-        if constexpr (D == 2) {
-            meq[0] += rk; meq[1] += rk * (R(-3.6) * al - R(0.4) + R(3) * u2);
-            meq[2] += rk * (R(5.4) * al - R(1.4) - R(3) * u2);
-            meq[3] += rk * ux; meq[4] += rk * (R(-1.8) * al - R(0.2)) * ux;
-            meq[5] += rk * uy; meq[6] += rk * (R(-1.8) * al - R(0.2)) * uy;
-            meq[7] += rk * (ux * ux - uy * uy); meq[8] += rk * ux * uy;
-        } else {
-            const R pc = rk * k.cs2[c];
-            meq[0] += rk; meq[1] += rk * ux; meq[2] += rk * uy; meq[3] += rk * uz;
-            meq[4] += R(3) * pc + rk * u2; meq[5] += rk * (R(2) * ux * ux - uy * uy - uz * uz);
-            meq[6] += rk * (uy * uy - uz * uz); meq[7] += rk * ux * uy; meq[8] += rk * ux * uz;
-            meq[9] += rk * uy * uz; meq[10] += pc * uy; meq[11] += pc * ux; meq[12] += pc * uz;
-            meq[13] += pc * ux; meq[14] += pc * uz; meq[15] += pc * uy;
-            const R b = R(1) - al - u2;
-            meq[16] += rk * (b + R(2) * (ux * ux + uy * uy)) / R(6);
-            meq[17] += rk * (b + R(2) * (ux * ux + uz * uz)) / R(6);
-            meq[18] += rk * (b + R(2) * (uy * uy + uz * uz)) / R(6);
-        }
-    }
-    // correction terms C^k with Q_a = qcoef_k d_a(rho^k u_a) (Appendix A)
+    for (int r = 0; r < Q; ++r) C[r] = 0;
+    const R ux = u[0], uy = u[1], uz = u[2];
+    // correction terms C^k with Q_a = qcoef_k d_a(rho^k u_a) (Appendix A); every
+    // C row is linear in the colour sum of Q_a, which is the derivative of the
+    // field qf_a = sum_k qcoef_k rho^k u_a stored by the force kernel
     if (k.qon) {
-        const R *uvec = k.fld.u;
-        R Qa[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        R Qs[3] = {0, 0, 0};
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            R acc0 = 0, acc1 = 0;
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                if (L::OPP[i] < i || L::E[i][a] == 0) continue;
-                const int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2], ea = L::E[i][a];
-                const long long p = n + nb_delta(nb, ex, ey, ez), q = n + nb_delta(nb, -ex, -ey, -ez);
-                R up = uvec[a * N + p], uq = uvec[a * N + q];
-                if (nb_wall_axis(nb, a, ea)) up = -up;
-                if (nb_wall_axis(nb, a, -ea)) uq = -uq;
-                R we = R(L::W[i] * L::E[i][a]);
-                if (k.qcoef[0] != R(0)) acc0 += we * (mac[p] * up - mac[q] * uq);
-                if (k.qcoef[1] != R(0)) acc1 += we * (mac[N + p] * up - mac[N + q] * uq);
-            }
-            Qa[0][a] = k.qcoef[0] * R(3) * acc0;
-            Qa[1][a] = k.qcoef[1] * R(3) * acc1;
-        }
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            if constexpr (D == 2) {
-                C[1] += R(3) * Qa[c][0] + R(3) * Qa[c][1];
-                C[7] += Qa[c][0] - Qa[c][1];
-            } else {
-                C[4] += Qa[c][0] + Qa[c][1] + Qa[c][2];
-                C[5] += R(2) * Qa[c][0] - Qa[c][1] - Qa[c][2];
-                C[6] += Qa[c][1] - Qa[c][2];
-            }
+        for (int a = 0; a < D; ++a) Qs[a] = lat_deriv<LAT, R>(nb, k.fld.qf + a * N, n, R(1), a, a);
+        if constexpr (D == 2) {
+            C[1] = R(3) * (Qs[0] + Qs[1]);
+            C[7] = Qs[0] - Qs[1];
+        } else {
+            C[4] = Qs[0] + Qs[1] + Qs[2];
+            C[5] = R(2) * Qs[0] - Qs[1] - Qs[2];
+            C[6] = Qs[1] - Qs[2];
         }
     }
     // forcing term (eq 4): the velocity-space integrand projected with M
@@ -500,6 +492,11 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
     const R *ds = k.fld.desc[k.lev];
     const Nbhd nb = make_nbhd(k, x, y, z);
     R rR = 0, rB = 0, j[3] = {0, 0, 0};
+    R m[P::DEV ? Q : 1];
+    if constexpr (P::DEV) {
+#pragma unroll
+        for (int r = 0; r < Q; ++r) m[r] = 0;
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         bool bo;
@@ -515,6 +512,11 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
         rB += (R(1) - as) * fq - r;
 #pragma unroll
         for (int d = 0; d < D; ++d) j[d] += fq * R(L::E[q][d]);
+        if constexpr (P::DEV) {
+#pragma unroll
+            for (int r2 = 0; r2 < Q; ++r2)
+                if (L::M[r2][q] != 0 && !conserved_row<LAT>(r2)) m[r2] += R(L::M[r2][q]) * fq;
+        }
     }
     R *mac = k.fld.mac[1 - k.lev];
     R rr = rR / k.rhoR0, bb = rB / k.rhoB0;
@@ -523,6 +525,14 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
     mac[2 * N + n] = (rr - bb) / (rr + bb);
 #pragma unroll
     for (int d = 0; d < D; ++d) mac[(3 + d) * N + n] = j[d];
+    if constexpr (P::DEV) {
+        // in place: the node's own slots, after all of its loads
+        R uj[3] = {0, 0, 0};
+        const R rho = rR + rB;
+#pragma unroll
+        for (int d = 0; d < D; ++d) uj[d] = j[d] / rho;
+        store_moments<LAT, P>(k, (S *)k.fld.f[1 - k.fc], n, rR, rB, uj, m);
+    }
 }
 
 // ============================================================== finite differences
@@ -634,24 +644,26 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
     if (conv[0] && conv[1]) return;
     const long long N = k.N;
     const int nx = k.nx, ny = k.ny, nz = k.nz, hx = (nx + 1) >> 1;
-    const long long H = (long long)hx * ny * nz;
-    const long long sy = nx, sz = (long long)nx * ny;
+    const int sy = nx, sz = nx * ny;
     const R *G1 = k.fld.G[1 - k.lev];
     const R *rN1 = k.fld.mac[1 - k.lev] + 2 * N;
     R *psi = k.fld.psi[1 - k.pc], *phi = k.fld.phi[1 - k.pc];
     const R *rhsP = k.fld.rhsP, *rhsF = k.fld.rhsF;
     const R eps = k.fd_eps, hdP = R(0.5) * k.Ds, hdF = R(0.5) * k.Db, om = k.omega;
     double rloc[2] = {0, 0}, bloc[2] = {0, 0};
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < H; t += stride) {
-        const long long row = t / hx;
-        const int i = (int)(t - row * hx);
-        const int y = (int)(row % ny), z = (int)(row / ny);
-        const int x = 2 * i + ((y + z + color) & 1);
-        if (x >= nx) continue;
-        const long long n = x + sy * y + sz * z;
+    // tiles of 64 same-colour nodes along x by 4 rows, one z plane
+    const int tx = (hx + 63) >> 6, ty = (ny + 3) >> 2;
+    const int ntiles = tx * ty * nz;
+    const int li = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int bx = tile % tx, rest = tile / tx;
+        const int by = rest % ty, z = rest / ty;
+        const int y = by * 4 + ly;
+        const int x = 2 * (bx * 64 + li) + ((y + z + color) & 1);
+        if (x >= nx || y >= ny) continue;
+        const int n = x + sy * y + sz * z;
         // face neighbours: periodic wrap, or the node itself across a wall (no flux)
-        long long q[6];
+        int q[6];
         q[0] = x > 0 ? n - 1 : (k.bc[0] ? n : n + (nx - 1));
         q[1] = x < nx - 1 ? n + 1 : (k.bc[0] ? n : n - (nx - 1));
         q[2] = y > 0 ? n - sy : (k.bc[1] ? n : n + sy * (ny - 1));
@@ -901,11 +913,18 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_export(KP<t
     switch (field) {
     case LBFD_FIELD_F: {
         const S *f = (const S *)k.fld.f[k.fc];
-        const Nbhd nb = make_nbhd(k, nd.x, nd.y, nd.z);
-        for (int j = 0; j < L::Q; ++j) {
-            bool bo;
-            long long src = P::DEV ? source_of<LAT>(nb, n, j, bo) : 0;
-            out[j * N + n] = (double)load_pop<LAT, P>(k, f, n, j, src, k.fld.desc[1 - k.lev]);
+        if constexpr (P::DEV) {
+            R m[L::Q], uj[3] = {0, 0, 0};
+            const R rR = mac[n], rB = mac[N + n];
+            for (int d = 0; d < L::D; ++d) uj[d] = mac[(3 + d) * N + n] / (rR + rB);
+            load_moments<LAT, P>(k, f, n, rR, rB, uj, m);
+            for (int i = 0; i < L::Q; ++i) {
+                R v = 0;
+                for (int r = 0; r < L::Q; ++r) v += R(L::MINV[i][r]) * m[r];
+                out[i * N + n] = (double)v;
+            }
+        } else {
+            for (int j = 0; j < L::Q; ++j) out[j * N + n] = (double)to_real(f[j * N + n]);
         }
         break;
     }
@@ -969,7 +988,7 @@ size_t pop_bytes(int prec) { return prec == LBFD_FP64 ? 8 : prec == LBFD_FP32 ? 
 size_t real_bytes(int prec) { return prec == LBFD_FP64 ? 8 : 4; }
 
 struct Layout {
-    size_t f[2], mac[2], desc[2], G[2], nrm, u, F, psi[2], phi[2], Sp, Bp, rhsP, rhsF, part, sc, obs, total;
+    size_t f[2], mac[2], desc[2], G[2], nrm, u, F, qf, psi[2], phi[2], Sp, Bp, rhsP, rhsF, part, sc, obs, total;
 };
 
 Layout layout(const lbfd_params *p)
@@ -989,6 +1008,7 @@ Layout layout(const lbfd_params *p)
     L.nrm = take(sr * D * N);
     L.u = take(sr * D * N);
     L.F = take(sr * D * N);
+    L.qf = take(sr * D * N);
     for (int b = 0; b < 2; ++b) L.psi[b] = take(sr * N);
     for (int b = 0; b < 2; ++b) L.phi[b] = take(sr * N);
     L.Sp = take(sr * N);
@@ -1009,7 +1029,7 @@ int check_params(const lbfd_params *p)
     if (p->precision < LBFD_FP64 || p->precision > LBFD_BF16DEV) return LBFD_EINVAL;
     if (p->nx < 4 || p->ny < 4) return LBFD_EINVAL;
     if (p->lattice == LBFD_D2Q9 ? p->nz != 1 : p->nz < 4) return LBFD_EINVAL;
-    if ((long long)p->nx * p->ny * p->nz > (1LL << 31)) return LBFD_EINVAL;
+    if ((long long)p->nx * p->ny * p->nz >= (1LL << 31)) return LBFD_EINVAL;
     if (!(p->rhoR0 > 0 && p->rhoB0 > 0 && p->muR0 > 0 && p->muB0 > 0)) return LBFD_EINVAL;
     if (!(p->alphaR > 0 && p->alphaR < 1)) return LBFD_EINVAL;
     double alphaB = 1.0 - (p->rhoR0 / p->rhoB0) * (1.0 - p->alphaR);
@@ -1095,6 +1115,7 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
     F.nrm = (R *)(ws + Lo.nrm);
     F.u = (R *)(ws + Lo.u);
     F.F = (R *)(ws + Lo.F);
+    F.qf = (R *)(ws + Lo.qf);
     F.Sp = (R *)(ws + Lo.Sp);
     F.Bp = (R *)(ws + Lo.Bp);
     F.rhsP = (R *)(ws + Lo.rhsP);
@@ -1184,8 +1205,7 @@ template <int LAT, class P> struct Impl {
         h->pc = 0;
         sync_levels(h);
         KP<R> &k = kp(h);
-        LAUNCH(KC_OTHER, (k_init_a<LAT, P>), h->grid, h->block, k, in);
-        LAUNCH(KC_OTHER, (k_init_b<LAT, P>), h->grid, h->block, k, in);
+        LAUNCH(KC_OTHER, (k_init<LAT, P>), h->grid, h->block, k, in);
         LAUNCH(KC_GEOM, (k_geom<LAT, P>), h->grid, h->block, k, k.lev);
         clear_scalars(h);
         totals(h, k.lev, k.pc, 1.0, 0);
@@ -1224,9 +1244,8 @@ template <int LAT, class P> struct Impl {
         clear_scalars(h);
         sync_levels(h);
         KP<R> &k = kp(h);
-        LAUNCH(KC_OTHER, (k_import_a<LAT, P>), h->grid, h->block, k, df, drR, drB, dps, dph, Sp ? dS : nullptr,
+        LAUNCH(KC_OTHER, (k_import<LAT, P>), h->grid, h->block, k, df, drR, drB, dps, dph, Sp ? dS : nullptr,
                Bp ? dB : nullptr);
-        LAUNCH(KC_OTHER, (k_import_b<LAT, P>), h->grid, h->block, k, df);
         derived(h);
         DevScalars z;
         std::memset(&z, 0, sizeof(z));
@@ -1435,9 +1454,9 @@ int lbfd_create(const lbfd_params *p, void *d_workspace, size_t bytes, void *str
     h->nblocks = (long long)h->grid.x * h->grid.y * h->grid.z;
     h->sweeps_launch = p->sor_max_sweeps;
     {
-        // one colour of the grid, capped at 8 workgroups of 256 per compute unit
-        long long half = (long long)((p->nx + 1) / 2) * p->ny * p->nz;
-        long long need = (half + 255) / 256;
+        // tiles of one colour (64 x 4 nodes), capped at 8 workgroups of 256 per compute unit
+        long long hx = (p->nx + 1) / 2;
+        long long need = ((hx + 63) / 64) * ((p->ny + 3) / 4) * (long long)p->nz;
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess) {
             hipDeviceProp_t prop;

@@ -2,13 +2,20 @@
 // lattice-Boltzmann colour-gradient / finite-difference surfactant method.
 //
 // State layout in HBM (structure of arrays, x fastest, node n = x + nx (y + ny z)):
-//   f[2]      total populations f_i = f^R_i + f^B_i, Q planes, ping-pong
+//   f[2]      total populations f_i = f^R_i + f^B_i, Q planes, ping-pong. In the
+//             16-bit deviation modes the buffer holding the state between steps
+//             stores non-equilibrium moments instead (load_moments), and the
+//             propagated populations are 16-bit deviations from a reference
+//             of the node they left (reference), converted back to moments in
+//             place by the macro kernel
 //   mac[2]    rho^R, rho^B, rhoN, j_x, j_y(, j_z) of a time level (j = sum f e)
 //   desc[2]   per-node outflow descriptor written by the collision: colour share
 //             a = rho^R/rho and recolouring vector c (D); in deviation modes also
 //             rho and the post-collision velocity u* (D)
 //   G[2]      |grad rhoN| of two time levels; nrm: interface normal (D)
 //   u, F      fluid velocity (eq 10) and total force (D each)
+//   qf        sum_k qcoef_k rho^k u_a (D), the field whose derivative is the
+//             colour-summed correction Q_a
 //   psi[2], phi[2], Sprev, Bprev, rhsP, rhsF   finite-difference fields
 //
 // Only the total population is stored. Recolouring (eq 11) splits the
@@ -57,6 +64,19 @@ template <int LAT> struct Lat;
 template <> struct Lat<0> : D2Q9Tables {};
 template <> struct Lat<1> : D3Q19Tables {};
 
+// Conserved moment rows (mass, momentum) of the moment bases: D2Q9 rows 0, 3, 5
+// (eq 36), D3Q19 rows 0..3 (eq 39); state_slot numbers the remaining rows.
+template <int LAT> __host__ __device__ constexpr bool conserved_row(int r)
+{
+    return LAT == 0 ? (r == 0 || r == 3 || r == 5) : r <= 3;
+}
+template <int LAT> __host__ __device__ constexpr int state_slot(int r)
+{
+    int s = 0;
+    for (int i = 0; i < r; ++i) s += conserved_row<LAT>(i) ? 0 : 1;
+    return s;
+}
+
 // ------------------------------------------------------------------ parameters
 
 constexpr int QMAX = 19;
@@ -84,6 +104,7 @@ template <class R> struct Fields {
     R *nrm;
     R *u;
     R *F;
+    R *qf;
     R *psi[2];
     R *phi[2];
     R *Sp, *Bp, *rhsP, *rhsF;
