@@ -57,12 +57,19 @@ def algorithmic_bytes(kernel: str, p: dict) -> float:
     br = 8 if prec == "fp64" else 4
     dev = prec in ("fp16dev", "bf16dev")
     desc_w = 1 + D + ((1 + D) if dev else 0)      # descriptor written by the collision
-    desc_r_dev = (2 + D) if dev else 0            # a, rho, u* of the sources, to decode deviations
+    # state between steps: Q populations, or (deviation modes) the Q - 1 - D
+    # non-conserved moments
+    state = (Q - 1 - D) if dev else Q
+    # the correction field qf_a exists when some colour has a non-zero
+    # correction prefactor (3-D: 1 - 3 cs^2 with cs^2 = (1 - alpha)/2; 2-D: 1.8 alpha - 0.8)
+    alphaB = 1.0 - (p["rhoR0"] / p["rhoB0"]) * (1.0 - p["alphaR"])
+    qc = [(1.0 - 1.5 * (1.0 - al)) if three else (1.8 * al - 0.8) for al in (p["alphaR"], alphaB)]
+    qf = D if any(abs(c) > 1e-15 for c in qc) else 0
     table = {
-        # f in + f out, rhoR rhoB rhoN, u, F, descriptor out (+ descriptor in)
-        "collide": 2 * Q * bf + (3 + 2 * D + desc_w + desc_r_dev) * br,
-        # f in, descriptor (a, c, +rho, u*) in, rhoR rhoB rhoN j out
-        "macro": Q * bf + (desc_w + 3 + D) * br,
+        # state in, Q populations out; rhoR rhoB rhoN, u, F, qf in; descriptor out
+        "collide": (state + Q) * bf + (3 + 2 * D + qf + desc_w) * br,
+        # Q populations in, descriptor in, rhoR rhoB rhoN j out (+ moment state out)
+        "macro": (Q + (state if dev else 0)) * bf + (desc_w + 3 + D) * br,
         # rhoN in, |grad rhoN| and normal out
         "geom": (2 + D) * br,
         # psi phi G rhoN u Sprev Bprev in; rhs x2, S B, psi phi guesses out
@@ -71,8 +78,8 @@ def algorithmic_bytes(kernel: str, p: dict) -> float:
         "sor": 0.5 * 8 * br,
         # G rhoN psi phi in
         "total": 4 * br,
-        # rhoN, normal, psi, rhoR rhoB j in; u, F out
-        "force": (4 + 2 * D + 2 * D) * br,
+        # rhoN, normal, psi, rhoR rhoB j in; u, F, qf out
+        "force": (4 + 2 * D) * br + (2 * D + qf) * br,
     }
     return float(table.get(kernel, 0.0))
 
@@ -183,6 +190,47 @@ def pmc_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
     return "\n".join(lines)
 
 
+def trace_summary(stats_csv):
+    """Per-kernel table of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
+    import csv
+
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"{'kernel':60s} {'calls':>7s} {'avg us':>10s} {'min us':>10s} {'max us':>10s} {'total %':>8s}"]
+    for r in rows:
+        name = r["Name"].replace("void lbfd::", "").split("(")[0]
+        lines.append(f"{name[:60]:60s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} "
+                     f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):8.2f}")
+    return "\n".join(lines)
+
+
+def write_traffic(kernel, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out_path):
+    """HBM bytes per launch of one kernel class (scaled FETCH_SIZE + WRITE_SIZE),
+    stored with the hash of the kernel sources they were measured on."""
+    import collections
+
+    def mean_kib(path):
+        acc = collections.defaultdict(list)
+        for name, v, _ in _pmc_rows(path):
+            acc[name].append(v)
+        sel = [sum(v) / len(v) for k, v in acc.items() if f"k_{kernel}<" in k]
+        return sel[0] if sel else None
+
+    def copy_kib(path):
+        vals = [v for name, v, _ in _pmc_rows(path) if "copy" in name.lower()]
+        return max(vals) if vals else None
+
+    nbytes = 1024 * (1 << 20)
+    sf = nbytes / (copy_kib(copy_fetch_csv) * 1024)
+    sw = nbytes / (copy_kib(copy_write_csv) * 1024)
+    fk, wk = mean_kib(fetch_csv), mean_kib(write_csv)
+    rec = dict(kernel=kernel, source_hash=kernel_source_hash(), fetch_kib=fk, write_kib=wk,
+               fetch_scale=round(sf, 4), write_scale=round(sw, 4),
+               bytes_per_launch=round((fk * sf + wk * sw) * 1024))
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
 def sweep_budget(p, q, warmup, margin=2):
     """SOR sweeps to launch per step: the most any warm-up step needed, plus a
     margin. Every step still checks its own convergence on the device; a step
@@ -191,10 +239,14 @@ def sweep_budget(p, q, warmup, margin=2):
 
     s = lbfd.Solver(p).init_fields(q)
     used = 0
-    for _ in range(max(warmup, 1)):
+    n = max(warmup, 1)
+    for i in range(n):
         s.step(1)
         ob = s.observables()
-        used = max(used, *ob["sor_sweeps"])
+        # the first two steps (Euler step, no extrapolated guess yet) are special;
+        # the timed steps come after the warm-up
+        if i >= 2 or n <= 3:
+            used = max(used, *ob["sor_sweeps"])
     s.close()
     return min(used + margin, p["sor_max_sweeps"])
 
@@ -217,9 +269,20 @@ def main():
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE counter CSVs per kernel (scaled by the "
                          "copy calibration run) and exit")
+    ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV",
+                    help="print the per-kernel table of a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--write-traffic", nargs=6,
+                    metavar=("KERNEL", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "OUT_JSON"),
+                    help="store the measured HBM bytes per launch of one kernel class and exit")
     args = ap.parse_args()
     if args.pmc_summary:
         print(pmc_summary(*args.pmc_summary))
+        return
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary))
+        return
+    if args.write_traffic:
+        print(json.dumps(write_traffic(*args.write_traffic)))
         return
     if args.copy_calibration:
         import torch

@@ -25,8 +25,11 @@ def build(verbose: bool = False) -> str:
     """Compile the HIP sources for gfx950 into paper_2311_15242_amd/liblbfd.so."""
     cmd = [hipcc(), "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
            "-Wno-unused-result", "-Wno-unused-value",
-           # no packed-FP32 instructions are generated (see the package notes)
+           # no packed-FP32 (v_pk_*_f32) instructions are generated
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # FP32 division and square root use the hardware reciprocal and square
+           # root (a few ulp) instead of the correctly rounded sequences; FP64 is unaffected
+           "-fno-hip-fp32-correctly-rounded-divide-sqrt",
            "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
            "-o", LIB + ".tmp"] + SOURCES
     if verbose:

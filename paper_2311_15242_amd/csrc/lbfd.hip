@@ -32,6 +32,7 @@ namespace lbfd {
 
 constexpr int BX = 64, BY = 4;          // one wavefront spans 64 consecutive x
 constexpr int NRED = 19;                 // observable partial sums per block
+constexpr int TOTAL_BLOCKS = 1024;       // fixed grid of the total-surfactant sum (deterministic order)
 
 struct InitDev {
     int n;
@@ -112,9 +113,10 @@ template <int LAT, class R> __device__ __forceinline__ void meq_sum(const KP<R> 
             meq[9] += rk * uy * uz; meq[10] += pc * uy; meq[11] += pc * ux; meq[12] += pc * uz;
             meq[13] += pc * ux; meq[14] += pc * uz; meq[15] += pc * uy;
             const R b = R(1) - al - u2;
-            meq[16] += rk * (b + R(2) * (ux * ux + uy * uy)) / R(6);
-            meq[17] += rk * (b + R(2) * (ux * ux + uz * uz)) / R(6);
-            meq[18] += rk * (b + R(2) * (uy * uy + uz * uz)) / R(6);
+            const R r6 = rk * R(1.0 / 6.0);
+            meq[16] += r6 * (b + R(2) * (ux * ux + uy * uy));
+            meq[17] += r6 * (b + R(2) * (ux * ux + uz * uz));
+            meq[18] += r6 * (b + R(2) * (uy * uy + uz * uz));
         }
     }
 }
@@ -283,16 +285,17 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_force(KP<ty
     const R s = (R)k.fld.sc->scale;
     const R *psiA = k.fld.psi[k.pc];
     const Nbhd nb = make_nbhd(k, x, y, z);
-    R g[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, nv[3] = {0, 0, 0}, kappa = 0, G2 = 0;
+    // grad rhoN = -n sqrt(|grad rhoN|^2 + eps_n^2), from the geometry kernel's n and |grad rhoN|
+    const R G = k.fld.G[k.lev][n];
+    const R den = sqrt(G * G + k.eps_n * k.eps_n);
+    R g[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, nv[3] = {0, 0, 0}, kappa = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        g[a] = lat_deriv<LAT, R>(nb, mac + 2 * N, n, R(1), a, -1);
-        G2 += g[a] * g[a];
         kappa -= lat_deriv<LAT, R>(nb, k.fld.nrm + a * N, n, R(1), a, a);
         gp[a] = lat_deriv<LAT, R>(nb, psiA, n, s, a, -1);
         nv[a] = k.fld.nrm[a * N + n];
+        g[a] = -nv[a] * den;
     }
-    const R G = sqrt(G2);
     const R psi = s * psiA[n];
     R Fs[3] = {0, 0, 0};
     if (k.E0 == R(0)) {
@@ -310,11 +313,11 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_force(KP<ty
 #pragma unroll
         for (int a = 0; a < D; ++a) Fs[a] = R(-0.5) * k.sigma_min * kappa * g[a];
     }
-    const R rho = mac[n] + mac[N + n];
+    const R rho = mac[n] + mac[N + n], irho = R(1) / rho;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         R Fa = Fs[a] + (rho - k.rhoB0) * k.grav[a];
-        const R ua = (mac[(3 + a) * N + n] + R(0.5) * Fa) / rho;
+        const R ua = (mac[(3 + a) * N + n] + R(0.5) * Fa) * irho;
         k.fld.F[a * N + n] = Fa;
         k.fld.u[a * N + n] = ua;
         if (k.qon) k.fld.qf[a * N + n] = (k.qcoef[0] * mac[n] + k.qcoef[1] * mac[N + n]) * ua;
@@ -339,25 +342,24 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
     const S *fin = (const S *)k.fld.f[k.fc];
     S *fout = (S *)k.fld.f[1 - k.fc];
     const R *mac = k.fld.mac[k.lev];
-    R *dnew = k.fld.desc[k.lev];
+    V4<R> *dsc = k.fld.desc;
 
     const Nbhd nb = make_nbhd(k, x, y, z);
     const R rR = mac[n], rB = mac[N + n], rN = mac[2 * N + n];
-    const R rho = rR + rB;
-    R u[3] = {0, 0, 0}, F[3] = {0, 0, 0}, g[3] = {0, 0, 0}, G2 = 0;
+    const R rho = rR + rB, irho = R(1) / rho;
+    R u[3] = {0, 0, 0}, F[3] = {0, 0, 0}, nv[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         u[d] = k.fld.u[d * N + n];
         F[d] = k.fld.F[d * N + n];
-        g[d] = lat_deriv<LAT, R>(nb, mac + 2 * N, n, R(1), d, -1);
-        G2 += g[d] * g[d];
+        nv[d] = k.fld.nrm[d * N + n];
     }
     // moments m = M f of the node
     R m[Q];
     if constexpr (P::DEV) {
         R uj[3] = {0, 0, 0};
 #pragma unroll
-        for (int d = 0; d < D; ++d) uj[d] = u[d] - R(0.5) * F[d] / rho;
+        for (int d = 0; d < D; ++d) uj[d] = u[d] - R(0.5) * F[d] * irho;
         load_moments<LAT, P>(k, fin, n, rR, rB, uj, m);
     } else {
 #pragma unroll
@@ -371,9 +373,11 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
         }
     }
     // relaxation rate of the viscous moments (eq 43 and the mu-s_v relation)
-    const R inv_mu = (R(1) + rN) / (R(2) * k.muR0) + (R(1) - rN) / (R(2) * k.muB0);
+    // 1/mu = (1 + rhoN)/(2 mu^R) + (1 - rhoN)/(2 mu^B); s_v = 1/(mu/p + 1/2) = p/mu / (1 + p/(2 mu))
+    const R inv_mu = (R(1) + rN) * k.ihmu[0] + (R(1) - rN) * k.ihmu[1];
     const R pk = rR * k.cs2[0] + rB * k.cs2[1];
-    const R sv = R(1) / ((R(1) / inv_mu) / pk + R(0.5));
+    const R pm = pk * inv_mu;
+    const R sv = pm / (R(1) + R(0.5) * pm);
 
     // equilibria summed over colours (eq 37 / eq 40)
     R meq[Q], C[Q];
@@ -397,20 +401,17 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
             C[6] = Qs[1] - Qs[2];
         }
     }
-    // forcing term (eq 4): the velocity-space integrand projected with M
+    // forcing term (eq 4) projected with M. F_i = w_i [3 (e_i - u).F + 9 (e_i.u)(e_i.F)]
+    // is a second-order polynomial in e_i times w_i, so its moments are combinations
+    // of the lattice tables M w, M w e and M w e e
     R Fm[Q];
+    {
+        const R uF = ux * F[0] + uy * F[1] + uz * F[2];
+        const R F3[3] = {R(3) * F[0], R(3) * F[1], R(3) * F[2]};
+        const R uFp[6] = {R(9) * ux * F[0], R(9) * uy * F[1], R(9) * uz * F[2], R(9) * (ux * F[1] + uy * F[0]),
+                          R(9) * (ux * F[2] + uz * F[0]), R(9) * (uy * F[2] + uz * F[1])};
 #pragma unroll
-    for (int r = 0; r < Q; ++r) Fm[r] = 0;
-    const R uF = ux * F[0] + uy * F[1] + uz * F[2];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        R eF = 0, eu = 0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) { eF += R(L::E[i][d]) * F[d]; eu += R(L::E[i][d]) * u[d]; }
-        const R Fi = R(L::W[i]) * (R(3) * (eF - uF) + R(9) * eu * eF);
-#pragma unroll
-        for (int r = 0; r < Q; ++r)
-            if (L::M[r][i] != 0) Fm[r] += R(L::M[r][i]) * Fi;
+        for (int r = 0; r < Q; ++r) Fm[r] = wpoly<LAT, R>(r, R(-3) * uF, F3, uFp);
     }
     // post-collision moments m* = m - S (m - meq) + (I - S/2)(C + F_m)  (eqs 1-3)
 #pragma unroll
@@ -423,49 +424,59 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
         }
         m[r] = m[r] - sr * (m[r] - meq[r]) + (R(1) - R(0.5) * sr) * (C[r] + Fm[r]);
     }
-    // recolouring descriptor (eqs 11-12): colour share and c = beta rho^R rho^B / rho g/|g|
-    const R a = rR / rho;
-    const R Gm = sqrt(G2);
-    const R cf = Gm > R(0) ? k.beta * (rR * rB / rho) / Gm : R(0);
-    dnew[n] = a;
-#pragma unroll
-    for (int d = 0; d < D; ++d) dnew[(1 + d) * N + n] = cf * g[d];
+    // recolouring descriptor (eqs 11-12): colour share and c = beta rho^R rho^B / rho g/|g|,
+    // g/|g| = -n sqrt(|g|^2 + eps_n^2) / |g| with the geometry kernel's n and |g|
+    const R a = rR * irho;
+    const R Gm = k.fld.G[k.lev][n];
+    const R cf = Gm > R(0) ? -k.beta * (a * rB) * (sqrt(Gm * Gm + k.eps_n * k.eps_n) / Gm) : R(0);
+    dsc[n] = V4<R>{a, cf * nv[0], cf * nv[1], cf * nv[2]};
     R us[3] = {0, 0, 0};
     if constexpr (P::DEV) {
-        dnew[(1 + D) * N + n] = rho;
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            us[d] = u[d] + R(0.5) * F[d] / rho;
-            dnew[(2 + D + d) * N + n] = us[d];
-        }
+        for (int d = 0; d < D; ++d) us[d] = u[d] + R(0.5) * F[d] * irho;
+        dsc[N + n] = V4<R>{rho, us[0], us[1], us[2]};
+        // deviation modes store f_dag_i - ref_i with ref_i = rho [a phiR_i + (1 - a) phiB_i
+        // + w_i (3 e.u* + 4.5 (e.u*)^2 - 1.5 u*^2)]: subtract the moments of ref from m*
+        // (rest part: the colour equilibria at u = 0; motion part: the weighted tables)
+        R mr[Q];
+        const R zero[3] = {0, 0, 0};
+        meq_sum<LAT, R>(k, rho * a, rho - rho * a, zero, mr);
+        const R uu = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
+        const R c1[3] = {R(3) * rho * us[0], R(3) * rho * us[1], R(3) * rho * us[2]};
+        const R h = R(4.5) * rho;
+        const R c2[6] = {h * us[0] * us[0], h * us[1] * us[1], h * us[2] * us[2], R(2) * h * us[0] * us[1],
+                         R(2) * h * us[0] * us[2], R(2) * h * us[1] * us[2]};
+#pragma unroll
+        for (int r = 0; r < Q; ++r) m[r] -= mr[r] + wpoly<LAT, R>(r, R(-1.5) * rho * uu, c1, c2);
     }
     // propagation with periodic wrap or half-way bounce-back
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        // f_dag_i = (M^-1 m*)_i
+        // f_dag_i = (M^-1 m*)_i (deviation modes: minus ref_i)
         R v = 0;
 #pragma unroll
         for (int r = 0; r < Q; ++r)
             if (L::MINV[i][r] != 0.0) v += R(L::MINV[i][r]) * m[r];
         const int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
-        int wall = -1;
-        if (nb_wall_axis(nb, 0, ex)) wall = ex > 0 ? 1 : 0;
-        else if (nb_wall_axis(nb, 1, ey)) wall = ey > 0 ? 3 : 2;
-        else if (nb_wall_axis(nb, 2, ez)) wall = ez > 0 ? 5 : 4;
-        long long dest;
-        int j;
-        if (wall >= 0) {
-            R eu = R(L::E[i][0]) * k.wall_u[wall][0] + R(L::E[i][1]) * k.wall_u[wall][1] +
-                   R(L::E[i][2]) * k.wall_u[wall][2];
-            v -= R(2) * R(L::W[i]) * rho * eu * R(3);
-            j = L::OPP[i];
-            dest = n;
-        } else {
-            j = i;
-            dest = n + nb_delta(nb, ex, ey, ez);
-        }
+        // the first wall axis the population crosses reflects it, with Ladd's moving-wall
+        // term -6 w_i rho (e_i . u_w) (a per-wall table); every index is a compile-time constant
+        const bool bx = ex != 0 && nb_wall_axis(nb, 0, ex);
+        const bool by = !bx && ey != 0 && nb_wall_axis(nb, 1, ey);
+        const bool bz = !bx && !by && ez != 0 && nb_wall_axis(nb, 2, ez);
+        const bool bo = bx || by || bz;
+        R wt = R(0);
+        if (ex != 0) wt = bx ? k.wterm[ex > 0 ? 1 : 0][i] : wt;
+        if (ey != 0) wt = by ? k.wterm[ey > 0 ? 3 : 2][i] : wt;
+        if (ez != 0) wt = bz ? k.wterm[ez > 0 ? 5 : 4][i] : wt;
+        v -= rho * wt;
+        const int j = bo ? L::OPP[i] : i;
+        const long long dest = bo ? n : n + nb_delta(nb, ex, ey, ez);
         if constexpr (P::DEV) {
-            v -= reference<LAT, R>(k, j, rho, a, us);
+            // a reflected population is stored in direction j = opp(i): ref_i - ref_j = 6 rho w_i e_i.u*
+            if (i != 0) {
+                const R eus = R(ex) * us[0] + R(ey) * us[1] + R(ez) * us[2];
+                v += bo ? R(6 * L::W[i]) * rho * eus : R(0);
+            }
             fout[(long long)j * N + dest] = from_real<S>(v);
         } else {
             fout[(long long)j * N + dest] = v;
@@ -489,7 +500,7 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
     const int x = nd.x, y = nd.y, z = nd.z;
     const long long N = k.N, n = lin(k, x, y, z);
     const S *fin = (const S *)k.fld.f[1 - k.fc];
-    const R *ds = k.fld.desc[k.lev];
+    const V4<R> *ds = k.fld.desc;
     const Nbhd nb = make_nbhd(k, x, y, z);
     R rR = 0, rB = 0, j[3] = {0, 0, 0};
     R m[P::DEV ? Q : 1];
@@ -501,11 +512,19 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
     for (int q = 0; q < Q; ++q) {
         bool bo;
         const long long src = source_of<LAT>(nb, n, q, bo);
-        const int pre = bo ? L::OPP[q] : q;
-        R fq = load_pop<LAT, P>(k, fin, n, q, src, ds);
-        R as = ds[src], ec = 0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) ec += R(L::E[pre][d]) * ds[(1 + d) * N + src];
+        const R sgn = bo ? R(-1) : R(1);   // a reflected arrival left its source along -e_q
+        const V4<R> A = ds[src];
+        R fq = to_real(fin[(long long)q * N + n]);
+        if constexpr (P::DEV) {
+            // decode with the reference of the node the population left
+            const V4<R> B = ds[N + src];
+            const R us[3] = {B.y, B.z, B.w};
+            fq += reference<LAT, R>(k, q, R(1), B.x, A.x, us);
+        }
+        const R as = A.x;
+        R ec = R(L::E[q][0]) * A.y + R(L::E[q][1]) * A.z;
+        if constexpr (D == 3) ec += R(L::E[q][2]) * A.w;
+        ec *= sgn;
         R wgt = k.recolour_literal ? R(L::W[q]) : as * k.rest[0][q] + (R(1) - as) * k.rest[1][q];
         R r = wgt * ec;
         rR += as * fq + r;
@@ -519,7 +538,7 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
         }
     }
     R *mac = k.fld.mac[1 - k.lev];
-    R rr = rR / k.rhoR0, bb = rB / k.rhoB0;
+    R rr = rR * k.irho0[0], bb = rB * k.irho0[1];
     mac[n] = rR;
     mac[N + n] = rB;
     mac[2 * N + n] = (rr - bb) / (rr + bb);
@@ -528,9 +547,9 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
     if constexpr (P::DEV) {
         // in place: the node's own slots, after all of its loads
         R uj[3] = {0, 0, 0};
-        const R rho = rR + rB;
+        const R irho = R(1) / (rR + rB);
 #pragma unroll
-        for (int d = 0; d < D; ++d) uj[d] = j[d] / rho;
+        for (int d = 0; d < D; ++d) uj[d] = j[d] * irho;
         store_moments<LAT, P>(k, (S *)k.fld.f[1 - k.fc], n, rR, rB, uj, m);
     }
 }
@@ -620,8 +639,16 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typen
     k.fld.rhsF[n] = Xn * phi + R(0.5) * k.Db * (swcF - swF * phi) + eB;
     k.fld.Sp[n] = Sn;
     k.fld.Bp[n] = Bn;
-    k.fld.psi[1 - k.pc][n] = psi;
-    k.fld.phi[1 - k.pc][n] = phi;
+    // initial guess of the implicit solve: linear extrapolation from the two
+    // previous levels where both exist (the other buffer holds level n-1)
+    R psig = psi, phig = phi;
+    if (k.extrap) {
+        const R sp = (R)k.fld.sc->scale_prev;
+        psig = R(2) * psi - sp * k.fld.psi[1 - k.pc][n];
+        phig = R(2) * phi - sp * k.fld.phi[1 - k.pc][n];
+    }
+    k.fld.psi[1 - k.pc][n] = psig;
+    k.fld.phi[1 - k.pc][n] = phig;
 }
 
 // One colour half of a red-black SOR sweep of both implicit systems
@@ -655,7 +682,9 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
     const int tx = (hx + 63) >> 6, ty = (ny + 3) >> 2;
     const int ntiles = tx * ty * nz;
     const int li = threadIdx.x & 63, ly = threadIdx.x >> 6;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // the grid is a multiple of 8 or covers every tile once, so raw index mod 8 is the XCD
+    for (int raw = blockIdx.x; raw < ntiles; raw += gridDim.x) {
+        const int tile = xcd_tile(raw, ntiles);
         const int bx = tile % tx, rest = tile / tx;
         const int by = rest % ty, z = rest / ty;
         const int y = by * 4 + ly;
@@ -765,22 +794,16 @@ template <int LAT, class P>
 __global__ __launch_bounds__(256) void k_total_part(KP<typename P::R> k, int level, int buf, double mult)
 {
     using R = typename P::R;
-    Node nd = node_id(k);
+    const long long N = k.N;
     double v[1] = {0.0};
-    if (nd.ok) {
-        const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
         double G = (double)(k.fld.G[level][n] + k.fd_eps);
         double X = (double)((R(1) - k.fld.mac[level][2 * N + n]) + k.fd_eps);
         double ps = mult * (double)k.fld.psi[buf][n], ph = mult * (double)k.fld.phi[buf][n];
-        v[0] = G * ps + X * ph;
+        v[0] += G * ps + X * ph;
     }
-    const long long b = blockIdx.x + gridDim.x * ((long long)blockIdx.y + gridDim.y * (long long)blockIdx.z);
-    block_sum_store<1>(v, k.fld.part + b);
+    block_sum_store<1>(v, k.fld.part + blockIdx.x);
 }
-
-// Final sum of the block partials in a fixed order. mode 0: record the
-// rescaling target; mode 1: record the total after a solve and set the factor
-// that restores the target (Sec 2.2), flagging a non-finite total.
 template <class R> __global__ void k_total_final(KP<R> k, long long nblocks, int mode)
 {
     __shared__ double sh[256];
@@ -801,7 +824,9 @@ template <class R> __global__ void k_total_final(KP<R> k, long long nblocks, int
             sc->Mlast = M;
             sc->drift_pre = 0.0;
             sc->scale = 1.0;
+            sc->scale_prev = 1.0;
         } else {
+            sc->scale_prev = sc->scale;
             sc->Mlast = M;
             sc->drift_pre = sc->M0 != 0.0 ? (M - sc->M0) / sc->M0 : 0.0;
             sc->scale = (k.rescale && sc->M0 != 0.0 && M != 0.0) ? sc->M0 / M : 1.0;
@@ -867,7 +892,7 @@ __global__ __launch_bounds__(256) void k_obs_part(KP<typename P::R> k, int pass,
         }
         __syncthreads();
     }
-    const long long b = blockIdx.x + gridDim.x * ((long long)blockIdx.y + gridDim.y * (long long)blockIdx.z);
+    const long long b = blockIdx.x;
     if (t == 0)
         for (int i = 0; i < NRED; ++i) k.fld.part[b * NRED + i] = sh[i][0];
 }
@@ -948,6 +973,8 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_export(KP<t
 
 using namespace lbfd;
 
+static_assert(sizeof(KP<double>) <= 3072, "kernel parameter block must stay within the kernel-argument limit");
+
 namespace {
 
 enum KernelClass { KC_COLLIDE = 0, KC_MACRO, KC_GEOM, KC_FD, KC_SOR, KC_TOTAL, KC_FORCE, KC_OTHER, KC_COUNT };
@@ -971,6 +998,7 @@ struct lbfd_handle {
     dim3 grid, block;
     long long nblocks;
     int sweeps_launch;
+    long long fd_hist;  // FD steps since the state was set (extrapolated guess needs one)
     int sor_blocks;     // persistent grid of the SOR sweeps
     bool prof;
     unsigned prof_mask;  // kernel classes timed when profiling (bit per class)
@@ -988,7 +1016,7 @@ size_t pop_bytes(int prec) { return prec == LBFD_FP64 ? 8 : prec == LBFD_FP32 ? 
 size_t real_bytes(int prec) { return prec == LBFD_FP64 ? 8 : 4; }
 
 struct Layout {
-    size_t f[2], mac[2], desc[2], G[2], nrm, u, F, qf, psi[2], phi[2], Sp, Bp, rhsP, rhsF, part, sc, obs, total;
+    size_t f[2], mac[2], desc, G[2], nrm, u, F, qf, psi[2], phi[2], Sp, Bp, rhsP, rhsF, part, sc, obs, total;
 };
 
 Layout layout(const lbfd_params *p)
@@ -997,13 +1025,13 @@ Layout layout(const lbfd_params *p)
     const int Q = p->lattice == LBFD_D3Q19 ? 19 : 9, D = p->lattice == LBFD_D3Q19 ? 3 : 2;
     const long long N = (long long)p->nx * p->ny * p->nz;
     const size_t sp = pop_bytes(p->precision), sr = real_bytes(p->precision);
-    const int ndesc = 1 + D + (is_dev(p->precision) ? 1 + D : 0);
+    const int ndesc = is_dev(p->precision) ? 8 : 4;  // one or two packed 4-vectors per node
     const long long nblocks = (long long)((p->nx + BX - 1) / BX) * ((p->ny + BY - 1) / BY) * p->nz;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
     for (int b = 0; b < 2; ++b) L.f[b] = take(sp * Q * N);
     for (int b = 0; b < 2; ++b) L.mac[b] = take(sr * (3 + D) * N);
-    for (int b = 0; b < 2; ++b) L.desc[b] = take(sr * ndesc * N);
+    L.desc = take(sr * ndesc * N);
     for (int b = 0; b < 2; ++b) L.G[b] = take(sr * N);
     L.nrm = take(sr * D * N);
     L.u = take(sr * D * N);
@@ -1015,7 +1043,8 @@ Layout layout(const lbfd_params *p)
     L.Bp = take(sr * N);
     L.rhsP = take(sr * N);
     L.rhsF = take(sr * N);
-    L.part = take(sizeof(double) * NRED * (size_t)nblocks);
+    const size_t npart = (size_t)NRED * (size_t)nblocks;
+    L.part = take(sizeof(double) * (npart > (size_t)TOTAL_BLOCKS ? npart : (size_t)TOTAL_BLOCKS));
     L.sc = take(sizeof(DevScalars));
     L.obs = take(sizeof(double) * NRED);
     L.total = o;
@@ -1065,6 +1094,25 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
 {
     const bool three = p->lattice == LBFD_D3Q19;
     k.nx = p->nx; k.ny = p->ny; k.nz = p->nz;
+    {
+        // moving-wall term of the half-way bounce-back per wall and direction: 6 w_i (e_i . u_w)
+        const int Q = three ? 19 : 9;
+        for (int w = 0; w < 6; ++w)
+            for (int i = 0; i < QMAX; ++i) {
+                double v = 0.0;
+                if (i < Q) {
+                    const int *e = three ? D3Q19Tables::E[i] : D2Q9Tables::E[i];
+                    const double wi = three ? D3Q19Tables::W[i] : D2Q9Tables::W[i];
+                    v = 6.0 * wi * (e[0] * p->wall_u[w][0] + e[1] * p->wall_u[w][1] + e[2] * p->wall_u[w][2]);
+                }
+                k.wterm[w][i] = (R)v;
+            }
+    }
+    k.ihmu[0] = (R)(0.5 / p->muR0);
+    k.ihmu[1] = (R)(0.5 / p->muB0);
+    k.irho0[0] = (R)(1.0 / p->rhoR0);
+    k.irho0[1] = (R)(1.0 / p->rhoB0);
+    k.gx = (p->nx + BX - 1) / BX; k.gy = (p->ny + BY - 1) / BY;
     k.N = (long long)p->nx * p->ny * p->nz;
     for (int a = 0; a < 3; ++a) k.bc[a] = p->bc[a];
     for (int w = 0; w < 6; ++w)
@@ -1107,11 +1155,11 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
     for (int b = 0; b < 2; ++b) {
         F.f[b] = ws + Lo.f[b];
         F.mac[b] = (R *)(ws + Lo.mac[b]);
-        F.desc[b] = (R *)(ws + Lo.desc[b]);
         F.G[b] = (R *)(ws + Lo.G[b]);
         F.psi[b] = (R *)(ws + Lo.psi[b]);
         F.phi[b] = (R *)(ws + Lo.phi[b]);
     }
+    F.desc = (V4<R> *)(ws + Lo.desc);
     F.nrm = (R *)(ws + Lo.nrm);
     F.u = (R *)(ws + Lo.u);
     F.F = (R *)(ws + Lo.F);
@@ -1180,13 +1228,14 @@ template <int LAT, class P> struct Impl {
         k.fc = h->fc;
         k.pc = h->pc;
         k.step = h->step;
+        k.extrap = h->fd_hist >= 1 ? 1 : 0;
     }
 
     static void totals(lbfd_handle *h, int level, int buf, double mult, int mode)
     {
         KP<R> &k = kp(h);
-        LAUNCH(KC_TOTAL, (k_total_part<LAT, P>), h->grid, h->block, k, level, buf, mult);
-        LAUNCH(KC_TOTAL, (k_total_final<R>), dim3(1), dim3(256), k, h->nblocks, mode);
+        LAUNCH(KC_TOTAL, (k_total_part<LAT, P>), dim3(TOTAL_BLOCKS), dim3(256), k, level, buf, mult);
+        LAUNCH(KC_TOTAL, (k_total_final<R>), dim3(1), dim3(256), k, (long long)TOTAL_BLOCKS, mode);
     }
 
     static void derived(lbfd_handle *h)
@@ -1200,6 +1249,7 @@ template <int LAT, class P> struct Impl {
 
     static int init(lbfd_handle *h, const InitDev &in)
     {
+        h->fd_hist = 0;
         h->step = 0;
         h->fc = 0;
         h->pc = 0;
@@ -1218,6 +1268,7 @@ template <int LAT, class P> struct Impl {
         DevScalars z;
         std::memset(&z, 0, sizeof(z));
         z.scale = 1.0;
+        z.scale_prev = 1.0;
         hipMemcpyAsync(kp(h).fld.sc, &z, sizeof(z), hipMemcpyHostToDevice, h->stream);
         hipStreamSynchronize(h->stream);
     }
@@ -1241,6 +1292,7 @@ template <int LAT, class P> struct Impl {
         h->step = step;
         h->fc = 0;
         h->pc = 0;
+        h->fd_hist = 0;
         clear_scalars(h);
         sync_levels(h);
         KP<R> &k = kp(h);
@@ -1250,6 +1302,7 @@ template <int LAT, class P> struct Impl {
         DevScalars z;
         std::memset(&z, 0, sizeof(z));
         z.scale = 1.0;
+        z.scale_prev = 1.0;
         z.M0 = M0;
         z.Mlast = M0;
         hipMemcpyAsync(k.fld.sc, &z, sizeof(z), hipMemcpyHostToDevice, h->stream);
@@ -1275,6 +1328,7 @@ template <int LAT, class P> struct Impl {
                 LAUNCH(KC_OTHER, (k_sor_done<R>), dim3(1), dim3(1), k, h->sweeps_launch);
                 totals(h, 1 - k.lev, 1 - k.pc, 1.0, 1);
                 h->pc = 1 - h->pc;
+                h->fd_hist += 1;
             }
             h->fc = 1 - h->fc;
             h->step += 1;
@@ -1450,8 +1504,8 @@ int lbfd_create(const lbfd_params *p, void *d_workspace, size_t bytes, void *str
     h->fc = h->pc = 0;
     h->step = 0;
     h->block = dim3(BX, BY, 1);
-    h->grid = dim3((p->nx + BX - 1) / BX, (p->ny + BY - 1) / BY, p->nz);
-    h->nblocks = (long long)h->grid.x * h->grid.y * h->grid.z;
+    h->nblocks = (long long)((p->nx + BX - 1) / BX) * ((p->ny + BY - 1) / BY) * p->nz;
+    h->grid = dim3((unsigned)h->nblocks);
     h->sweeps_launch = p->sor_max_sweeps;
     {
         // tiles of one colour (64 x 4 nodes), capped at 8 workgroups of 256 per compute unit
@@ -1463,7 +1517,7 @@ int lbfd_create(const lbfd_params *p, void *d_workspace, size_t bytes, void *str
             if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
                 cus = prop.multiProcessorCount;
         }
-        long long cap = 8LL * cus;
+        long long cap = 8LL * cus;  // a multiple of 8 (XCD-aware tile order)
         h->sor_blocks = (int)(need < cap ? need : cap);
     }
     h->prof = false;

@@ -9,9 +9,10 @@
 //             of the node they left (reference), converted back to moments in
 //             place by the macro kernel
 //   mac[2]    rho^R, rho^B, rhoN, j_x, j_y(, j_z) of a time level (j = sum f e)
-//   desc[2]   per-node outflow descriptor written by the collision: colour share
-//             a = rho^R/rho and recolouring vector c (D); in deviation modes also
-//             rho and the post-collision velocity u* (D)
+//   desc      per-node outflow descriptor written by the collision, packed four
+//             reals per node so that the macro kernel gathers it with one vector
+//             load per source: colour share a = rho^R/rho and recolouring
+//             vector c; in deviation modes also rho and the velocity u*
 //   G[2]      |grad rhoN| of two time levels; nrm: interface normal (D)
 //   u, F      fluid velocity (eq 10) and total force (D each)
 //   qf        sum_k qcoef_k rho^k u_a (D), the field whose derivative is the
@@ -86,6 +87,7 @@ constexpr int MAX_SWEEPS = 256;
 // bookkeeping of the implicit solve and of error detection.
 struct DevScalars {
     double scale;                 // stored psi, phi are multiplied by this on read
+    double scale_prev;            // the factor of the other psi, phi buffer (previous time level)
     double M0;                    // total surfactant to restore
     double Mlast;                 // total after the last solve, before rescaling
     double drift_pre;             // (Mlast - M0) / M0
@@ -96,10 +98,13 @@ struct DevScalars {
     int32_t pad;
 };
 
+// Four reals read or written by one vector access (the packed descriptor).
+template <class R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
+
 template <class R> struct Fields {
     void *f[2];
     R *mac[2];      // planes: 0 rhoR, 1 rhoB, 2 rhoN, 3.. j
-    R *desc[2];     // planes: 0 a, 1.. c, then (deviation modes) rho, u*
+    V4<R> *desc;    // N x (a, c_x, c_y, c_z), then (deviation modes) N x (rho, u*_x, u*_y, u*_z)
     R *G[2];
     R *nrm;
     R *u;
@@ -114,11 +119,15 @@ template <class R> struct Fields {
 
 template <class R> struct KP {
     int nx, ny, nz;
+    int gx, gy;         // tiles along x and y of the node launches
     long long N;
     int bc[3];
     R wall_u[6][3];
+    R wterm[6][QMAX];   // 6 w_i (e_i . u_w) per wall (-x,+x,-y,+y,-z,+z) and direction
     R rhoR0, rhoB0;
+    R irho0[2];         // 1/rhoR0, 1/rhoB0
     R muR0, muB0;
+    R ihmu[2];          // 1/(2 muR0), 1/(2 muB0)
     R alpha[2];         // sound-speed parameters alpha^k of red, blue (App. A, eq 42)
     R cs2[2];           // (cs^k)^2 of red, blue
     R qcoef[2];         // prefactor of the correction Q_a per colour
@@ -136,6 +145,7 @@ template <class R> struct KP {
     R fd_eps;           // background support of the FD weights
     R upwind_eps;       // |u_a| band with upwind weights 1/2
     int rescale;
+    int extrap;         // a previous psi, phi level exists: extrapolate the solver's initial guess
     // time-level selectors set per launch by the host
     int lev;            // mac/G/desc level of the current time n (n & 1)
     int fc;             // f buffer holding f^n
@@ -148,12 +158,26 @@ template <class R> struct KP {
 
 struct Node { int x, y, z; bool ok; };
 
+// XCD-aware tile order. The hardware hands workgroup i of a launch to XCD
+// i mod 8, and each XCD has its own L2. Renumbering the tiles so that XCD x
+// processes one contiguous range of tile indices keeps the halo rows and
+// planes that neighbouring tiles share inside one L2. A bijection of [0, n).
+__device__ __forceinline__ int xcd_tile(int i, int n)
+{
+    const int q = n >> 3, r = n & 7, x = i & 7, l = i >> 3;
+    return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+// Node of this thread: a 1-D launch of gx * gy * nz tiles of blockDim.x by
+// blockDim.y nodes (x fastest), in XCD-aware order.
 template <class R> __device__ __forceinline__ Node node_id(const KP<R> &k)
 {
     Node n;
-    n.x = blockIdx.x * blockDim.x + threadIdx.x;
-    n.y = blockIdx.y * blockDim.y + threadIdx.y;
-    n.z = blockIdx.z;
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int bx = t % k.gx, r = t / k.gx;
+    n.x = bx * blockDim.x + threadIdx.x;
+    n.y = (r % k.gy) * blockDim.y + threadIdx.y;
+    n.z = r / k.gy;
     n.ok = n.x < k.nx && n.y < k.ny;
     return n;
 }
@@ -254,13 +278,17 @@ __device__ __forceinline__ R lat_deriv(const Nbhd &b, const R *chi, long long n,
 // Rest-plus-motion reference of a population leaving a node with density rho,
 // colour share a and velocity us: rho [a phiR_i + (1-a) phiB_i + w_i (3 e.u + 4.5 (e.u)^2 - 1.5 u^2)].
 // Deviation modes store f_i minus this, evaluated at the node the population left.
+// sgn = -1 evaluates it for the opposite direction of i (the rest weights and
+// lattice weights are symmetric under e -> -e), which keeps every table index
+// a compile-time constant.
 template <int LAT, class R>
-__device__ __forceinline__ R reference(const KP<R> &k, int i, R rho, R a, const R *us)
+__device__ __forceinline__ R reference(const KP<R> &k, int i, R sgn, R rho, R a, const R *us)
 {
     using L = Lat<LAT>;
     R eu = 0, uu = 0;
 #pragma unroll
     for (int d = 0; d < L::D; ++d) { eu += R(L::E[i][d]) * us[d]; uu += us[d] * us[d]; }
+    eu *= sgn;
     R rest = a * k.rest[0][i] + (R(1) - a) * k.rest[1][i];
     return rho * (rest + R(L::W[i]) * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu));
 }
@@ -277,24 +305,20 @@ __device__ __forceinline__ long long source_of(const Nbhd &b, long long n, int j
     return bounced ? n : n + nb_delta(b, ex, ey, ez);
 }
 
-// Load population j stored at node n (after propagation) as a real number,
-// decoding a deviation with the descriptor of the node it came from.
-template <int LAT, class P>
-__device__ __forceinline__ typename P::R load_pop(const KP<typename P::R> &k, const typename P::S *f, long long n,
-                                                  int j, long long src, const typename P::R *desc)
+// Moments of a second-order polynomial in e_i weighted by w_i:
+// sum_i M_ri w_i [c0 + sum_a c1_a e_ia + sum_p c2_p (e_i e_i)_p], pairs p = xx yy zz xy xz yz
+// (an off-diagonal coefficient multiplies e_ia e_ib once). Zero table entries fold away.
+template <int LAT, class R> __device__ __forceinline__ R wpoly(int r, R c0, const R *c1, const R *c2)
 {
-    using R = typename P::R;
-    R v = to_real(f[(long long)j * k.N + n]);
-    if constexpr (P::DEV) {
-        using L = Lat<LAT>;
-        const long long N = k.N;
-        R us[3] = {0, 0, 0};
-        R a = desc[src];
-        R rho = desc[(1 + L::D) * N + src];
+    using L = Lat<LAT>;
+    R v = 0;
+    if (L::MW[r] != 0.0) v += R(L::MW[r]) * c0;
 #pragma unroll
-        for (int d = 0; d < L::D; ++d) us[d] = desc[(2 + L::D + d) * N + src];
-        v += reference<LAT, R>(k, j, rho, a, us);
-    }
+    for (int a = 0; a < 3; ++a)
+        if (L::MWE[r][a] != 0.0) v += R(L::MWE[r][a]) * c1[a];
+#pragma unroll
+    for (int p = 0; p < 6; ++p)
+        if (L::MWEE[r][p] != 0.0) v += R(L::MWEE[r][p]) * c2[p];
     return v;
 }
 
