@@ -579,10 +579,14 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typen
     using R = typename P::R;
     using L = Lat<LAT>;
     constexpr int D = L::D;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
-        DevScalars *sc = k.fld.sc;
-        sc->rmax[0] = sc->rmax[1] = 0ull;
-        for (int s = 0; s < MAX_SWEEPS; ++s) sc->res[0][s] = sc->res[1][s] = 0ull;
+    if (blockIdx.x == 0) {
+        // clear the residual slots of the sweeps this step launches (and of the |rhs| maxima)
+        const int t = threadIdx.x + threadIdx.y * blockDim.x, nt = blockDim.x * blockDim.y;
+        const int per = (k.nsweeps + 1) * RSLOTS;
+        for (int i = t; i < 2 * per; i += nt) {
+            const int fi = i / per, r = i % per, sw = r / RSLOTS, slot = r % RSLOTS;
+            *res_slot(k.fld.sorres, fi, sw == k.nsweeps ? MAX_SWEEPS : sw, slot) = 0ull;
+        }
     }
     Node nd = node_id(k);
     if (!nd.ok) return;
@@ -663,11 +667,17 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
     using R = typename P::R;
     using L = Lat<LAT>;
     constexpr int D = L::D;
-    DevScalars *sc = k.fld.sc;
-    bool conv[2];
+    // convergence of the previous sweep: maxima over the residual slots, one per lane
+    bool conv[2] = {false, false};
+    if (sweep > 0) {
+        const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int fi = 0; fi < 2; ++fi)
-        conv[fi] = sweep > 0 && bits_to_double(sc->res[fi][sweep - 1]) <= (double)k.tol * bits_to_double(sc->rmax[fi]);
+        for (int fi = 0; fi < 2; ++fi) {
+            const double r = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, sweep - 1, lane)));
+            const double b = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, MAX_SWEEPS, lane)));
+            conv[fi] = r <= (double)k.tol * b;
+        }
+    }
     if (conv[0] && conv[1]) return;
     const long long N = k.N;
     const int nx = k.nx, ny = k.ny, nz = k.nz, hx = (nx + 1) >> 1;
@@ -732,7 +742,7 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
             phi[n] = (R(1) - om) * c0 + om * (rhs + off) / diag;
         }
     }
-    // block maxima, one atomic per block and quantity
+    // block maxima, one atomic per block and quantity, spread over RSLOTS cache lines
     __shared__ double red[4][4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double v[4] = {wave_max(rloc[0]), wave_max(rloc[1]), wave_max(bloc[0]), wave_max(bloc[1])};
@@ -748,23 +758,34 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
 #pragma unroll
         for (int fi = 0; fi < 2; ++fi) {
             if (conv[fi]) continue;
-            atomic_max_nonneg(&sc->res[fi][sweep], red[fi][0]);
-            if (sweep == 0) atomic_max_nonneg(&sc->rmax[fi], red[2 + fi][0]);
+            const int slot = blockIdx.x % RSLOTS;
+            atomic_max_nonneg(res_slot(k.fld.sorres, fi, sweep, slot), red[fi][0]);
+            if (sweep == 0) atomic_max_nonneg(res_slot(k.fld.sorres, fi, MAX_SWEEPS, slot), red[2 + fi][0]);
         }
     }
 }
 
 // Sweep counts of the last solve; LBFD_ESOR when a system never met its tolerance.
+// One wavefront: lane l reads residual slot l.
 template <class R> __global__ void k_sor_done(KP<R> k, int nsw)
 {
     DevScalars *sc = k.fld.sc;
+    const int lane = threadIdx.x & 63;
     for (int fi = 0; fi < 2; ++fi) {
+        const double rm = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, MAX_SWEEPS, lane)));
+        const double lim = (double)k.tol * rm;
         int K = nsw;
-        for (int s = 1; s < nsw; ++s)
-            if (bits_to_double(sc->res[fi][s - 1]) <= (double)k.tol * bits_to_double(sc->rmax[fi])) { K = s; break; }
-        sc->sweeps[fi] = K;
-        if (K == nsw && !(bits_to_double(sc->res[fi][nsw - 1]) <= (double)k.tol * bits_to_double(sc->rmax[fi])))
-            if (sc->status == 0) sc->status = LBFD_ESOR;
+        double prev = 0.0;
+        for (int s = 0; s < nsw; ++s) {
+            const double r = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, s, lane)));
+            if (s >= 1 && K == nsw && prev <= lim) K = s;
+            prev = r;
+        }
+        if (lane == 0) {
+            sc->rmax[fi] = (unsigned long long)__double_as_longlong(rm);
+            sc->sweeps[fi] = K;
+            if (K == nsw && !(prev <= lim) && sc->status == 0) sc->status = LBFD_ESOR;
+        }
     }
 }
 
@@ -1016,7 +1037,7 @@ size_t pop_bytes(int prec) { return prec == LBFD_FP64 ? 8 : prec == LBFD_FP32 ? 
 size_t real_bytes(int prec) { return prec == LBFD_FP64 ? 8 : 4; }
 
 struct Layout {
-    size_t f[2], mac[2], desc, G[2], nrm, u, F, qf, psi[2], phi[2], Sp, Bp, rhsP, rhsF, part, sc, obs, total;
+    size_t f[2], mac[2], desc, G[2], nrm, u, F, qf, sorres, psi[2], phi[2], Sp, Bp, rhsP, rhsF, part, sc, obs, total;
 };
 
 Layout layout(const lbfd_params *p)
@@ -1037,6 +1058,7 @@ Layout layout(const lbfd_params *p)
     L.u = take(sr * D * N);
     L.F = take(sr * D * N);
     L.qf = take(sr * D * N);
+    L.sorres = take(sizeof(unsigned long long) * 2 * (MAX_SWEEPS + 1) * RSLOTS * RSTRIDE);
     for (int b = 0; b < 2; ++b) L.psi[b] = take(sr * N);
     for (int b = 0; b < 2; ++b) L.phi[b] = take(sr * N);
     L.Sp = take(sr * N);
@@ -1164,6 +1186,7 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
     F.u = (R *)(ws + Lo.u);
     F.F = (R *)(ws + Lo.F);
     F.qf = (R *)(ws + Lo.qf);
+    F.sorres = (unsigned long long *)(ws + Lo.sorres);
     F.Sp = (R *)(ws + Lo.Sp);
     F.Bp = (R *)(ws + Lo.Bp);
     F.rhsP = (R *)(ws + Lo.rhsP);
@@ -1229,6 +1252,7 @@ template <int LAT, class P> struct Impl {
         k.pc = h->pc;
         k.step = h->step;
         k.extrap = h->fd_hist >= 1 ? 1 : 0;
+        k.nsweeps = h->sweeps_launch;
     }
 
     static void totals(lbfd_handle *h, int level, int buf, double mult, int mode)
@@ -1325,7 +1349,7 @@ template <int LAT, class P> struct Impl {
                     LAUNCH(KC_SOR, (k_sor<LAT, P>), dim3(h->sor_blocks), dim3(256), k, 0, s);
                     LAUNCH(KC_SOR, (k_sor<LAT, P>), dim3(h->sor_blocks), dim3(256), k, 1, s);
                 }
-                LAUNCH(KC_OTHER, (k_sor_done<R>), dim3(1), dim3(1), k, h->sweeps_launch);
+                LAUNCH(KC_OTHER, (k_sor_done<R>), dim3(1), dim3(64), k, h->sweeps_launch);
                 totals(h, 1 - k.lev, 1 - k.pc, 1.0, 1);
                 h->pc = 1 - h->pc;
                 h->fd_hist += 1;

@@ -82,6 +82,8 @@ template <int LAT> __host__ __device__ constexpr int state_slot(int r)
 
 constexpr int QMAX = 19;
 constexpr int MAX_SWEEPS = 256;
+constexpr int RSLOTS = 64;    // residual maxima of a sweep are spread over this many cache lines
+constexpr int RSTRIDE = 16;   // 128 bytes between slots
 
 // Device-resident scalars: the rescaling factor, the rescaling target, and the
 // bookkeeping of the implicit solve and of error detection.
@@ -91,8 +93,7 @@ struct DevScalars {
     double M0;                    // total surfactant to restore
     double Mlast;                 // total after the last solve, before rescaling
     double drift_pre;             // (Mlast - M0) / M0
-    unsigned long long rmax[2];   // max |rhs| over active rows (bits of a non-negative double)
-    unsigned long long res[2][MAX_SWEEPS];  // max |residual| per sweep
+    unsigned long long rmax[2];   // max |rhs| of the last solve (bits of a non-negative double)
     int32_t sweeps[2];
     int32_t status;               // sticky lbfd_status of device-detected errors
     int32_t pad;
@@ -114,6 +115,7 @@ template <class R> struct Fields {
     R *phi[2];
     R *Sp, *Bp, *rhsP, *rhsF;
     double *part;   // reduction partials
+    unsigned long long *sorres;  // residual and |rhs| maxima per field, sweep and slot (bits of doubles)
     DevScalars *sc;
 };
 
@@ -146,6 +148,7 @@ template <class R> struct KP {
     R upwind_eps;       // |u_a| band with upwind weights 1/2
     int rescale;
     int extrap;         // a previous psi, phi level exists: extrapolate the solver's initial guess
+    int nsweeps;        // SOR sweeps launched per step
     // time-level selectors set per launch by the host
     int lev;            // mac/G/desc level of the current time n (n & 1)
     int fc;             // f buffer holding f^n
@@ -337,5 +340,11 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *addr, doub
 }
 
 __device__ __forceinline__ double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+// Slot of the residual (s < MAX_SWEEPS) or |rhs| (s = MAX_SWEEPS) maximum of field fi.
+__device__ __forceinline__ unsigned long long *res_slot(unsigned long long *base, int fi, int s, int slot)
+{
+    return base + ((size_t)(fi * (MAX_SWEEPS + 1) + s) * RSLOTS + slot) * RSTRIDE;
+}
 
 }  // namespace lbfd
