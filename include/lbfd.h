@@ -69,7 +69,7 @@ typedef enum { LBFD_PERIODIC = 0, LBFD_WALL = 1 } lbfd_bc;
 typedef struct {
     int32_t lattice;             /* lbfd_lattice */
     int32_t precision;           /* lbfd_precision */
-    int32_t nx, ny, nz;          /* each >= 4 (nz = 1 for D2Q9) */
+    int32_t nx, ny, nz;          /* each >= 4 (nz = 1 for D2Q9); nx*ny*nz < 2^28 (FP64: < 2^27) */
     int32_t bc[3];               /* per axis x,y,z: periodic, or half-way walls at -1/2 and n-1/2 */
     double wall_u[6][3];         /* wall velocities at -x,+x,-y,+y,-z,+z */
     double rhoR0, rhoB0;         /* pure-fluid densities, red (dispersed) and blue (eq 6) */

@@ -128,7 +128,7 @@ template <int LAT, class R> __device__ __forceinline__ void meq_sum(const KP<R> 
 // the others are stored in 16 bits, compacted to the first Q - 1 - D planes
 // of the population buffer.
 template <int LAT, class P>
-__device__ __forceinline__ void load_moments(const KP<typename P::R> &k, const typename P::S *fs, long long n,
+__device__ __forceinline__ void load_moments(const KP<typename P::R> &k, const typename P::S *fs, uint32_t n,
                                              typename P::R rR, typename P::R rB, const typename P::R *uj,
                                              typename P::R *m)
 {
@@ -137,11 +137,11 @@ __device__ __forceinline__ void load_moments(const KP<typename P::R> &k, const t
     meq_sum<LAT, R>(k, rR, rB, uj, m);
 #pragma unroll
     for (int r = 0; r < L::Q; ++r)
-        if (!conserved_row<LAT>(r)) m[r] += to_real(fs[(long long)state_slot<LAT>(r) * k.N + n]);
+        if (!conserved_row<LAT>(r)) m[r] += to_real(ld(fs + (long long)state_slot<LAT>(r) * k.N, n));
 }
 
 template <int LAT, class P>
-__device__ __forceinline__ void store_moments(const KP<typename P::R> &k, typename P::S *fs, long long n,
+__device__ __forceinline__ void store_moments(const KP<typename P::R> &k, typename P::S *fs, uint32_t n,
                                               typename P::R rR, typename P::R rB, const typename P::R *uj,
                                               const typename P::R *m)
 {
@@ -152,7 +152,7 @@ __device__ __forceinline__ void store_moments(const KP<typename P::R> &k, typena
     meq_sum<LAT, R>(k, rR, rB, uj, mref);
 #pragma unroll
     for (int r = 0; r < L::Q; ++r)
-        if (!conserved_row<LAT>(r)) fs[(long long)state_slot<LAT>(r) * k.N + n] = from_real<S>(m[r] - mref[r]);
+        if (!conserved_row<LAT>(r)) st(fs + (long long)state_slot<LAT>(r) * k.N, n, from_real<S>(m[r] - mref[r]));
 }
 
 // Store the populations f of node n at the start of a step: as populations,
@@ -252,7 +252,8 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_geom(KP<typ
     using L = Lat<LAT>;
     Node nd = node_id(k);
     if (!nd.ok) return;
-    const long long N = k.N, n = lin(k, nd.x, nd.y, nd.z);
+    const long long N = k.N;
+    const uint32_t n = node_index(k, nd);
     const R *rN = k.fld.mac[level] + 2 * N;
     const Nbhd nb = make_nbhd(k, nd.x, nd.y, nd.z);
     R g[3], G2 = 0;
@@ -261,10 +262,10 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_geom(KP<typ
         g[a] = lat_deriv<LAT, R>(nb, rN, n, R(1), a, -1);
         G2 += g[a] * g[a];
     }
-    k.fld.G[level][n] = sqrt(G2);
+    st(k.fld.G[level], n, sqrt(G2));
     R den = sqrt(G2 + k.eps_n * k.eps_n);
 #pragma unroll
-    for (int a = 0; a < L::D; ++a) k.fld.nrm[a * N + n] = den > R(0) ? -g[a] / den : R(0);
+    for (int a = 0; a < L::D; ++a) st(k.fld.nrm + a * N, n, den > R(0) ? -g[a] / den : R(0));
 }
 
 // ============================================================== forces
@@ -280,23 +281,24 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_force(KP<ty
     Node nd = node_id(k);
     if (!nd.ok) return;
     const int x = nd.x, y = nd.y, z = nd.z;
-    const long long N = k.N, n = lin(k, x, y, z);
+    const long long N = k.N;
+    const uint32_t n = node_index(k, nd);
     const R *mac = k.fld.mac[k.lev];
     const R s = (R)k.fld.sc->scale;
     const R *psiA = k.fld.psi[k.pc];
     const Nbhd nb = make_nbhd(k, x, y, z);
     // grad rhoN = -n sqrt(|grad rhoN|^2 + eps_n^2), from the geometry kernel's n and |grad rhoN|
-    const R G = k.fld.G[k.lev][n];
+    const R G = ld(k.fld.G[k.lev], n);
     const R den = sqrt(G * G + k.eps_n * k.eps_n);
     R g[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, nv[3] = {0, 0, 0}, kappa = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         kappa -= lat_deriv<LAT, R>(nb, k.fld.nrm + a * N, n, R(1), a, a);
         gp[a] = lat_deriv<LAT, R>(nb, psiA, n, s, a, -1);
-        nv[a] = k.fld.nrm[a * N + n];
+        nv[a] = ld(k.fld.nrm + a * N, n);
         g[a] = -nv[a] * den;
     }
-    const R psi = s * psiA[n];
+    const R psi = s * ld(psiA, n);
     R Fs[3] = {0, 0, 0};
     if (k.E0 == R(0)) {
 #pragma unroll
@@ -313,14 +315,15 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_force(KP<ty
 #pragma unroll
         for (int a = 0; a < D; ++a) Fs[a] = R(-0.5) * k.sigma_min * kappa * g[a];
     }
-    const R rho = mac[n] + mac[N + n], irho = R(1) / rho;
+    const R rR = ld(mac, n), rB = ld(mac + N, n);
+    const R rho = rR + rB, irho = R(1) / rho;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         R Fa = Fs[a] + (rho - k.rhoB0) * k.grav[a];
-        const R ua = (mac[(3 + a) * N + n] + R(0.5) * Fa) * irho;
-        k.fld.F[a * N + n] = Fa;
-        k.fld.u[a * N + n] = ua;
-        if (k.qon) k.fld.qf[a * N + n] = (k.qcoef[0] * mac[n] + k.qcoef[1] * mac[N + n]) * ua;
+        const R ua = (ld(mac + (3 + a) * N, n) + R(0.5) * Fa) * irho;
+        st(k.fld.F + a * N, n, Fa);
+        st(k.fld.u + a * N, n, ua);
+        if (k.qon) st(k.fld.qf + a * N, n, (k.qcoef[0] * rR + k.qcoef[1] * rB) * ua);
     }
 }
 
@@ -338,21 +341,22 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
     Node nd = node_id(k);
     if (!nd.ok) return;
     const int x = nd.x, y = nd.y, z = nd.z;
-    const long long N = k.N, n = lin(k, x, y, z);
+    const long long N = k.N;
+    const uint32_t n = node_index(k, nd);
     const S *fin = (const S *)k.fld.f[k.fc];
     S *fout = (S *)k.fld.f[1 - k.fc];
     const R *mac = k.fld.mac[k.lev];
     V4<R> *dsc = k.fld.desc;
 
     const Nbhd nb = make_nbhd(k, x, y, z);
-    const R rR = mac[n], rB = mac[N + n], rN = mac[2 * N + n];
+    const R rR = ld(mac, n), rB = ld(mac + N, n), rN = ld(mac + 2 * N, n);
     const R rho = rR + rB, irho = R(1) / rho;
     R u[3] = {0, 0, 0}, F[3] = {0, 0, 0}, nv[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        u[d] = k.fld.u[d * N + n];
-        F[d] = k.fld.F[d * N + n];
-        nv[d] = k.fld.nrm[d * N + n];
+        u[d] = ld(k.fld.u + d * N, n);
+        F[d] = ld(k.fld.F + d * N, n);
+        nv[d] = ld(k.fld.nrm + d * N, n);
     }
     // moments m = M f of the node
     R m[Q];
@@ -366,7 +370,7 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
         for (int r = 0; r < Q; ++r) m[r] = 0;
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
-            const R fj = fin[(long long)j * N + n];
+            const R fj = ld(fin + j * N, n);
 #pragma unroll
             for (int r = 0; r < Q; ++r)
                 if (L::M[r][j] != 0) m[r] += R(L::M[r][j]) * fj;
@@ -427,14 +431,14 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
     // recolouring descriptor (eqs 11-12): colour share and c = beta rho^R rho^B / rho g/|g|,
     // g/|g| = -n sqrt(|g|^2 + eps_n^2) / |g| with the geometry kernel's n and |g|
     const R a = rR * irho;
-    const R Gm = k.fld.G[k.lev][n];
+    const R Gm = ld(k.fld.G[k.lev], n);
     const R cf = Gm > R(0) ? -k.beta * (a * rB) * (sqrt(Gm * Gm + k.eps_n * k.eps_n) / Gm) : R(0);
-    dsc[n] = V4<R>{a, cf * nv[0], cf * nv[1], cf * nv[2]};
+    st(dsc, n, V4<R>{a, cf * nv[0], cf * nv[1], cf * nv[2]});
     R us[3] = {0, 0, 0};
     if constexpr (P::DEV) {
 #pragma unroll
         for (int d = 0; d < D; ++d) us[d] = u[d] + R(0.5) * F[d] * irho;
-        dsc[N + n] = V4<R>{rho, us[0], us[1], us[2]};
+        st(dsc + N, n, V4<R>{rho, us[0], us[1], us[2]});
         // deviation modes store f_dag_i - ref_i with ref_i = rho [a phiR_i + (1 - a) phiB_i
         // + w_i (3 e.u* + 4.5 (e.u*)^2 - 1.5 u*^2)]: subtract the moments of ref from m*
         // (rest part: the colour equilibria at u = 0; motion part: the weighted tables)
@@ -469,18 +473,21 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
         if (ey != 0) wt = by ? k.wterm[ey > 0 ? 3 : 2][i] : wt;
         if (ez != 0) wt = bz ? k.wterm[ez > 0 ? 5 : 4][i] : wt;
         v -= rho * wt;
-        const int j = bo ? L::OPP[i] : i;
-        const long long dest = bo ? n : n + nb_delta(nb, ex, ey, ez);
         if constexpr (P::DEV) {
-            // a reflected population is stored in direction j = opp(i): ref_i - ref_j = 6 rho w_i e_i.u*
+            // a reflected population is stored in direction opp(i): ref_i - ref_opp(i) = 6 rho w_i e_i.u*
             if (i != 0) {
                 const R eus = R(ex) * us[0] + R(ey) * us[1] + R(ez) * us[2];
                 v += bo ? R(6 * L::W[i]) * rho * eus : R(0);
             }
-            fout[(long long)j * N + dest] = from_real<S>(v);
-        } else {
-            fout[(long long)j * N + dest] = v;
         }
+        // one store: base at the lower plane of the pair (i, opp(i)), which are at most
+        // two planes apart, so the offset stays below 3 N elements
+        const int lo = i < L::OPP[i] ? i : L::OPP[i];
+        const uint32_t N32 = (uint32_t)N;
+        const uint32_t dst = bo ? (uint32_t)(L::OPP[i] - lo) * N32 + n
+                                : (uint32_t)(i - lo) * N32 + n + (uint32_t)nb_delta(nb, ex, ey, ez);
+        if constexpr (P::DEV) st(fout + lo * N, dst, from_real<S>(v));
+        else st(fout + lo * N, dst, (S)v);
     }
 }
 
@@ -498,7 +505,8 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
     Node nd = node_id(k);
     if (!nd.ok) return;
     const int x = nd.x, y = nd.y, z = nd.z;
-    const long long N = k.N, n = lin(k, x, y, z);
+    const long long N = k.N;
+    const uint32_t n = node_index(k, nd);
     const S *fin = (const S *)k.fld.f[1 - k.fc];
     const V4<R> *ds = k.fld.desc;
     const Nbhd nb = make_nbhd(k, x, y, z);
@@ -511,13 +519,13 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         bool bo;
-        const long long src = source_of<LAT>(nb, n, q, bo);
+        const uint32_t src = source_of<LAT>(nb, n, q, bo);
         const R sgn = bo ? R(-1) : R(1);   // a reflected arrival left its source along -e_q
-        const V4<R> A = ds[src];
-        R fq = to_real(fin[(long long)q * N + n]);
+        const V4<R> A = ld(ds, src);
+        R fq = to_real(ld(fin + q * N, n));
         if constexpr (P::DEV) {
             // decode with the reference of the node the population left
-            const V4<R> B = ds[N + src];
+            const V4<R> B = ld(ds + N, src);
             const R us[3] = {B.y, B.z, B.w};
             fq += reference<LAT, R>(k, q, R(1), B.x, A.x, us);
         }
@@ -539,11 +547,11 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
     }
     R *mac = k.fld.mac[1 - k.lev];
     R rr = rR * k.irho0[0], bb = rB * k.irho0[1];
-    mac[n] = rR;
-    mac[N + n] = rB;
-    mac[2 * N + n] = (rr - bb) / (rr + bb);
+    st(mac, n, rR);
+    st(mac + N, n, rB);
+    st(mac + 2 * N, n, (rr - bb) / (rr + bb));
 #pragma unroll
-    for (int d = 0; d < D; ++d) mac[(3 + d) * N + n] = j[d];
+    for (int d = 0; d < D; ++d) st(mac + (3 + d) * N, n, j[d]);
     if constexpr (P::DEV) {
         // in place: the node's own slots, after all of its loads
         R uj[3] = {0, 0, 0};
@@ -557,23 +565,22 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
 // ============================================================== finite differences
 
 // WENO3 one-sided differences of eqs 26-27 at the centre of a 5-point line.
+// With A = eps + (D+D- at i-1)^2, B = eps + (D+D- at i)^2, C = eps + (D+D- at i+1)^2
+// the weights 1/(1 + 2 r^2) are B^2/(B^2 + 2A^2) and B^2/(B^2 + 2C^2); both come
+// from one reciprocal of the product of their denominators (all terms >= eps^2).
 template <class R> __device__ __forceinline__ void weno_pair(const R *P, R eps, R &Dm, R &Dp)
 {
     // P[0..4] = Psi at i-2..i+2
     R d_2 = P[1] - P[0], d_1 = P[2] - P[1], d0 = P[3] - P[2], d1 = P[4] - P[3];
     R dd_1 = P[2] - R(2) * P[1] + P[0], dd0 = P[3] - R(2) * P[2] + P[1], dd1 = P[4] - R(2) * P[3] + P[2];
-    R rm = (eps + dd_1 * dd_1) / (eps + dd0 * dd0);
-    R wm = R(1) / (R(1) + R(2) * rm * rm);
+    const R A = eps + dd_1 * dd_1, B = eps + dd0 * dd0, C = eps + dd1 * dd1;
+    const R B2 = B * B, den_m = B2 + R(2) * A * A, den_p = B2 + R(2) * C * C;
+    const R inv = fast_rcp(den_m * den_p);
+    const R wm = B2 * den_p * inv, wp = B2 * den_m * inv;
     Dm = R(0.5) * ((d_1 + d0) - wm * (d_2 - R(2) * d_1 + d0));
-    R rp = (eps + dd1 * dd1) / (eps + dd0 * dd0);
-    R wp = R(1) / (R(1) + R(2) * rp * rp);
     Dp = R(0.5) * ((d_1 + d0) - wp * (d1 - R(2) * d0 + d_1));
 }
 
-// Explicit part of the modified Crank-Nicolson step (eqs 20-28): WENO3
-// convection of Psi = psi G u and Phi = phi X u, adsorption source, AB2 (or
-// Euler at the first step), explicit half of the diffusion; writes the
-// right-hand sides, S^n and B^n, and the rescaled initial guess of the solve.
 template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typename P::R> k)
 {
     using R = typename P::R;
@@ -591,7 +598,8 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typen
     Node nd = node_id(k);
     if (!nd.ok) return;
     const int x = nd.x, y = nd.y, z = nd.z;
-    const long long N = k.N, n = lin(k, x, y, z);
+    const long long N = k.N;
+    const uint32_t n = node_index(k, nd);
     const R s = (R)k.fld.sc->scale;
     const R *psiA = k.fld.psi[k.pc], *phiA = k.fld.phi[k.pc];
     const R *G0 = k.fld.G[k.lev];
@@ -604,55 +612,57 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typen
         R Pp[5], Pf[5];
 #pragma unroll
         for (int o = -2; o <= 2; ++o) {
-            const long long q = o == 0 ? n : n + nb.d[a][slot_of(o)];
+            const uint32_t q = o == 0 ? n : n + (uint32_t)nb.d[a][slot_of(o)];
             const R sg = (o != 0 && ((nb.mir >> (a * 4 + slot_of(o))) & 1u)) ? R(-1) : R(1);
-            R ua = uv[a * N + q];
-            Pp[o + 2] = sg * ((s * psiA[q]) * (G0[q] + k.fd_eps) * ua);
-            Pf[o + 2] = sg * ((s * phiA[q]) * ((R(1) - rN0[q]) + k.fd_eps) * ua);
+            R ua = ld(uv + a * N, q);
+            Pp[o + 2] = sg * ((s * ld(psiA, q)) * (ld(G0, q) + k.fd_eps) * ua);
+            Pf[o + 2] = sg * ((s * ld(phiA, q)) * ((R(1) - ld(rN0, q)) + k.fd_eps) * ua);
         }
-        R Dm, Dp, ua = uv[a * N + n], hp, hm;
-        if (fabs(ua) <= k.upwind_eps) { hp = R(0.5); hm = R(0.5); }
-        else { hp = fmax(ua, R(0)) / fabs(ua); hm = fabs(fmin(ua, R(0))) / fabs(ua); }
+        // H+ = u+/|u| and H- = |u-|/|u| are exactly 1 or 0 away from the +-upwind_eps band
+        R Dm, Dp, ua = ld(uv + a * N, n);
+        const bool band = fabs(ua) <= k.upwind_eps;
+        const R hp = band ? R(0.5) : (ua > R(0) ? R(1) : R(0));
+        const R hm = band ? R(0.5) : (ua < R(0) ? R(1) : R(0));
         weno_pair(Pp, k.weno_eps, Dm, Dp);
         divP += hp * Dm + hm * Dp;
         weno_pair(Pf, k.weno_eps, Dm, Dp);
         divF += hp * Dm + hm * Dp;
     }
-    const R psi = s * psiA[n], phi = s * phiA[n];
+    const R psi = s * ld(psiA, n), phi = s * ld(phiA, n);
     // weights of eqs 20-21 with the background support
-    const R Gn = G0[n] + k.fd_eps, Xn = (R(1) - rN0[n]) + k.fd_eps;
+    const R Gn = ld(G0, n) + k.fd_eps, Xn = (R(1) - ld(rN0, n)) + k.fd_eps;
     const R jj = k.source_mode == 1 ? k.ra * k.psi_inf * phi : k.ra * phi * (k.psi_inf - psi) - k.rd * psi;
     const R Sn = -divP + Gn * jj, Bn = -divF - Gn * jj;
-    const R eS = k.step == 0 ? Sn : R(1.5) * Sn - R(0.5) * k.fld.Sp[n];
-    const R eB = k.step == 0 ? Bn : R(1.5) * Bn - R(0.5) * k.fld.Bp[n];
+    const R eS = k.step == 0 ? Sn : R(1.5) * Sn - R(0.5) * ld(k.fld.Sp, n);
+    const R eB = k.step == 0 ? Bn : R(1.5) * Bn - R(0.5) * ld(k.fld.Bp, n);
     // diffusion operator of eq 28 with half-point weights, as printed
     R swP = 0, swcP = 0, swF = 0, swcF = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int o = -1; o <= 1; o += 2) {
-            const long long q = n + nb.d[a][slot_of(o)];
-            R wP = R(0.5) * (Gn + (G0[q] + k.fd_eps));
-            R wF = R(0.5) * (Xn + ((R(1) - rN0[q]) + k.fd_eps));
-            swcP += wP * (s * psiA[q]);
+            const uint32_t q = n + (uint32_t)nb.d[a][slot_of(o)];
+            R wP = R(0.5) * (Gn + (ld(G0, q) + k.fd_eps));
+            R wF = R(0.5) * (Xn + ((R(1) - ld(rN0, q)) + k.fd_eps));
+            swcP += wP * (s * ld(psiA, q));
             swP += wP;
-            swcF += wF * (s * phiA[q]);
+            swcF += wF * (s * ld(phiA, q));
             swF += wF;
         }
-    k.fld.rhsP[n] = Gn * psi + R(0.5) * k.Ds * (swcP - swP * psi) + eS;
-    k.fld.rhsF[n] = Xn * phi + R(0.5) * k.Db * (swcF - swF * phi) + eB;
-    k.fld.Sp[n] = Sn;
-    k.fld.Bp[n] = Bn;
+    st(k.fld.rhsP, n, Gn * psi + R(0.5) * k.Ds * (swcP - swP * psi) + eS);
+    st(k.fld.rhsF, n, Xn * phi + R(0.5) * k.Db * (swcF - swF * phi) + eB);
+    st(k.fld.Sp, n, Sn);
+    st(k.fld.Bp, n, Bn);
     // initial guess of the implicit solve: linear extrapolation from the two
     // previous levels where both exist (the other buffer holds level n-1)
     R psig = psi, phig = phi;
     if (k.extrap) {
         const R sp = (R)k.fld.sc->scale_prev;
-        psig = R(2) * psi - sp * k.fld.psi[1 - k.pc][n];
-        phig = R(2) * phi - sp * k.fld.phi[1 - k.pc][n];
+        psig = R(2) * psi - sp * ld(k.fld.psi[1 - k.pc], n);
+        phig = R(2) * phi - sp * ld(k.fld.phi[1 - k.pc], n);
     }
-    k.fld.psi[1 - k.pc][n] = psig;
-    k.fld.phi[1 - k.pc][n] = phig;
+    st(k.fld.psi[1 - k.pc], n, psig);
+    st(k.fld.phi[1 - k.pc], n, phig);
 }
 
 // One colour half of a red-black SOR sweep of both implicit systems
@@ -687,7 +697,7 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
     R *psi = k.fld.psi[1 - k.pc], *phi = k.fld.phi[1 - k.pc];
     const R *rhsP = k.fld.rhsP, *rhsF = k.fld.rhsF;
     const R eps = k.fd_eps, hdP = R(0.5) * k.Ds, hdF = R(0.5) * k.Db, om = k.omega;
-    double rloc[2] = {0, 0}, bloc[2] = {0, 0};
+    R rloc[2] = {0, 0}, bloc[2] = {0, 0};
     // tiles of 64 same-colour nodes along x by 4 rows, one z plane
     const int tx = (hx + 63) >> 6, ty = (ny + 3) >> 2;
     const int ntiles = tx * ty * nz;
@@ -700,9 +710,9 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
         const int y = by * 4 + ly;
         const int x = 2 * (bx * 64 + li) + ((y + z + color) & 1);
         if (x >= nx || y >= ny) continue;
-        const int n = x + sy * y + sz * z;
+        const uint32_t n = (uint32_t)(x + sy * y + sz * z);
         // face neighbours: periodic wrap, or the node itself across a wall (no flux)
-        int q[6];
+        uint32_t q[6];
         q[0] = x > 0 ? n - 1 : (k.bc[0] ? n : n + (nx - 1));
         q[1] = x < nx - 1 ? n + 1 : (k.bc[0] ? n : n - (nx - 1));
         q[2] = y > 0 ? n - sy : (k.bc[1] ? n : n + sy * (ny - 1));
@@ -712,40 +722,41 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
             q[5] = z < nz - 1 ? n + sz : (k.bc[2] ? n : n - sz * (nz - 1));
         }
         if (!conv[0]) {
-            const R Wn = G1[n] + eps;
+            const R Wn = ld(G1, n) + eps;
             R diag = Wn, off = 0;
 #pragma unroll
             for (int f = 0; f < 2 * D; ++f) {
                 if (q[f] == n) continue;
-                const R wf = hdP * (R(0.5) * (Wn + (G1[q[f]] + eps)));
+                const R wf = hdP * (R(0.5) * (Wn + (ld(G1, q[f]) + eps)));
                 diag += wf;
-                off += wf * psi[q[f]];
+                off += wf * ld((const R *)psi, q[f]);
             }
-            const R rhs = rhsP[n], c0 = psi[n];
-            rloc[0] = fmax(rloc[0], fabs((double)(rhs - (diag * c0 - off))));
-            bloc[0] = fmax(bloc[0], fabs((double)rhs));
-            psi[n] = (R(1) - om) * c0 + om * (rhs + off) / diag;
+            const R rhs = ld(rhsP, n), c0 = ld((const R *)psi, n);
+            rloc[0] = fmax(rloc[0], fabs(rhs - (diag * c0 - off)));
+            bloc[0] = fmax(bloc[0], fabs(rhs));
+            st(psi, n, (R(1) - om) * c0 + om * (rhs + off) / diag);
         }
         if (!conv[1]) {
-            const R Wn = (R(1) - rN1[n]) + eps;
+            const R Wn = (R(1) - ld(rN1, n)) + eps;
             R diag = Wn, off = 0;
 #pragma unroll
             for (int f = 0; f < 2 * D; ++f) {
                 if (q[f] == n) continue;
-                const R wf = hdF * (R(0.5) * (Wn + ((R(1) - rN1[q[f]]) + eps)));
+                const R wf = hdF * (R(0.5) * (Wn + ((R(1) - ld(rN1, q[f])) + eps)));
                 diag += wf;
-                off += wf * phi[q[f]];
+                off += wf * ld((const R *)phi, q[f]);
             }
-            const R rhs = rhsF[n], c0 = phi[n];
-            rloc[1] = fmax(rloc[1], fabs((double)(rhs - (diag * c0 - off))));
-            bloc[1] = fmax(bloc[1], fabs((double)rhs));
-            phi[n] = (R(1) - om) * c0 + om * (rhs + off) / diag;
+            const R rhs = ld(rhsF, n), c0 = ld((const R *)phi, n);
+            rloc[1] = fmax(rloc[1], fabs(rhs - (diag * c0 - off)));
+            bloc[1] = fmax(bloc[1], fabs(rhs));
+            st(phi, n, (R(1) - om) * c0 + om * (rhs + off) / diag);
         }
     }
     // block maxima, one atomic per block and quantity, spread over RSLOTS cache lines
     __shared__ double red[4][4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double v[4] = {wave_max(rloc[0]), wave_max(rloc[1]), wave_max(bloc[0]), wave_max(bloc[1])};
+    double v[4] = {wave_max((double)rloc[0]), wave_max((double)rloc[1]), wave_max((double)bloc[0]),
+                   wave_max((double)bloc[1])};
     if (lane == 0)
 #pragma unroll
         for (int j = 0; j < 4; ++j) red[j][wv] = v[j];
@@ -1080,7 +1091,8 @@ int check_params(const lbfd_params *p)
     if (p->precision < LBFD_FP64 || p->precision > LBFD_BF16DEV) return LBFD_EINVAL;
     if (p->nx < 4 || p->ny < 4) return LBFD_EINVAL;
     if (p->lattice == LBFD_D2Q9 ? p->nz != 1 : p->nz < 4) return LBFD_EINVAL;
-    if ((long long)p->nx * p->ny * p->nz >= (1LL << 31)) return LBFD_EINVAL;
+    // 32-bit byte offsets within a plane: N * (largest element, a 4-vector of reals) < 2^32
+    if ((long long)p->nx * p->ny * p->nz * (p->precision == LBFD_FP64 ? 32 : 16) >= (1LL << 32)) return LBFD_EINVAL;
     if (!(p->rhoR0 > 0 && p->rhoB0 > 0 && p->muR0 > 0 && p->muB0 > 0)) return LBFD_EINVAL;
     if (!(p->alphaR > 0 && p->alphaR < 1)) return LBFD_EINVAL;
     double alphaB = 1.0 - (p->rhoR0 / p->rhoB0) * (1.0 - p->alphaR);

@@ -190,6 +190,24 @@ template <class R> __device__ __forceinline__ long long lin(const KP<R> &k, int 
     return (long long)x + (long long)k.nx * ((long long)y + (long long)k.ny * z);
 }
 
+// Element idx of an array addressed as a uniform base pointer plus a 32-bit
+// byte offset. This maps onto the scalar-base + vector-offset form of the
+// global loads and stores, and one offset serves every array with the same
+// element size. Requires idx * sizeof(T) < 2^32 (the host bounds the node count).
+template <class T> __device__ __forceinline__ T ld(const T *base, uint32_t idx)
+{
+    return *(const T *)((const char *)base + idx * (uint32_t)sizeof(T));
+}
+template <class T> __device__ __forceinline__ void st(T *base, uint32_t idx, const T &v)
+{
+    *(T *)((char *)base + idx * (uint32_t)sizeof(T)) = v;
+}
+
+template <class R> __device__ __forceinline__ uint32_t node_index(const KP<R> &k, const Node &nd)
+{
+    return (uint32_t)nd.x + (uint32_t)k.nx * ((uint32_t)nd.y + (uint32_t)k.ny * (uint32_t)nd.z);
+}
+
 // Per-thread neighbourhood: for each axis a and offset o in {-2,-1,+1,+2} the
 // linear index delta of the neighbour (periodic wrap, or the mirror image
 // across a half-way wall: c = -1-j -> j, c = n+j -> n-1-j) and whether a wall
@@ -258,7 +276,7 @@ __device__ __forceinline__ bool nb_wall_axis(const Nbhd &b, int a, int ea)
 // odd_axis >= 0 marks the odd_axis component of a vector field, which changes
 // sign in a mirror normal to that axis.
 template <int LAT, class R>
-__device__ __forceinline__ R lat_deriv(const Nbhd &b, const R *chi, long long n, R scl, int a, int odd_axis)
+__device__ __forceinline__ R lat_deriv(const Nbhd &b, const R *chi, uint32_t n, R scl, int a, int odd_axis)
 {
     using L = Lat<LAT>;
     R acc = 0;
@@ -266,8 +284,8 @@ __device__ __forceinline__ R lat_deriv(const Nbhd &b, const R *chi, long long n,
     for (int i = 1; i < L::Q; ++i) {
         if (L::OPP[i] < i || L::E[i][a] == 0) continue;
         const int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
-        R vp = chi[n + nb_delta(b, ex, ey, ez)];
-        R vm = chi[n + nb_delta(b, -ex, -ey, -ez)];
+        R vp = ld(chi, n + (uint32_t)nb_delta(b, ex, ey, ez));
+        R vm = ld(chi, n + (uint32_t)nb_delta(b, -ex, -ey, -ez));
         if (odd_axis >= 0) {
             const int eo = L::E[i][odd_axis];
             if (nb_wall_axis(b, odd_axis, eo)) vp = -vp;
@@ -300,12 +318,12 @@ __device__ __forceinline__ R reference(const KP<R> &k, int i, R sgn, R rho, R a,
 // n itself when that crosses a wall (half-way bounce-back returns a population
 // that left through a wall to its node reversed).
 template <int LAT>
-__device__ __forceinline__ long long source_of(const Nbhd &b, long long n, int j, bool &bounced)
+__device__ __forceinline__ uint32_t source_of(const Nbhd &b, uint32_t n, int j, bool &bounced)
 {
     using L = Lat<LAT>;
     const int ex = -L::E[j][0], ey = -L::E[j][1], ez = -L::E[j][2];
     bounced = nb_wall(b, ex, ey, ez);
-    return bounced ? n : n + nb_delta(b, ex, ey, ez);
+    return bounced ? n : n + (uint32_t)nb_delta(b, ex, ey, ez);
 }
 
 // Moments of a second-order polynomial in e_i weighted by w_i:
@@ -324,6 +342,11 @@ template <int LAT, class R> __device__ __forceinline__ R wpoly(int r, R c0, cons
         if (L::MWEE[r][p] != 0.0) v += R(L::MWEE[r][p]) * c2[p];
     return v;
 }
+
+// Reciprocal of a positive normal number: the hardware approximation (1 ulp) in
+// FP32, the correctly rounded quotient in FP64.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
 // ------------------------------------------------------------------ wave reductions
 
