@@ -84,7 +84,9 @@ typedef struct {
     int32_t source_mode;         /* 0: j of eq 22; 1: adsorption only, j = ra psi_inf phi (Sec 3.1) */
     double gravity[3];           /* body force F_b = (rho - rhoB0) * gravity (Sec 3.4) */
     double sor_omega;            /* SOR relaxation factor (1.2 in Sec 2.2) */
-    double sor_tol;              /* stop at max|residual| <= sor_tol * max|rhs| */
+    double sor_tol;              /* stop at max|residual| <= sor_tol * max|rhs| (red-black ordering;
+                                    with sor_omega = 1 the test after sweep s is the red residual at
+                                    the start of sweep s + 1, whose red half is then kept) */
     int32_t sor_max_sweeps;      /* sweeps launched per step; LBFD_ESOR if still above tolerance */
     double weno_eps;             /* WENO3 epsilon (1e-6, Sec 2.2) */
     int32_t rescale;             /* 1: restore the initial total surfactant each step */
@@ -124,7 +126,7 @@ typedef struct {
     double psi_min, psi_max;     /* over nodes with |rhoN| <= 0.5 */
     double p_in, p_out;          /* mean sum_k rho^k (cs^k)^2 over rhoN > 0.99 and rhoN < -0.99 */
     double deformation;          /* (L - B)/(L + B) from the second-moment eigenvalues */
-    int32_t sor_sweeps[2];       /* sweeps the last step needed for psi and phi */
+    int32_t sor_sweeps[2];       /* full sweeps after which psi and phi met the tolerance (last step) */
     int32_t status;              /* sticky device error status (lbfd_status) */
 } lbfd_obs;
 

@@ -586,15 +586,6 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typen
     using R = typename P::R;
     using L = Lat<LAT>;
     constexpr int D = L::D;
-    if (blockIdx.x == 0) {
-        // clear the residual slots of the sweeps this step launches (and of the |rhs| maxima)
-        const int t = threadIdx.x + threadIdx.y * blockDim.x, nt = blockDim.x * blockDim.y;
-        const int per = (k.nsweeps + 1) * RSLOTS;
-        for (int i = t; i < 2 * per; i += nt) {
-            const int fi = i / per, r = i % per, sw = r / RSLOTS, slot = r % RSLOTS;
-            *res_slot(k.fld.sorres, fi, sw == k.nsweeps ? MAX_SWEEPS : sw, slot) = 0ull;
-        }
-    }
     Node nd = node_id(k);
     if (!nd.ok) return;
     const int x = nd.x, y = nd.y, z = nd.z;
@@ -649,8 +640,10 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typen
             swcF += wF * (s * ld(phiA, q));
             swF += wF;
         }
-    st(k.fld.rhsP, n, Gn * psi + R(0.5) * k.Ds * (swcP - swP * psi) + eS);
-    st(k.fld.rhsF, n, Xn * phi + R(0.5) * k.Db * (swcF - swF * phi) + eB);
+    const R rhP = Gn * psi + R(0.5) * k.Ds * (swcP - swP * psi) + eS;
+    const R rhF = Xn * phi + R(0.5) * k.Db * (swcF - swF * phi) + eB;
+    st(k.fld.rhsP, n, rhP);
+    st(k.fld.rhsF, n, rhF);
     st(k.fld.Sp, n, Sn);
     st(k.fld.Bp, n, Bn);
     // initial guess of the implicit solve: linear extrapolation from the two
@@ -677,15 +670,28 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
     using R = typename P::R;
     using L = Lat<LAT>;
     constexpr int D = L::D;
-    // convergence of the previous sweep: maxima over the residual slots, one per lane
+    // Convergence, from maxima over the residual slots (one per lane). With omega = 1
+    // the black rows are solved exactly by each black half-sweep, so the red residual
+    // before the red update of sweep s is the whole residual after sweep s-1: a black
+    // half-sweep is skipped once the red half before it found the system converged,
+    // and the red half of the next sweep too. Otherwise both colours of the previous
+    // sweep are tested.
     bool conv[2] = {false, false};
-    if (sweep > 0) {
+    {
         const int lane = threadIdx.x & 63;
 #pragma unroll
         for (int fi = 0; fi < 2; ++fi) {
-            const double r = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, sweep - 1, lane)));
-            const double b = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, MAX_SWEEPS, lane)));
-            conv[fi] = r <= (double)k.tol * b;
+            const double b = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, RMAX_IDX, lane)));
+            double r = -1.0;
+            if (k.omega == R(1)) {
+                // red of sweep s >= 2: test of sweep s-1; black of sweep s >= 1: test of sweep s
+                const int sw = color == 0 ? sweep - 1 : sweep;
+                if (sw >= 1) r = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, 2 * sw, lane)));
+            } else if (sweep > 0) {
+                r = fmax(wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, 2 * (sweep - 1), lane))),
+                         wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, 2 * (sweep - 1) + 1, lane))));
+            }
+            conv[fi] = r >= 0.0 && r <= (double)k.tol * b;
         }
     }
     if (conv[0] && conv[1]) return;
@@ -752,53 +758,48 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
             st(phi, n, (R(1) - om) * c0 + om * (rhs + off) / diag);
         }
     }
-    // block maxima, one atomic per block and quantity, spread over RSLOTS cache lines
-    __shared__ double red[4][4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double v[4] = {wave_max((double)rloc[0]), wave_max((double)rloc[1]), wave_max((double)bloc[0]),
-                   wave_max((double)bloc[1])};
-    if (lane == 0)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) red[j][wv] = v[j];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = blockDim.x >> 6;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            for (int w = 1; w < nw; ++w) red[j][0] = fmax(red[j][0], red[j][w]);
-#pragma unroll
-        for (int fi = 0; fi < 2; ++fi) {
-            if (conv[fi]) continue;
-            const int slot = blockIdx.x % RSLOTS;
-            atomic_max_nonneg(res_slot(k.fld.sorres, fi, sweep, slot), red[fi][0]);
-            if (sweep == 0) atomic_max_nonneg(res_slot(k.fld.sorres, fi, MAX_SWEEPS, slot), red[2 + fi][0]);
-        }
-    }
+    // block maxima of the pre-update residuals of this colour half-sweep; max |rhs| over
+    // the rows of both colours during sweep 0 (no convergence test reads it before sweep 1)
+    block_max_to_slots(conv[0] ? R(-1) : rloc[0], conv[1] ? R(-1) : rloc[1], k.fld.sorres, 2 * sweep + color);
+    if (sweep == 0) block_max_to_slots(bloc[0], bloc[1], k.fld.sorres, RMAX_IDX);
 }
 
 // Sweep counts of the last solve; LBFD_ESOR when a system never met its tolerance.
-// One wavefront: lane l reads residual slot l.
+// One wavefront: lane l reads residual slot l. Afterwards it clears the slots of
+// every half-sweep and of the |rhs| maxima for the next step.
 template <class R> __global__ void k_sor_done(KP<R> k, int nsw)
 {
     DevScalars *sc = k.fld.sc;
     const int lane = threadIdx.x & 63;
     for (int fi = 0; fi < 2; ++fi) {
-        const double rm = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, MAX_SWEEPS, lane)));
+        const double rm = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, RMAX_IDX, lane)));
         const double lim = (double)k.tol * rm;
         int K = nsw;
-        double prev = 0.0;
-        for (int s = 0; s < nsw; ++s) {
-            const double r = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, s, lane)));
-            if (s >= 1 && K == nsw && prev <= lim) K = s;
-            prev = r;
+        bool ok = false;
+        if (k.omega == R(1)) {
+            // whole residual after s sweeps = red residual at the start of sweep s
+            for (int s = 1; s < nsw; ++s) {
+                const double r = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, 2 * s, lane)));
+                if (r <= lim) { K = s; ok = true; break; }
+            }
+        } else {
+            for (int s = 1; s <= nsw; ++s) {
+                const double r = fmax(wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, 2 * (s - 1), lane))),
+                                      wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, 2 * (s - 1) + 1, lane))));
+                if (r <= lim) { K = s; ok = true; break; }
+            }
         }
         if (lane == 0) {
             sc->rmax[fi] = (unsigned long long)__double_as_longlong(rm);
             sc->sweeps[fi] = K;
-            if (K == nsw && !(prev <= lim) && sc->status == 0) sc->status = LBFD_ESOR;
+            if (!ok && sc->status == 0) sc->status = LBFD_ESOR;
         }
     }
+    sor_slots_clear(k.fld.sorres, nsw);
 }
+
+// Clears the residual and |rhs| slots (set-up, before the first step).
+template <class R> __global__ void k_sor_clear(KP<R> k, int nsw) { sor_slots_clear(k.fld.sorres, nsw); }
 
 // ============================================================== reductions
 
@@ -1069,7 +1070,7 @@ Layout layout(const lbfd_params *p)
     L.u = take(sr * D * N);
     L.F = take(sr * D * N);
     L.qf = take(sr * D * N);
-    L.sorres = take(sizeof(unsigned long long) * 2 * (MAX_SWEEPS + 1) * RSLOTS * RSTRIDE);
+    L.sorres = take(sizeof(unsigned long long) * 2 * (RMAX_IDX + 1) * RSLOTS * RSTRIDE);
     for (int b = 0; b < 2; ++b) L.psi[b] = take(sr * N);
     for (int b = 0; b < 2; ++b) L.phi[b] = take(sr * N);
     L.Sp = take(sr * N);
@@ -1292,6 +1293,7 @@ template <int LAT, class P> struct Impl {
         sync_levels(h);
         KP<R> &k = kp(h);
         LAUNCH(KC_OTHER, (k_init<LAT, P>), h->grid, h->block, k, in);
+        LAUNCH(KC_OTHER, (k_sor_clear<R>), dim3(1), dim3(256), k, h->sweeps_launch);
         LAUNCH(KC_GEOM, (k_geom<LAT, P>), h->grid, h->block, k, k.lev);
         clear_scalars(h);
         totals(h, k.lev, k.pc, 1.0, 0);
@@ -1334,6 +1336,7 @@ template <int LAT, class P> struct Impl {
         KP<R> &k = kp(h);
         LAUNCH(KC_OTHER, (k_import<LAT, P>), h->grid, h->block, k, df, drR, drB, dps, dph, Sp ? dS : nullptr,
                Bp ? dB : nullptr);
+        LAUNCH(KC_OTHER, (k_sor_clear<R>), dim3(1), dim3(256), k, h->sweeps_launch);
         derived(h);
         DevScalars z;
         std::memset(&z, 0, sizeof(z));

@@ -364,10 +364,45 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long *addr, doub
 
 __device__ __forceinline__ double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
 
-// Slot of the residual (s < MAX_SWEEPS) or |rhs| (s = MAX_SWEEPS) maximum of field fi.
-__device__ __forceinline__ unsigned long long *res_slot(unsigned long long *base, int fi, int s, int slot)
+// Slot of a maximum of field fi: index 2 s + colour for the pre-update residual of
+// a half-sweep, RMAX_IDX for max |rhs|.
+constexpr int RMAX_IDX = 2 * MAX_SWEEPS;
+__device__ __forceinline__ unsigned long long *res_slot(unsigned long long *base, int fi, int idx, int slot)
 {
-    return base + ((size_t)(fi * (MAX_SWEEPS + 1) + s) * RSLOTS + slot) * RSTRIDE;
+    return base + ((size_t)(fi * (RMAX_IDX + 1) + idx) * RSLOTS + slot) * RSTRIDE;
+}
+
+// Block maxima of two non-negative values (a negative value means "nothing to
+// record"), each folded into one of the RSLOTS slots of entry idx with one
+// atomic per block. Every thread of the block must call it.
+template <class R>
+__device__ __forceinline__ void block_max_to_slots(R v0, R v1, unsigned long long *base, int idx)
+{
+    __shared__ double red[2][16];
+    const int t = threadIdx.x + threadIdx.y * blockDim.x;
+    const int lane = t & 63, wv = t >> 6, nw = (blockDim.x * blockDim.y) >> 6;
+    const double a = wave_max((double)v0), b = wave_max((double)v1);
+    if (lane == 0) { red[0][wv] = a; red[1][wv] = b; }
+    __syncthreads();
+    if (t == 0) {
+        double m[2] = {red[0][0], red[1][0]};
+        for (int w = 1; w < nw; ++w) { m[0] = fmax(m[0], red[0][w]); m[1] = fmax(m[1], red[1][w]); }
+        const int slot = (int)(blockIdx.x % RSLOTS);
+#pragma unroll
+        for (int fi = 0; fi < 2; ++fi)
+            if (m[fi] >= 0.0) atomic_max_nonneg(res_slot(base, fi, idx, slot), m[fi]);
+    }
+}
+
+// Zero the slots of the 2 nsw half-sweeps and of max |rhs| (threads of one block).
+__device__ __forceinline__ void sor_slots_clear(unsigned long long *base, int nsw)
+{
+    const int t = threadIdx.x + threadIdx.y * blockDim.x, nt = blockDim.x * blockDim.y;
+    const int per = (2 * nsw + 1) * RSLOTS;
+    for (int i = t; i < 2 * per; i += nt) {
+        const int fi = i / per, r = i % per, e = r / RSLOTS, slot = r % RSLOTS;
+        *res_slot(base, fi, e == 2 * nsw ? RMAX_IDX : e, slot) = 0ull;
+    }
 }
 
 }  // namespace lbfd
