@@ -56,7 +56,9 @@ def algorithmic_bytes(kernel: str, p: dict) -> float:
     bf = {"fp64": 8, "fp32": 4, "fp16dev": 2, "bf16dev": 2}[prec]
     br = 8 if prec == "fp64" else 4
     dev = prec in ("fp16dev", "bf16dev")
-    desc_w = 1 + D + ((1 + D) if dev else 0)      # descriptor written by the collision
+    # descriptor written by the collision, in bytes: (a, c) in the storage real, or the
+    # packed deviation-mode descriptor (a, rho FP32; c, u* FP16)
+    desc_b = (8 + 4 * D) if dev else (1 + D) * br
     # state between steps: Q populations, or (deviation modes) the Q - 1 - D
     # non-conserved moments
     state = (Q - 1 - D) if dev else Q
@@ -66,10 +68,10 @@ def algorithmic_bytes(kernel: str, p: dict) -> float:
     qc = [(1.0 - 1.5 * (1.0 - al)) if three else (1.8 * al - 0.8) for al in (p["alphaR"], alphaB)]
     qf = D if any(abs(c) > 1e-15 for c in qc) else 0
     table = {
-        # state in, Q populations out; rhoR rhoB rhoN, u, F, qf in; descriptor out
-        "collide": (state + Q) * bf + (3 + 2 * D + qf + desc_w) * br,
+        # state in, Q populations out; rhoR rhoB rhoN, u, F, normal, G, qf in; descriptor out
+        "collide": (state + Q) * bf + (3 + 3 * D + 1 + qf) * br + desc_b,
         # Q populations in, descriptor in, rhoR rhoB rhoN j out (+ moment state out)
-        "macro": (Q + (state if dev else 0)) * bf + (desc_w + 3 + D) * br,
+        "macro": (Q + (state if dev else 0)) * bf + (3 + D) * br + desc_b,
         # rhoN in, |grad rhoN| and normal out
         "geom": (2 + D) * br,
         # psi phi G rhoN u Sprev Bprev in; rhs x2, S B, psi phi guesses out

@@ -346,7 +346,6 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
     const S *fin = (const S *)k.fld.f[k.fc];
     S *fout = (S *)k.fld.f[1 - k.fc];
     const R *mac = k.fld.mac[k.lev];
-    V4<R> *dsc = k.fld.desc;
 
     const Nbhd nb = make_nbhd(k, x, y, z);
     const R rR = ld(mac, n), rB = ld(mac + N, n), rN = ld(mac + 2 * N, n);
@@ -433,12 +432,19 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
     const R a = rR * irho;
     const R Gm = ld(k.fld.G[k.lev], n);
     const R cf = Gm > R(0) ? -k.beta * (a * rB) * (sqrt(Gm * Gm + k.eps_n * k.eps_n) / Gm) : R(0);
-    st(dsc, n, V4<R>{a, cf * nv[0], cf * nv[1], cf * nv[2]});
     R us[3] = {0, 0, 0};
     if constexpr (P::DEV) {
+        // packed descriptor; the reference velocity is used as stored (FP16), so that
+        // the decoder's reference equals the encoder's
 #pragma unroll
-        for (int d = 0; d < D; ++d) us[d] = u[d] + R(0.5) * F[d] * irho;
-        st(dsc + N, n, V4<R>{rho, us[0], us[1], us[2]});
+        for (int d = 0; d < D; ++d) us[d] = round_h(u[d] + R(0.5) * F[d] * irho);
+        DescDev A;
+        A.a = a;
+        A.rho = rho;
+        A.c01 = pack_h2(cf * nv[0], cf * nv[1]);
+        A.c2u0 = D == 3 ? pack_h2(cf * nv[2], us[0]) : pack_h2(us[0], us[1]);
+        st((DescDev *)k.fld.desc, n, A);
+        if constexpr (D == 3) st(desc_dev_b(k), n, pack_h2(us[1], us[2]));
         // deviation modes store f_dag_i - ref_i with ref_i = rho [a phiR_i + (1 - a) phiB_i
         // + w_i (3 e.u* + 4.5 (e.u*)^2 - 1.5 u*^2)]: subtract the moments of ref from m*
         // (rest part: the colour equilibria at u = 0; motion part: the weighted tables)
@@ -452,6 +458,8 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
                          R(2) * h * us[0] * us[2], R(2) * h * us[1] * us[2]};
 #pragma unroll
         for (int r = 0; r < Q; ++r) m[r] -= mr[r] + wpoly<LAT, R>(r, R(-1.5) * rho * uu, c1, c2);
+    } else {
+        st((V4<R> *)k.fld.desc, n, V4<R>{a, cf * nv[0], cf * nv[1], cf * nv[2]});
     }
     // propagation with periodic wrap or half-way bounce-back
 #pragma unroll
@@ -508,7 +516,6 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
     const long long N = k.N;
     const uint32_t n = node_index(k, nd);
     const S *fin = (const S *)k.fld.f[1 - k.fc];
-    const V4<R> *ds = k.fld.desc;
     const Nbhd nb = make_nbhd(k, x, y, z);
     R rR = 0, rB = 0, j[3] = {0, 0, 0};
     R m[P::DEV ? Q : 1];
@@ -521,17 +528,35 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
         bool bo;
         const uint32_t src = source_of<LAT>(nb, n, q, bo);
         const R sgn = bo ? R(-1) : R(1);   // a reflected arrival left its source along -e_q
-        const V4<R> A = ld(ds, src);
         R fq = to_real(ld(fin + q * N, n));
+        R as, c[3] = {0, 0, 0};
         if constexpr (P::DEV) {
             // decode with the reference of the node the population left
-            const V4<R> B = ld(ds + N, src);
-            const R us[3] = {B.y, B.z, B.w};
-            fq += reference<LAT, R>(k, q, R(1), B.x, A.x, us);
+            const DescDev A = ld((const DescDev *)k.fld.desc, src);
+            R us[3] = {0, 0, 0};
+            c[0] = h_lo(A.c01);
+            c[1] = h_hi(A.c01);
+            if constexpr (D == 3) {
+                const uint32_t Bv = ld((const uint32_t *)desc_dev_b(k), src);
+                c[2] = h_lo(A.c2u0);
+                us[0] = h_hi(A.c2u0);
+                us[1] = h_lo(Bv);
+                us[2] = h_hi(Bv);
+            } else {
+                us[0] = h_lo(A.c2u0);
+                us[1] = h_hi(A.c2u0);
+            }
+            as = A.a;
+            fq += reference<LAT, R>(k, q, R(1), A.rho, as, us);
+        } else {
+            const V4<R> A = ld((const V4<R> *)k.fld.desc, src);
+            as = A.x;
+            c[0] = A.y;
+            c[1] = A.z;
+            c[2] = A.w;
         }
-        const R as = A.x;
-        R ec = R(L::E[q][0]) * A.y + R(L::E[q][1]) * A.z;
-        if constexpr (D == 3) ec += R(L::E[q][2]) * A.w;
+        R ec = R(L::E[q][0]) * c[0] + R(L::E[q][1]) * c[1];
+        if constexpr (D == 3) ec += R(L::E[q][2]) * c[2];
         ec *= sgn;
         R wgt = k.recolour_literal ? R(L::W[q]) : as * k.rest[0][q] + (R(1) - as) * k.rest[1][q];
         R r = wgt * ec;
@@ -1194,7 +1219,7 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
         F.psi[b] = (R *)(ws + Lo.psi[b]);
         F.phi[b] = (R *)(ws + Lo.phi[b]);
     }
-    F.desc = (V4<R> *)(ws + Lo.desc);
+    F.desc = (void *)(ws + Lo.desc);
     F.nrm = (R *)(ws + Lo.nrm);
     F.u = (R *)(ws + Lo.u);
     F.F = (R *)(ws + Lo.F);

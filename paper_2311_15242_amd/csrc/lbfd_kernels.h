@@ -99,13 +99,32 @@ struct DevScalars {
     int32_t pad;
 };
 
+// FP16 helpers of the packed descriptor (round to nearest even).
+__device__ __forceinline__ float round_h(float v) { return (float)(_Float16)v; }
+__device__ __forceinline__ uint32_t pack_h2(float lo, float hi)
+{
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)lo) |
+           ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)hi) << 16);
+}
+__device__ __forceinline__ float h_lo(uint32_t v) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xffffu)); }
+__device__ __forceinline__ float h_hi(uint32_t v) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16)); }
+
 // Four reals read or written by one vector access (the packed descriptor).
 template <class R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
+
+// Recolouring descriptor of a node in the 16-bit deviation modes (16 bytes): colour
+// share and density in FP32, the recolouring vector c and the reference velocity u*
+// in FP16 (c_x, c_y | c_z, u*_x in 3-D; c_x, c_y | u*_x, u*_y in 2-D); u*_y, u*_z of
+// 3-D lattices follow in a second plane. FP64 and FP32 modes use a V4 (a, c).
+struct alignas(16) DescDev {
+    float a, rho;
+    uint32_t c01, c2u0;
+};
 
 template <class R> struct Fields {
     void *f[2];
     R *mac[2];      // planes: 0 rhoR, 1 rhoB, 2 rhoN, 3.. j
-    V4<R> *desc;    // N x (a, c_x, c_y, c_z), then (deviation modes) N x (rho, u*_x, u*_y, u*_z)
+    void *desc;     // N x V4 (a, c) (FP64, FP32), or N x DescDev then N x 2 FP16 (deviation modes)
     R *G[2];
     R *nrm;
     R *u;
@@ -188,6 +207,12 @@ template <class R> __device__ __forceinline__ Node node_id(const KP<R> &k)
 template <class R> __device__ __forceinline__ long long lin(const KP<R> &k, int x, int y, int z)
 {
     return (long long)x + (long long)k.nx * ((long long)y + (long long)k.ny * z);
+}
+
+// Second plane of the deviation-mode descriptor (u*_y, u*_z of 3-D lattices).
+template <class R> __device__ __forceinline__ uint32_t *desc_dev_b(const KP<R> &k)
+{
+    return (uint32_t *)((DescDev *)k.fld.desc + k.N);
 }
 
 // Element idx of an array addressed as a uniform base pointer plus a 32-bit
