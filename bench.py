@@ -18,6 +18,8 @@ The printed JSON line also carries:
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
   secondary     the 2-D workloads (shear 512 x 256 in FP64 / FP32 / FP16-dev,
                 droplet 128 x 128 FP64), same timing method
+  batched       the parameter sweep of 64 uneven 2-D bubble columns as one
+                batch against the same instances run one after another
 """
 from __future__ import annotations
 
@@ -253,6 +255,80 @@ def sweep_budget(p, q, warmup, margin=2):
     return min(used + margin, p["sor_max_sweeps"])
 
 
+def batch_bench(steps, warmup, sor_sweeps, precision="bf16dev"):
+    """The parameter sweep: 64 uneven 2-D bubble columns (the committed
+    manifest), advanced as one batch, against the same 64 instances run one
+    after another as single solvers. Both use the same SOR launch budget (the
+    most any instance needed in the batched warm-up, plus a margin)."""
+    import torch
+
+    import workloads as W
+    from paper_2311_15242_amd import lbfd
+
+    inst = W.batch_instances(W.load_manifest(), precision=precision)
+    nodes = sum(p["nx"] * p["ny"] * p["nz"] for p, _ in inst)
+
+    def new_batch():
+        b = lbfd.Batch([p for p, _ in inst])
+        for m, (_, q) in zip(b.members, inst):
+            m.init_fields(q)
+        return b
+
+    if sor_sweeps == "auto":
+        b = new_batch()
+        used = 0
+        for i in range(max(warmup, 3)):
+            b.step(1)
+            if i >= 2:
+                used = max([used] + [max(m.observables()["sor_sweeps"]) for m in b.members])
+        b.close()
+        budget = min(used + 2, inst[0][0]["sor_max_sweeps"])
+    else:
+        budget = int(sor_sweeps)
+    for p, _ in inst:
+        p["sor_max_sweeps"] = budget
+
+    def check(objs, where):
+        bad = [i for i, m in enumerate(objs) if m.observables()["status"] != 0]
+        if bad:
+            raise RuntimeError(f"instances {bad[:8]} report a solver error {where}")
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b = new_batch()
+    b.step(warmup)
+    torch.cuda.synchronize()
+    check(b.members, "after the batched warm-up")
+    ev0.record()
+    b.step(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_b = ev0.elapsed_time(ev1)
+    check(b.members, "in the batched timed region")
+    b.close()
+    del b
+
+    solvers = [lbfd.Solver(p).init_fields(q) for p, q in inst]
+    for s in solvers:
+        s.step(warmup)
+    torch.cuda.synchronize()
+    ev0.record()
+    for s in solvers:
+        s.step(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_s = ev0.elapsed_time(ev1)
+    check(solvers, "in the sequential timed region")
+    for s in solvers:
+        s.close()
+    mb = nodes * steps / (ms_b / 1e3) / 1e6
+    ms = nodes * steps / (ms_s / 1e3) / 1e6
+    return dict(workload="bubble_rise_batch64: 64 uneven 2-D bubble columns (D2Q9, W 128-256 x H 256-768, "
+                         "Eo and Bi swept)", storage=precision, instances=len(inst), nodes=nodes, steps=steps,
+                batched_mlups=round(mb, 2), sequential_mlups=round(ms, 2), speedup=round(mb / ms, 3),
+                batched_ms_per_step=round(ms_b / steps, 4), sequential_ms_per_step=round(ms_s / steps, 4),
+                sor_sweeps_launched=budget)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +341,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance parameter sweep")
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--omega", type=float, default=None, help="SOR relaxation factor (default: the workload's)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (scales rocprofv3 byte counters)")
@@ -359,6 +437,8 @@ def main():
                                          ms_per_step=round(ms2 / 200, 4), sor_sweeps_used=ob2["sor_sweeps"],
                                          sor_sweeps_launched=pp["sor_max_sweeps"])
         out["secondary"] = sec
+    if not args.no_batch:
+        out["batched"] = batch_bench(args.batch_steps, args.warmup, args.sor_sweeps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, q, args.cpu_seconds)
     print(json.dumps(out), flush=True)

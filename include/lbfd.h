@@ -199,6 +199,39 @@ void lbfd_destroy(lbfd_handle *h);
 /* Static description of a status code. */
 const char *lbfd_strerror(int status);
 
+/* ---- Batches: independent instances stepped together ----------------------
+ *
+ * A batch holds n independent instances (a parameter sweep of uneven grids,
+ * say), each an ordinary handle on its own slice of one caller-owned device
+ * workspace, and advances all of them with one launch per kernel class instead
+ * of one per instance. The method per instance is unchanged: the same time
+ * step as lbfd_step. The instances share the lattice, the precision,
+ * fd_enable and sor_max_sweeps; grid sizes, boundaries and physical parameters
+ * are free. Each instance is initialised, observed and read through the
+ * single-instance calls on the handle lbfd_batch_instance returns (those calls
+ * synchronise the batch's stream); it is not stepped on its own. */
+typedef struct lbfd_batch lbfd_batch;
+
+/* Bytes of device workspace for a batch of the n parameter blocks p[0..n-1]. */
+int lbfd_batch_workspace_bytes(const lbfd_params *p, int32_t n, size_t *bytes);
+
+/* Create a batch on a caller-owned workspace (256-byte aligned, at least
+ * lbfd_batch_workspace_bytes) and stream. Errors: EINVAL (n outside 1..65536,
+ * an invalid parameter block, or lattice, precision, fd_enable or
+ * sor_max_sweeps differing between instances), EWORKSPACE, ENOMEM, EHIP. */
+int lbfd_batch_create(const lbfd_params *p, int32_t n, void *d_workspace, size_t bytes, void *stream,
+                      lbfd_batch **out);
+
+/* Handle of instance i (owned by the batch), or NULL when i is out of range. */
+lbfd_handle *lbfd_batch_instance(lbfd_batch *b, int32_t i);
+
+/* Advance every instance n >= 0 steps. All instances must be at the same step
+ * (initialised, or set to the same step, together), else EINVAL. Asynchronous. */
+int lbfd_batch_step(lbfd_batch *b, int64_t n);
+
+/* Release the batch and its instance handles (not the workspace or stream). */
+void lbfd_batch_destroy(lbfd_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,17 @@ namespace lbfd {
 
 constexpr int BX = 64, BY = 4;          // one wavefront spans 64 consecutive x
 constexpr int NRED = 19;                 // observable partial sums per block
-constexpr int TOTAL_BLOCKS = 1024;       // fixed grid of the total-surfactant sum (deterministic order)
+constexpr int TOTAL_BLOCKS = 1024;       // most workgroups of the total-surfactant sum
+constexpr int TOTAL_NODES = 4096;        // nodes per workgroup of that sum below the cap
+
+// Workgroups of the total-surfactant sum of an N-node grid. A function of N
+// alone, so the summation order (and the rounded total) of an instance is the
+// same whether it is stepped alone or in a batch.
+inline int total_blocks(long long N)
+{
+    const long long b = (N + TOTAL_NODES - 1) / TOTAL_NODES;
+    return (int)(b < 1 ? 1 : b > TOTAL_BLOCKS ? TOTAL_BLOCKS : b);
+}
 
 struct InitDev {
     int n;
@@ -246,11 +256,11 @@ __global__ __launch_bounds__(256) void k_import(KP<typename P::R> k, const doubl
 
 // |grad rhoN| and the regularised normal n = -grad rhoN / sqrt(|grad rhoN|^2 + eps^2)
 // of the time level `level` (below eq 6).
-template <int LAT, class P> __global__ __launch_bounds__(256) void k_geom(KP<typename P::R> k, int level)
+template <int LAT, class P> __device__ __forceinline__ void geom_body(const KP<typename P::R> &k, int tile, const StepArgs &sa, int level)
 {
     using R = typename P::R;
     using L = Lat<LAT>;
-    Node nd = node_id(k);
+    Node nd = node_at(k, tile);
     if (!nd.ok) return;
     const long long N = k.N;
     const uint32_t n = node_index(k, nd);
@@ -267,28 +277,39 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_geom(KP<typ
 #pragma unroll
     for (int a = 0; a < L::D; ++a) st(k.fld.nrm + a * N, n, den > R(0) ? -g[a] / den : R(0));
 }
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_geom(KP<typename P::R> k, int level)
+{
+    geom_body<LAT, P>(k, xcd_tile((int)blockIdx.x, (int)gridDim.x), step_args(k), level);
+}
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void kb_geom(const KP<typename P::R> *tab, const int *prefix, int ninst, StepArgs sa, int level)
+{
+    int inst, local;
+    batch_tile(prefix, ninst, inst, local);
+    geom_body<LAT, P>(tab[inst], local, sa, level);
+}
 
 // ============================================================== forces
 
 // Curvature (eq 7), modified Langmuir EOS (eq 8), interfacial force with the
 // Marangoni term (eq 9), buoyancy (Sec 3.4), total force and velocity (eq 10)
 // at the current time level.
-template <int LAT, class P> __global__ __launch_bounds__(256) void k_force(KP<typename P::R> k)
+template <int LAT, class P> __device__ __forceinline__ void force_body(const KP<typename P::R> &k, int tile, const StepArgs &sa)
 {
     using R = typename P::R;
     using L = Lat<LAT>;
     constexpr int D = L::D;
-    Node nd = node_id(k);
+    Node nd = node_at(k, tile);
     if (!nd.ok) return;
     const int x = nd.x, y = nd.y, z = nd.z;
     const long long N = k.N;
     const uint32_t n = node_index(k, nd);
-    const R *mac = k.fld.mac[k.lev];
+    const R *mac = k.fld.mac[sa.lev];
     const R s = (R)k.fld.sc->scale;
-    const R *psiA = k.fld.psi[k.pc];
+    const R *psiA = k.fld.psi[sa.pc];
     const Nbhd nb = make_nbhd(k, x, y, z);
     // grad rhoN = -n sqrt(|grad rhoN|^2 + eps_n^2), from the geometry kernel's n and |grad rhoN|
-    const R G = ld(k.fld.G[k.lev], n);
+    const R G = ld(k.fld.G[sa.lev], n);
     const R den = sqrt(G * G + k.eps_n * k.eps_n);
     R g[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, nv[3] = {0, 0, 0}, kappa = 0;
 #pragma unroll
@@ -326,26 +347,37 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_force(KP<ty
         if (k.qon) st(k.fld.qf + a * N, n, (k.qcoef[0] * rR + k.qcoef[1] * rB) * ua);
     }
 }
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_force(KP<typename P::R> k)
+{
+    force_body<LAT, P>(k, xcd_tile((int)blockIdx.x, (int)gridDim.x), step_args(k));
+}
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void kb_force(const KP<typename P::R> *tab, const int *prefix, int ninst, StepArgs sa)
+{
+    int inst, local;
+    batch_tile(prefix, ninst, inst, local);
+    force_body<LAT, P>(tab[inst], local, sa);
+}
 
 // ============================================================== collision
 
 // MRT collision in moment space (eqs 1-4 with the equilibria, corrections and
 // relaxation rates of Appendix A), the recolouring descriptor of eqs 11-12,
 // and push propagation (eq 13) into the other population buffer.
-template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<typename P::R> k)
+template <int LAT, class P> __device__ __forceinline__ void collide_body(const KP<typename P::R> &k, int tile, const StepArgs &sa)
 {
     using R = typename P::R;
     using S = typename P::S;
     using L = Lat<LAT>;
     constexpr int Q = L::Q, D = L::D;
-    Node nd = node_id(k);
+    Node nd = node_at(k, tile);
     if (!nd.ok) return;
     const int x = nd.x, y = nd.y, z = nd.z;
     const long long N = k.N;
     const uint32_t n = node_index(k, nd);
-    const S *fin = (const S *)k.fld.f[k.fc];
-    S *fout = (S *)k.fld.f[1 - k.fc];
-    const R *mac = k.fld.mac[k.lev];
+    const S *fin = (const S *)k.fld.f[sa.fc];
+    S *fout = (S *)k.fld.f[1 - sa.fc];
+    const R *mac = k.fld.mac[sa.lev];
 
     const Nbhd nb = make_nbhd(k, x, y, z);
     const R rR = ld(mac, n), rB = ld(mac + N, n), rN = ld(mac + 2 * N, n);
@@ -430,7 +462,7 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
     // recolouring descriptor (eqs 11-12): colour share and c = beta rho^R rho^B / rho g/|g|,
     // g/|g| = -n sqrt(|g|^2 + eps_n^2) / |g| with the geometry kernel's n and |g|
     const R a = rR * irho;
-    const R Gm = ld(k.fld.G[k.lev], n);
+    const R Gm = ld(k.fld.G[sa.lev], n);
     const R cf = Gm > R(0) ? -k.beta * (a * rB) * (sqrt(Gm * Gm + k.eps_n * k.eps_n) / Gm) : R(0);
     R us[3] = {0, 0, 0};
     if constexpr (P::DEV) {
@@ -498,24 +530,35 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<
         else st(fout + lo * N, dst, (S)v);
     }
 }
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<typename P::R> k)
+{
+    collide_body<LAT, P>(k, xcd_tile((int)blockIdx.x, (int)gridDim.x), step_args(k));
+}
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void kb_collide(const KP<typename P::R> *tab, const int *prefix, int ninst, StepArgs sa)
+{
+    int inst, local;
+    batch_tile(prefix, ninst, inst, local);
+    collide_body<LAT, P>(tab[inst], local, sa);
+}
 
 // ============================================================== macroscopic fields
 
 // rho^R, rho^B of the streamed populations, rebuilt from the recolouring
 // descriptors of the nodes they left (eq 11 summed over arrivals), the colour
 // function (eq 6) and the momentum sum f e, into mac of the next level.
-template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<typename P::R> k)
+template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<typename P::R> &k, int tile, const StepArgs &sa)
 {
     using R = typename P::R;
     using S = typename P::S;
     using L = Lat<LAT>;
     constexpr int Q = L::Q, D = L::D;
-    Node nd = node_id(k);
+    Node nd = node_at(k, tile);
     if (!nd.ok) return;
     const int x = nd.x, y = nd.y, z = nd.z;
     const long long N = k.N;
     const uint32_t n = node_index(k, nd);
-    const S *fin = (const S *)k.fld.f[1 - k.fc];
+    const S *fin = (const S *)k.fld.f[1 - sa.fc];
     const Nbhd nb = make_nbhd(k, x, y, z);
     R rR = 0, rB = 0, j[3] = {0, 0, 0};
     R m[P::DEV ? Q : 1];
@@ -570,7 +613,7 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
                 if (L::M[r2][q] != 0 && !conserved_row<LAT>(r2)) m[r2] += R(L::M[r2][q]) * fq;
         }
     }
-    R *mac = k.fld.mac[1 - k.lev];
+    R *mac = k.fld.mac[1 - sa.lev];
     R rr = rR * k.irho0[0], bb = rB * k.irho0[1];
     st(mac, n, rR);
     st(mac + N, n, rB);
@@ -583,8 +626,19 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<ty
         const R irho = R(1) / (rR + rB);
 #pragma unroll
         for (int d = 0; d < D; ++d) uj[d] = j[d] * irho;
-        store_moments<LAT, P>(k, (S *)k.fld.f[1 - k.fc], n, rR, rB, uj, m);
+        store_moments<LAT, P>(k, (S *)k.fld.f[1 - sa.fc], n, rR, rB, uj, m);
     }
+}
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<typename P::R> k)
+{
+    macro_body<LAT, P>(k, xcd_tile((int)blockIdx.x, (int)gridDim.x), step_args(k));
+}
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void kb_macro(const KP<typename P::R> *tab, const int *prefix, int ninst, StepArgs sa)
+{
+    int inst, local;
+    batch_tile(prefix, ninst, inst, local);
+    macro_body<LAT, P>(tab[inst], local, sa);
 }
 
 // ============================================================== finite differences
@@ -606,20 +660,20 @@ template <class R> __device__ __forceinline__ void weno_pair(const R *P, R eps, 
     Dp = R(0.5) * ((d_1 + d0) - wp * (d1 - R(2) * d0 + d_1));
 }
 
-template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typename P::R> k)
+template <int LAT, class P> __device__ __forceinline__ void fd_body(const KP<typename P::R> &k, int tile, const StepArgs &sa)
 {
     using R = typename P::R;
     using L = Lat<LAT>;
     constexpr int D = L::D;
-    Node nd = node_id(k);
+    Node nd = node_at(k, tile);
     if (!nd.ok) return;
     const int x = nd.x, y = nd.y, z = nd.z;
     const long long N = k.N;
     const uint32_t n = node_index(k, nd);
     const R s = (R)k.fld.sc->scale;
-    const R *psiA = k.fld.psi[k.pc], *phiA = k.fld.phi[k.pc];
-    const R *G0 = k.fld.G[k.lev];
-    const R *rN0 = k.fld.mac[k.lev] + 2 * N;
+    const R *psiA = k.fld.psi[sa.pc], *phiA = k.fld.phi[sa.pc];
+    const R *G0 = k.fld.G[sa.lev];
+    const R *rN0 = k.fld.mac[sa.lev] + 2 * N;
     const R *uv = k.fld.u;
     const Nbhd nb = make_nbhd(k, x, y, z);
     R divP = 0, divF = 0;
@@ -649,8 +703,8 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typen
     const R Gn = ld(G0, n) + k.fd_eps, Xn = (R(1) - ld(rN0, n)) + k.fd_eps;
     const R jj = k.source_mode == 1 ? k.ra * k.psi_inf * phi : k.ra * phi * (k.psi_inf - psi) - k.rd * psi;
     const R Sn = -divP + Gn * jj, Bn = -divF - Gn * jj;
-    const R eS = k.step == 0 ? Sn : R(1.5) * Sn - R(0.5) * ld(k.fld.Sp, n);
-    const R eB = k.step == 0 ? Bn : R(1.5) * Bn - R(0.5) * ld(k.fld.Bp, n);
+    const R eS = sa.step == 0 ? Sn : R(1.5) * Sn - R(0.5) * ld(k.fld.Sp, n);
+    const R eB = sa.step == 0 ? Bn : R(1.5) * Bn - R(0.5) * ld(k.fld.Bp, n);
     // diffusion operator of eq 28 with half-point weights, as printed
     R swP = 0, swcP = 0, swF = 0, swcF = 0;
 #pragma unroll
@@ -674,13 +728,24 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typen
     // initial guess of the implicit solve: linear extrapolation from the two
     // previous levels where both exist (the other buffer holds level n-1)
     R psig = psi, phig = phi;
-    if (k.extrap) {
+    if (sa.extrap) {
         const R sp = (R)k.fld.sc->scale_prev;
-        psig = R(2) * psi - sp * ld(k.fld.psi[1 - k.pc], n);
-        phig = R(2) * phi - sp * ld(k.fld.phi[1 - k.pc], n);
+        psig = R(2) * psi - sp * ld(k.fld.psi[1 - sa.pc], n);
+        phig = R(2) * phi - sp * ld(k.fld.phi[1 - sa.pc], n);
     }
-    st(k.fld.psi[1 - k.pc], n, psig);
-    st(k.fld.phi[1 - k.pc], n, phig);
+    st(k.fld.psi[1 - sa.pc], n, psig);
+    st(k.fld.phi[1 - sa.pc], n, phig);
+}
+template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typename P::R> k)
+{
+    fd_body<LAT, P>(k, xcd_tile((int)blockIdx.x, (int)gridDim.x), step_args(k));
+}
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void kb_fd(const KP<typename P::R> *tab, const int *prefix, int ninst, StepArgs sa)
+{
+    int inst, local;
+    batch_tile(prefix, ninst, inst, local);
+    fd_body<LAT, P>(tab[inst], local, sa);
 }
 
 // One colour half of a red-black SOR sweep of both implicit systems
@@ -690,25 +755,24 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typen
 // small dispatch. The residual of a row before its update feeds a per-sweep
 // maximum (one atomic per block); a sweep whose previous maximum is within
 // tolerance returns at once.
-template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<typename P::R> k, int color, int sweep)
+template <int LAT, class P>
+__device__ __forceinline__ void sor_conv(const KP<typename P::R> &k, int color, int sweep, bool *conv)
 {
     using R = typename P::R;
-    using L = Lat<LAT>;
-    constexpr int D = L::D;
     // Convergence, from maxima over the residual slots (one per lane). With omega = 1
-    // the black rows are solved exactly by each black half-sweep, so the red residual
-    // before the red update of sweep s is the whole residual after sweep s-1: a black
-    // half-sweep is skipped once the red half before it found the system converged,
-    // and the red half of the next sweep too. Otherwise both colours of the previous
-    // sweep are tested.
-    bool conv[2] = {false, false};
+    // and no seam classes the black rows are solved exactly by each black half-sweep,
+    // so the red residual before the red update of sweep s is the whole residual after
+    // sweep s-1: a black half-sweep is skipped once the red half before it found the
+    // system converged, and the red half of the next sweep too. Otherwise the
+    // pre-update residuals of every row of the previous sweep are tested.
+    conv[0] = conv[1] = false;
     {
         const int lane = threadIdx.x & 63;
 #pragma unroll
         for (int fi = 0; fi < 2; ++fi) {
             const double b = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, RMAX_IDX, lane)));
             double r = -1.0;
-            if (k.omega == R(1)) {
+            if (k.sor_exact) {
                 // red of sweep s >= 2: test of sweep s-1; black of sweep s >= 1: test of sweep s
                 const int sw = color == 0 ? sweep - 1 : sweep;
                 if (sw >= 1) r = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, 2 * sw, lane)));
@@ -719,72 +783,237 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
             conv[fi] = r >= 0.0 && r <= (double)k.tol * b;
         }
     }
-    if (conv[0] && conv[1]) return;
-    const long long N = k.N;
-    const int nx = k.nx, ny = k.ny, nz = k.nz, hx = (nx + 1) >> 1;
+}
+
+// Node (x, y, z) lies on the last plane of an axis that is periodic with an odd
+// extent (a seam class of the SOR ordering, below).
+template <int D, class R> __device__ __forceinline__ bool on_seam(const KP<R> &k, int x, int y, int z)
+{
+    return ((k.seam & 1) && x == k.nx - 1) || ((k.seam & 2) && y == k.ny - 1) ||
+           (D == 3 && (k.seam & 4) && z == k.nz - 1);
+}
+
+// Operands of the implicit systems at this step, resolved once per workgroup.
+template <class R> struct SorOps {
+    const R *G1, *rN1;   // W = G^{n+1} + eps (psi) and X^{n+1} + eps from rhoN^{n+1} (phi)
+    R *psi, *phi;        // iterates (initial guess on entry)
+    const R *rhsP, *rhsF;
+    R eps, hdP, hdF, om;
+};
+template <class R> __device__ __forceinline__ SorOps<R> sor_ops(const KP<R> &k, const StepArgs &sa)
+{
+    SorOps<R> a;
+    a.G1 = k.fld.G[1 - sa.lev];
+    a.rN1 = k.fld.mac[1 - sa.lev] + 2 * k.N;
+    a.psi = k.fld.psi[1 - sa.pc];
+    a.phi = k.fld.phi[1 - sa.pc];
+    a.rhsP = k.fld.rhsP;
+    a.rhsF = k.fld.rhsF;
+    a.eps = k.fd_eps;
+    a.hdP = R(0.5) * k.Ds;
+    a.hdF = R(0.5) * k.Db;
+    a.om = k.omega;
+    return a;
+}
+
+// One SOR update of node (x, y, z) in both implicit systems (a converged system is
+// left alone), recording its pre-update residual and |rhs|.
+template <int LAT, class P>
+__device__ __forceinline__ void sor_node(const KP<typename P::R> &k, const SorOps<typename P::R> &a, int x, int y,
+                                         int z, const bool *conv, typename P::R *rloc, typename P::R *bloc)
+{
+    using R = typename P::R;
+    using L = Lat<LAT>;
+    constexpr int D = L::D;
+    const int nx = k.nx, ny = k.ny, nz = k.nz;
     const int sy = nx, sz = nx * ny;
-    const R *G1 = k.fld.G[1 - k.lev];
-    const R *rN1 = k.fld.mac[1 - k.lev] + 2 * N;
-    R *psi = k.fld.psi[1 - k.pc], *phi = k.fld.phi[1 - k.pc];
-    const R *rhsP = k.fld.rhsP, *rhsF = k.fld.rhsF;
-    const R eps = k.fd_eps, hdP = R(0.5) * k.Ds, hdF = R(0.5) * k.Db, om = k.omega;
-    R rloc[2] = {0, 0}, bloc[2] = {0, 0};
-    // tiles of 64 same-colour nodes along x by 4 rows, one z plane
-    const int tx = (hx + 63) >> 6, ty = (ny + 3) >> 2;
-    const int ntiles = tx * ty * nz;
-    const int li = threadIdx.x & 63, ly = threadIdx.x >> 6;
-    // the grid is a multiple of 8 or covers every tile once, so raw index mod 8 is the XCD
-    for (int raw = blockIdx.x; raw < ntiles; raw += gridDim.x) {
-        const int tile = xcd_tile(raw, ntiles);
-        const int bx = tile % tx, rest = tile / tx;
-        const int by = rest % ty, z = rest / ty;
-        const int y = by * 4 + ly;
-        const int x = 2 * (bx * 64 + li) + ((y + z + color) & 1);
-        if (x >= nx || y >= ny) continue;
-        const uint32_t n = (uint32_t)(x + sy * y + sz * z);
-        // face neighbours: periodic wrap, or the node itself across a wall (no flux)
-        uint32_t q[6];
-        q[0] = x > 0 ? n - 1 : (k.bc[0] ? n : n + (nx - 1));
-        q[1] = x < nx - 1 ? n + 1 : (k.bc[0] ? n : n - (nx - 1));
-        q[2] = y > 0 ? n - sy : (k.bc[1] ? n : n + sy * (ny - 1));
-        q[3] = y < ny - 1 ? n + sy : (k.bc[1] ? n : n - sy * (ny - 1));
-        if constexpr (D == 3) {
-            q[4] = z > 0 ? n - sz : (k.bc[2] ? n : n + sz * (nz - 1));
-            q[5] = z < nz - 1 ? n + sz : (k.bc[2] ? n : n - sz * (nz - 1));
-        }
-        if (!conv[0]) {
-            const R Wn = ld(G1, n) + eps;
-            R diag = Wn, off = 0;
-#pragma unroll
-            for (int f = 0; f < 2 * D; ++f) {
-                if (q[f] == n) continue;
-                const R wf = hdP * (R(0.5) * (Wn + (ld(G1, q[f]) + eps)));
-                diag += wf;
-                off += wf * ld((const R *)psi, q[f]);
-            }
-            const R rhs = ld(rhsP, n), c0 = ld((const R *)psi, n);
-            rloc[0] = fmax(rloc[0], fabs(rhs - (diag * c0 - off)));
-            bloc[0] = fmax(bloc[0], fabs(rhs));
-            st(psi, n, (R(1) - om) * c0 + om * (rhs + off) / diag);
-        }
-        if (!conv[1]) {
-            const R Wn = (R(1) - ld(rN1, n)) + eps;
-            R diag = Wn, off = 0;
-#pragma unroll
-            for (int f = 0; f < 2 * D; ++f) {
-                if (q[f] == n) continue;
-                const R wf = hdF * (R(0.5) * (Wn + ((R(1) - ld(rN1, q[f])) + eps)));
-                diag += wf;
-                off += wf * ld((const R *)phi, q[f]);
-            }
-            const R rhs = ld(rhsF, n), c0 = ld((const R *)phi, n);
-            rloc[1] = fmax(rloc[1], fabs(rhs - (diag * c0 - off)));
-            bloc[1] = fmax(bloc[1], fabs(rhs));
-            st(phi, n, (R(1) - om) * c0 + om * (rhs + off) / diag);
-        }
+    const R *G1 = a.G1, *rN1 = a.rN1;
+    R *psi = a.psi, *phi = a.phi;
+    const R *rhsP = a.rhsP, *rhsF = a.rhsF;
+    const R eps = a.eps, hdP = a.hdP, hdF = a.hdF, om = a.om;
+    const uint32_t n = (uint32_t)(x + sy * y + sz * z);
+    // face neighbours: periodic wrap, or the node itself across a wall (no flux)
+    uint32_t q[6];
+    q[0] = x > 0 ? n - 1 : (k.bc[0] ? n : n + (nx - 1));
+    q[1] = x < nx - 1 ? n + 1 : (k.bc[0] ? n : n - (nx - 1));
+    q[2] = y > 0 ? n - sy : (k.bc[1] ? n : n + sy * (ny - 1));
+    q[3] = y < ny - 1 ? n + sy : (k.bc[1] ? n : n - sy * (ny - 1));
+    if constexpr (D == 3) {
+        q[4] = z > 0 ? n - sz : (k.bc[2] ? n : n + sz * (nz - 1));
+        q[5] = z < nz - 1 ? n + sz : (k.bc[2] ? n : n - sz * (nz - 1));
     }
+    if (!conv[0]) {
+        const R Wn = ld(G1, n) + eps;
+        R diag = Wn, off = 0;
+#pragma unroll
+        for (int f = 0; f < 2 * D; ++f) {
+            if (q[f] == n) continue;
+            const R wf = hdP * (R(0.5) * (Wn + (ld(G1, q[f]) + eps)));
+            diag += wf;
+            off += wf * ld((const R *)psi, q[f]);
+        }
+        const R rhs = ld(rhsP, n), c0 = ld((const R *)psi, n);
+        rloc[0] = fmax(rloc[0], fabs(rhs - (diag * c0 - off)));
+        bloc[0] = fmax(bloc[0], fabs(rhs));
+        st(psi, n, (R(1) - om) * c0 + om * (rhs + off) / diag);
+    }
+    if (!conv[1]) {
+        const R Wn = (R(1) - ld(rN1, n)) + eps;
+        R diag = Wn, off = 0;
+#pragma unroll
+        for (int f = 0; f < 2 * D; ++f) {
+            if (q[f] == n) continue;
+            const R wf = hdF * (R(0.5) * (Wn + ((R(1) - ld(rN1, q[f])) + eps)));
+            diag += wf;
+            off += wf * ld((const R *)phi, q[f]);
+        }
+        const R rhs = ld(rhsF, n), c0 = ld((const R *)phi, n);
+        rloc[1] = fmax(rloc[1], fabs(rhs - (diag * c0 - off)));
+        bloc[1] = fmax(bloc[1], fabs(rhs));
+        st(phi, n, (R(1) - om) * c0 + om * (rhs + off) / diag);
+    }
+}
+
+// One tile (64 same-colour nodes along x by 4 rows, one z plane) of a colour half-sweep.
+// SEAM: the grid has seam classes (the test costs registers, so grids without are
+// served by a variant without it).
+template <int LAT, class P, bool SEAM>
+__device__ __forceinline__ void sor_tile(const KP<typename P::R> &k, const SorOps<typename P::R> &a, int tile,
+                                         int color, const bool *conv, typename P::R *rloc, typename P::R *bloc)
+{
+    const int hx = (k.nx + 1) >> 1;
+    const int tx = (hx + 63) >> 6, ty = (k.ny + 3) >> 2;
+    const int li = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int bx = tile % tx, rest = tile / tx;
+    const int by = rest % ty, z = rest / ty;
+    const int y = by * 4 + ly;
+    const int x = 2 * (bx * 64 + li) + ((y + z + color) & 1);
+    if (x >= k.nx || y >= k.ny) return;
+    if (SEAM && on_seam<Lat<LAT>::D>(k, x, y, z)) return;   // updated with its seam class
+    sor_node<LAT, P>(k, a, x, y, z, conv, rloc, bloc);
+}
+
+// Seam classes. On a periodic axis of odd extent the parity colouring wraps onto
+// itself: the first and the last plane hold face neighbours of the same parity.
+// Nodes on the last plane of such an axis leave the red and black half-sweeps;
+// after them they are updated by level (the number of such last planes the node
+// lies on), each level in two parity half-sweeps. Face neighbours differ in one
+// coordinate, so two nodes of one level and one parity are never neighbours:
+// each half-sweep is free of races and the order of all updates is fixed.
+// Index space of an instance: for each seam axis a in turn, its last plane, the
+// other two axes in increasing order with the lower one fastest.
+template <int LAT, class P>
+__device__ __forceinline__ void sor_seam_node(const KP<typename P::R> &k, const SorOps<typename P::R> &a, long long t,
+                                              int level, int color, const bool *conv, typename P::R *rloc,
+                                              typename P::R *bloc)
+{
+    constexpr int D = Lat<LAT>::D;
+    const int ext[3] = {k.nx, k.ny, k.nz};
+    int axis = -1;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (axis >= 0 || !((k.seam >> a) & 1)) continue;
+        const long long plane = k.N / ext[a];
+        if (t < plane) axis = a;
+        else t -= plane;
+    }
+    if (axis < 0) return;
+    const int b0 = axis == 0 ? 1 : 0, b1 = axis == 2 ? 1 : 2;
+    int c[3];
+    c[axis] = ext[axis] - 1;
+    c[b0] = (int)(t % ext[b0]);
+    c[b1] = (int)(t / ext[b0]);
+    int lv = 0, lowest = -1;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        if (((k.seam >> a) & 1) && c[a] == ext[a] - 1) {
+            ++lv;
+            if (lowest < 0) lowest = a;
+        }
+    // a node on several last planes is visited once, from its lowest seam axis
+    if (lv != level || lowest != axis || ((c[0] + c[1] + c[2]) & 1) != color) return;
+    sor_node<LAT, P>(k, a, c[0], c[1], c[2], conv, rloc, bloc);
+}
+
+// Number of tiles of one colour of a half-sweep.
+template <class R> __host__ __device__ inline int sor_ntiles(const KP<R> &k)
+{
+    return (((k.nx + 1) / 2 + 63) / 64) * ((k.ny + 3) / 4) * k.nz;
+}
+
+// One colour half of a red-black SOR sweep of both implicit systems
+// [W - (Dc/2) L_W] chi = rhs with W = G^{n+1} + eps (psi) and X^{n+1} + eps (phi).
+// Persistent grid-stride kernel over the nodes of one colour (x = 2i + parity),
+// so every lane updates a node and a sweep that is already converged costs one
+// small dispatch. The residual of a row before its update feeds a per-sweep
+// maximum (one atomic per block); a sweep whose previous maximum is within
+// tolerance returns at once.
+template <int LAT, class P, bool SEAM>
+__global__ __launch_bounds__(256) void k_sor(KP<typename P::R> k, int color, int sweep)
+{
+    using R = typename P::R;
+    bool conv[2];
+    sor_conv<LAT, P>(k, color, sweep, conv);
+    if (conv[0] && conv[1]) return;
+    R rloc[2] = {0, 0}, bloc[2] = {0, 0};
+    const int ntiles = sor_ntiles(k);
+    const SorOps<R> a = sor_ops(k, step_args(k));
+    // the grid is a multiple of 8 or covers every tile once, so raw index mod 8 is the XCD
+    for (int raw = blockIdx.x; raw < ntiles; raw += gridDim.x)
+        sor_tile<LAT, P, SEAM>(k, a, xcd_tile(raw, ntiles), color, conv, rloc, bloc);
     // block maxima of the pre-update residuals of this colour half-sweep; max |rhs| over
     // the rows of both colours during sweep 0 (no convergence test reads it before sweep 1)
+    block_max_to_slots(conv[0] ? R(-1) : rloc[0], conv[1] ? R(-1) : rloc[1], k.fld.sorres, 2 * sweep + color);
+    if (sweep == 0) block_max_to_slots(bloc[0], bloc[1], k.fld.sorres, RMAX_IDX);
+}
+
+// The same half-sweep for a batch of instances: one workgroup per tile of one instance.
+template <int LAT, class P, bool SEAM>
+__global__ __launch_bounds__(256) void kb_sor(const KP<typename P::R> *tab, const int *prefix, int ninst, StepArgs sa,
+                                             int color, int sweep)
+{
+    using R = typename P::R;
+    int inst, local;
+    batch_tile(prefix, ninst, inst, local);
+    const KP<R> &k = tab[inst];
+    bool conv[2];
+    sor_conv<LAT, P>(k, color, sweep, conv);
+    if (conv[0] && conv[1]) return;
+    R rloc[2] = {0, 0}, bloc[2] = {0, 0};
+    sor_tile<LAT, P, SEAM>(k, sor_ops(k, sa), local, color, conv, rloc, bloc);
+    block_max_to_slots(conv[0] ? R(-1) : rloc[0], conv[1] ? R(-1) : rloc[1], k.fld.sorres, 2 * sweep + color);
+    if (sweep == 0) block_max_to_slots(bloc[0], bloc[1], k.fld.sorres, RMAX_IDX);
+}
+
+// One parity half-sweep of one seam level (one thread per entry of the seam index space).
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void k_sor_seam(KP<typename P::R> k, int level, int color, int sweep)
+{
+    using R = typename P::R;
+    bool conv[2];
+    sor_conv<LAT, P>(k, color, sweep, conv);
+    if (conv[0] && conv[1]) return;
+    R rloc[2] = {0, 0}, bloc[2] = {0, 0};
+    sor_seam_node<LAT, P>(k, sor_ops(k, step_args(k)), (long long)blockIdx.x * 256 + threadIdx.x, level, color, conv,
+                          rloc, bloc);
+    block_max_to_slots(conv[0] ? R(-1) : rloc[0], conv[1] ? R(-1) : rloc[1], k.fld.sorres, 2 * sweep + color);
+    if (sweep == 0) block_max_to_slots(bloc[0], bloc[1], k.fld.sorres, RMAX_IDX);
+}
+
+// The same for a batch: instance i owns workgroups prefix[i] .. prefix[i+1]-1.
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void kb_sor_seam(const KP<typename P::R> *tab, const int *prefix, int ninst,
+                                                  StepArgs sa, int level, int color, int sweep)
+{
+    using R = typename P::R;
+    int inst, local;
+    batch_tile(prefix, ninst, inst, local);
+    const KP<R> &k = tab[inst];
+    bool conv[2];
+    sor_conv<LAT, P>(k, color, sweep, conv);
+    if (conv[0] && conv[1]) return;
+    R rloc[2] = {0, 0}, bloc[2] = {0, 0};
+    sor_seam_node<LAT, P>(k, sor_ops(k, sa), (long long)local * 256 + threadIdx.x, level, color, conv, rloc, bloc);
     block_max_to_slots(conv[0] ? R(-1) : rloc[0], conv[1] ? R(-1) : rloc[1], k.fld.sorres, 2 * sweep + color);
     if (sweep == 0) block_max_to_slots(bloc[0], bloc[1], k.fld.sorres, RMAX_IDX);
 }
@@ -792,7 +1021,7 @@ template <int LAT, class P> __global__ __launch_bounds__(256) void k_sor(KP<type
 // Sweep counts of the last solve; LBFD_ESOR when a system never met its tolerance.
 // One wavefront: lane l reads residual slot l. Afterwards it clears the slots of
 // every half-sweep and of the |rhs| maxima for the next step.
-template <class R> __global__ void k_sor_done(KP<R> k, int nsw)
+template <class R> __device__ __forceinline__ void sor_done_body(const KP<R> &k, int nsw)
 {
     DevScalars *sc = k.fld.sc;
     const int lane = threadIdx.x & 63;
@@ -801,7 +1030,7 @@ template <class R> __global__ void k_sor_done(KP<R> k, int nsw)
         const double lim = (double)k.tol * rm;
         int K = nsw;
         bool ok = false;
-        if (k.omega == R(1)) {
+        if (k.sor_exact) {
             // whole residual after s sweeps = red residual at the start of sweep s
             for (int s = 1; s < nsw; ++s) {
                 const double r = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, 2 * s, lane)));
@@ -821,6 +1050,12 @@ template <class R> __global__ void k_sor_done(KP<R> k, int nsw)
         }
     }
     sor_slots_clear(k.fld.sorres, nsw);
+}
+template <class R> __global__ void k_sor_done(KP<R> k, int nsw) { sor_done_body(k, nsw); }
+// batch: one wavefront per instance
+template <class R> __global__ void kb_sor_done(const KP<R> *tab, int nsw)
+{
+    sor_done_body(tab[blockIdx.x], nsw);
 }
 
 // Clears the residual and |rhs| slots (set-up, before the first step).
@@ -849,20 +1084,35 @@ template <int NV> __device__ __forceinline__ void block_sum_store(double (&v)[NV
 // Per-block FP64 sums of G psi + X phi (the conserved integrand of eqs 20-21)
 // at `level`, psi/phi from buffer `buf` times `mult`.
 template <int LAT, class P>
-__global__ __launch_bounds__(256) void k_total_part(KP<typename P::R> k, int level, int buf, double mult)
+__device__ __forceinline__ void total_part_body(const KP<typename P::R> &k, int level, int buf, double mult, int blk,
+                                                int nblk)
 {
     using R = typename P::R;
     const long long N = k.N;
     double v[1] = {0.0};
-    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    for (long long n = (long long)blk * blockDim.x + threadIdx.x; n < N; n += (long long)nblk * blockDim.x) {
         double G = (double)(k.fld.G[level][n] + k.fd_eps);
         double X = (double)((R(1) - k.fld.mac[level][2 * N + n]) + k.fd_eps);
         double ps = mult * (double)k.fld.psi[buf][n], ph = mult * (double)k.fld.phi[buf][n];
         v[0] += G * ps + X * ph;
     }
-    block_sum_store<1>(v, k.fld.part + blockIdx.x);
+    block_sum_store<1>(v, k.fld.part + blk);
 }
-template <class R> __global__ void k_total_final(KP<R> k, long long nblocks, int mode)
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void k_total_part(KP<typename P::R> k, int level, int buf, double mult)
+{
+    total_part_body<LAT, P>(k, level, buf, mult, (int)blockIdx.x, (int)gridDim.x);
+}
+// batch: instance i owns workgroups prefix[i] .. prefix[i+1]-1
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void kb_total_part(const KP<typename P::R> *tab, const int *prefix, int ninst,
+                                                    int level, int buf, double mult)
+{
+    int inst, local;
+    batch_tile(prefix, ninst, inst, local);
+    total_part_body<LAT, P>(tab[inst], level, buf, mult, local, prefix[inst + 1] - prefix[inst]);
+}
+template <class R> __device__ __forceinline__ void total_final_body(const KP<R> &k, long long nblocks, int mode)
 {
     __shared__ double sh[256];
     const int t = threadIdx.x;
@@ -891,6 +1141,12 @@ template <class R> __global__ void k_total_final(KP<R> k, long long nblocks, int
             if (!isfinite(M) && sc->status == 0) sc->status = LBFD_ENONFINITE;
         }
     }
+}
+template <class R> __global__ void k_total_final(KP<R> k, long long nblocks, int mode) { total_final_body(k, nblocks, mode); }
+template <class R> __global__ void kb_total_final(const KP<R> *tab, const int *prefix, int mode)
+{
+    const int i = blockIdx.x;
+    total_final_body(tab[i], (long long)(prefix[i + 1] - prefix[i]), mode);
 }
 
 // Observables, pass 0: sums and extrema; pass 1: central second moments.
@@ -1055,14 +1311,32 @@ struct lbfd_handle {
     KP<float> kf;
     dim3 grid, block;
     long long nblocks;
+    int tblocks;        // workgroups of the total-surfactant sum
     int sweeps_launch;
     long long fd_hist;  // FD steps since the state was set (extrapolated guess needs one)
     int sor_blocks;     // persistent grid of the SOR sweeps
+    int seam_tiles;     // workgroups over the seam index space (0: no seam classes)
+    int seam_levels;    // seam levels (periodic axes of odd extent)
     bool prof;
     unsigned prof_mask;  // kernel classes timed when profiling (bit per class)
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     double *obs_out;  // device, NRED doubles (inside the workspace)
+};
+
+// A batch: independent instances (ordinary handles on slices of one workspace)
+// advanced together, one launch per kernel class for all of them.
+struct lbfd_batch {
+    int n;
+    std::vector<lbfd_handle *> inst;
+    hipStream_t stream;
+    void *tab;          // device table of the instances' kernel parameter blocks
+    int *prefix_node;   // device: first node tile of each instance (n + 1 entries)
+    int *prefix_sor;    // device: first half-sweep tile of each instance (n + 1 entries)
+    int *prefix_total;  // device: first total-sum workgroup of each instance (n + 1 entries)
+    int *prefix_seam;   // device: first seam workgroup of each instance (n + 1 entries)
+    dim3 grid_node, grid_sor, grid_total, grid_seam;
+    int seam_levels;    // most seam levels of any instance
 };
 
 namespace {
@@ -1150,6 +1424,35 @@ template <class Tab> void rest_weights(double al, double cs2, double *out)
     }
 }
 
+// Axes that are periodic with an odd extent above one (bit a): their last planes
+// form the seam classes of the SOR ordering.
+int seam_axes(const lbfd_params *p)
+{
+    const int ext[3] = {p->nx, p->ny, p->nz};
+    const int D = p->lattice == LBFD_D3Q19 ? 3 : 2;
+    int m = 0;
+    for (int a = 0; a < D; ++a)
+        if (p->bc[a] == LBFD_PERIODIC && ext[a] > 1 && (ext[a] & 1)) m |= 1 << a;
+    return m;
+}
+
+// Workgroups of 256 over the seam index space, and the number of seam levels.
+void seam_shape(const lbfd_params *p, int *tiles, int *levels)
+{
+    const int m = seam_axes(p);
+    const long long N = (long long)p->nx * p->ny * p->nz;
+    const int ext[3] = {p->nx, p->ny, p->nz};
+    long long S = 0;
+    int lv = 0;
+    for (int a = 0; a < 3; ++a)
+        if ((m >> a) & 1) {
+            S += N / ext[a];
+            ++lv;
+        }
+    *tiles = (int)((S + 255) / 256);
+    *levels = lv;
+}
+
 template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const Layout &Lo)
 {
     const bool three = p->lattice == LBFD_D3Q19;
@@ -1205,6 +1508,8 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
     for (int a = 0; a < 3; ++a) k.grav[a] = (R)p->gravity[a];
     k.omega = (R)p->sor_omega;
     k.tol = (R)p->sor_tol;
+    k.seam = seam_axes(p);
+    k.sor_exact = (p->sor_omega == 1.0 && k.seam == 0) ? 1 : 0;
     k.weno_eps = (R)p->weno_eps;
     k.eps_n = (R)p->eps_n;
     k.fd_eps = (R)p->fd_eps;
@@ -1296,8 +1601,8 @@ template <int LAT, class P> struct Impl {
     static void totals(lbfd_handle *h, int level, int buf, double mult, int mode)
     {
         KP<R> &k = kp(h);
-        LAUNCH(KC_TOTAL, (k_total_part<LAT, P>), dim3(TOTAL_BLOCKS), dim3(256), k, level, buf, mult);
-        LAUNCH(KC_TOTAL, (k_total_final<R>), dim3(1), dim3(256), k, (long long)TOTAL_BLOCKS, mode);
+        LAUNCH(KC_TOTAL, (k_total_part<LAT, P>), dim3(h->tblocks), dim3(256), k, level, buf, mult);
+        LAUNCH(KC_TOTAL, (k_total_final<R>), dim3(1), dim3(256), k, (long long)h->tblocks, mode);
     }
 
     static void derived(lbfd_handle *h)
@@ -1386,8 +1691,17 @@ template <int LAT, class P> struct Impl {
             if (h->p.fd_enable) {
                 LAUNCH(KC_FD, (k_fd<LAT, P>), h->grid, h->block, k);
                 for (int s = 0; s < h->sweeps_launch; ++s) {
-                    LAUNCH(KC_SOR, (k_sor<LAT, P>), dim3(h->sor_blocks), dim3(256), k, 0, s);
-                    LAUNCH(KC_SOR, (k_sor<LAT, P>), dim3(h->sor_blocks), dim3(256), k, 1, s);
+                    if (h->seam_levels == 0) {
+                        LAUNCH(KC_SOR, (k_sor<LAT, P, false>), dim3(h->sor_blocks), dim3(256), k, 0, s);
+                        LAUNCH(KC_SOR, (k_sor<LAT, P, false>), dim3(h->sor_blocks), dim3(256), k, 1, s);
+                        continue;
+                    }
+                    LAUNCH(KC_SOR, (k_sor<LAT, P, true>), dim3(h->sor_blocks), dim3(256), k, 0, s);
+                    LAUNCH(KC_SOR, (k_sor<LAT, P, true>), dim3(h->sor_blocks), dim3(256), k, 1, s);
+                    for (int lv = 1; lv <= h->seam_levels; ++lv) {
+                        LAUNCH(KC_SOR, (k_sor_seam<LAT, P>), dim3(h->seam_tiles), dim3(256), k, lv, 0, s);
+                        LAUNCH(KC_SOR, (k_sor_seam<LAT, P>), dim3(h->seam_tiles), dim3(256), k, lv, 1, s);
+                    }
                 }
                 LAUNCH(KC_OTHER, (k_sor_done<R>), dim3(1), dim3(64), k, h->sweeps_launch);
                 totals(h, 1 - k.lev, 1 - k.pc, 1.0, 1);
@@ -1400,6 +1714,79 @@ template <int LAT, class P> struct Impl {
             LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
         }
         return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    // One step for every instance of a batch: the same sequence as step(), each
+    // kernel class launched once over the tiles of all instances.
+    static int batch_step(lbfd_batch *b, long long nsteps)
+    {
+        lbfd_handle *h = b->inst[0];   // time levels are common; profiling goes to instance 0
+        const KP<R> *tab = (const KP<R> *)b->tab;
+        const int n = b->n;
+        const dim3 blk(BX, BY, 1);
+        for (long long t = 0; t < nsteps; ++t) {
+            StepArgs sa;
+            sa.lev = (int)(h->step & 1);
+            sa.fc = h->fc;
+            sa.pc = h->pc;
+            sa.extrap = h->fd_hist >= 1 ? 1 : 0;
+            sa.step = h->step;
+            LAUNCH(KC_COLLIDE, (kb_collide<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sa);
+            LAUNCH(KC_MACRO, (kb_macro<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sa);
+            LAUNCH(KC_GEOM, (kb_geom<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sa, 1 - sa.lev);
+            const bool fd = h->p.fd_enable != 0;
+            if (fd) {
+                LAUNCH(KC_FD, (kb_fd<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sa);
+                for (int s = 0; s < h->sweeps_launch; ++s) {
+                    if (b->seam_levels == 0) {
+                        LAUNCH(KC_SOR, (kb_sor<LAT, P, false>), b->grid_sor, dim3(256), tab, b->prefix_sor, n, sa, 0, s);
+                        LAUNCH(KC_SOR, (kb_sor<LAT, P, false>), b->grid_sor, dim3(256), tab, b->prefix_sor, n, sa, 1, s);
+                        continue;
+                    }
+                    LAUNCH(KC_SOR, (kb_sor<LAT, P, true>), b->grid_sor, dim3(256), tab, b->prefix_sor, n, sa, 0, s);
+                    LAUNCH(KC_SOR, (kb_sor<LAT, P, true>), b->grid_sor, dim3(256), tab, b->prefix_sor, n, sa, 1, s);
+                    for (int lv = 1; lv <= b->seam_levels; ++lv) {
+                        LAUNCH(KC_SOR, (kb_sor_seam<LAT, P>), b->grid_seam, dim3(256), tab, b->prefix_seam, n, sa, lv,
+                               0, s);
+                        LAUNCH(KC_SOR, (kb_sor_seam<LAT, P>), b->grid_seam, dim3(256), tab, b->prefix_seam, n, sa, lv,
+                               1, s);
+                    }
+                }
+                LAUNCH(KC_OTHER, (kb_sor_done<R>), dim3(n), dim3(64), tab, h->sweeps_launch);
+                LAUNCH(KC_TOTAL, (kb_total_part<LAT, P>), b->grid_total, dim3(256), tab, b->prefix_total, n,
+                       1 - sa.lev, 1 - sa.pc, 1.0);
+                LAUNCH(KC_TOTAL, (kb_total_final<R>), dim3(n), dim3(256), tab, b->prefix_total, 1);
+            }
+            for (lbfd_handle *x : b->inst) {
+                if (fd) {
+                    x->pc = 1 - x->pc;
+                    x->fd_hist += 1;
+                }
+                x->fc = 1 - x->fc;
+                x->step += 1;
+                sync_levels(x);
+            }
+            StepArgs sb;
+            sb.lev = (int)(h->step & 1);
+            sb.fc = h->fc;
+            sb.pc = h->pc;
+            sb.extrap = h->fd_hist >= 1 ? 1 : 0;
+            sb.step = h->step;
+            LAUNCH(KC_FORCE, (kb_force<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sb);
+        }
+        return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    // Upload the instances' parameter blocks (per-step selectors are passed per launch).
+    static int batch_table(lbfd_batch *b)
+    {
+        std::vector<KP<R>> host(b->n);
+        for (int i = 0; i < b->n; ++i) {
+            sync_levels(b->inst[i]);
+            host[i] = kp(b->inst[i]);
+        }
+        if (hipMemcpy(b->tab, host.data(), sizeof(KP<R>) * b->n, hipMemcpyHostToDevice) != hipSuccess) return LBFD_EHIP;
+        return LBFD_OK;
     }
 
     static int observables(lbfd_handle *h, lbfd_obs *o)
@@ -1499,12 +1886,16 @@ struct Dispatch {
     int (*step)(lbfd_handle *, long long);
     int (*observables)(lbfd_handle *, lbfd_obs *);
     int (*read_field)(lbfd_handle *, int, double *, size_t);
+    int (*batch_step)(lbfd_batch *, long long);
+    int (*batch_table)(lbfd_batch *);
+    size_t kp_bytes;
 };
 
 template <int LAT, class P> Dispatch make_dispatch()
 {
-    return Dispatch{&Impl<LAT, P>::init, &Impl<LAT, P>::set_state, &Impl<LAT, P>::step, &Impl<LAT, P>::observables,
-                    &Impl<LAT, P>::read_field};
+    return Dispatch{&Impl<LAT, P>::init,        &Impl<LAT, P>::set_state,  &Impl<LAT, P>::step,
+                    &Impl<LAT, P>::observables, &Impl<LAT, P>::read_field, &Impl<LAT, P>::batch_step,
+                    &Impl<LAT, P>::batch_table, sizeof(KP<typename P::R>)};
 }
 
 Dispatch dispatch_for(int lat, int prec)
@@ -1570,6 +1961,8 @@ int lbfd_create(const lbfd_params *p, void *d_workspace, size_t bytes, void *str
     h->block = dim3(BX, BY, 1);
     h->nblocks = (long long)((p->nx + BX - 1) / BX) * ((p->ny + BY - 1) / BY) * p->nz;
     h->grid = dim3((unsigned)h->nblocks);
+    h->tblocks = total_blocks(h->N);
+    seam_shape(p, &h->seam_tiles, &h->seam_levels);
     h->sweeps_launch = p->sor_max_sweeps;
     {
         // tiles of one colour (64 x 4 nodes), capped at 8 workgroups of 256 per compute unit
@@ -1678,6 +2071,126 @@ void lbfd_destroy(lbfd_handle *h)
     for (auto &r : h->recs) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
     for (auto e : h->pool) hipEventDestroy(e);
     delete h;
+}
+
+// ------------------------------------------------------------------ batches
+
+static int batch_layout(const lbfd_params *p, int32_t n, std::vector<size_t> *offs, size_t *tab_off, size_t *pre_off,
+                        size_t *total)
+{
+    if (!p || n < 1 || n > 65536) return LBFD_EINVAL;
+    size_t o = 0;
+    long long node_tiles = 0, sor_tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        int st = check_params(&p[i]);
+        if (st != LBFD_OK) return st;
+        if (p[i].lattice != p[0].lattice || p[i].precision != p[0].precision || p[i].fd_enable != p[0].fd_enable ||
+            p[i].sor_max_sweeps != p[0].sor_max_sweeps)
+            return LBFD_EINVAL;
+        if (offs) offs->push_back(o);
+        o += align256(layout(&p[i]).total);
+        node_tiles += (long long)((p[i].nx + BX - 1) / BX) * ((p[i].ny + BY - 1) / BY) * p[i].nz;
+        sor_tiles += (long long)(((p[i].nx + 1) / 2 + 63) / 64) * ((p[i].ny + 3) / 4) * p[i].nz;
+    }
+    // one launch covers the tiles of all instances: 256 lanes per tile, 32-bit lane ids
+    if (node_tiles * 256 > (long long)UINT32_MAX || sor_tiles * 256 > (long long)UINT32_MAX) return LBFD_EINVAL;
+    const size_t kpb = dispatch_for(p[0].lattice, p[0].precision).kp_bytes;
+    *tab_off = o;
+    o += align256(kpb * (size_t)n);
+    *pre_off = o;
+    o += align256(sizeof(int) * 4 * ((size_t)n + 1));
+    *total = o;
+    return LBFD_OK;
+}
+
+int lbfd_batch_workspace_bytes(const lbfd_params *p, int32_t n, size_t *bytes)
+{
+    if (!bytes) return LBFD_EINVAL;
+    size_t t, pr, tot;
+    int st = batch_layout(p, n, nullptr, &t, &pr, &tot);
+    if (st != LBFD_OK) return st;
+    *bytes = tot;
+    return LBFD_OK;
+}
+
+void lbfd_batch_destroy(lbfd_batch *b)
+{
+    if (!b) return;
+    for (lbfd_handle *h : b->inst) lbfd_destroy(h);
+    delete b;
+}
+
+int lbfd_batch_create(const lbfd_params *p, int32_t n, void *d_workspace, size_t bytes, void *stream, lbfd_batch **out)
+{
+    if (!out) return LBFD_EINVAL;
+    *out = nullptr;
+    std::vector<size_t> offs;
+    size_t tab_off, pre_off, total;
+    int st = batch_layout(p, n, &offs, &tab_off, &pre_off, &total);
+    if (st != LBFD_OK) return st;
+    if (!d_workspace || bytes < total || ((uintptr_t)d_workspace & 255) != 0) return LBFD_EWORKSPACE;
+    lbfd_batch *b = new (std::nothrow) lbfd_batch();
+    if (!b) return LBFD_ENOMEM;
+    b->n = n;
+    b->stream = (hipStream_t)stream;
+    char *ws = (char *)d_workspace;
+    std::vector<int> pn(n + 1), ps(n + 1), pt(n + 1), pm(n + 1);
+    pn[0] = ps[0] = pt[0] = pm[0] = 0;
+    b->seam_levels = 0;
+    for (int i = 0; i < n; ++i) {
+        lbfd_handle *h = nullptr;
+        st = lbfd_create(&p[i], ws + offs[i], layout(&p[i]).total, stream, &h);
+        if (st != LBFD_OK) {
+            lbfd_batch_destroy(b);
+            return st;
+        }
+        b->inst.push_back(h);
+        const long long hx = (p[i].nx + 1) / 2;
+        pn[i + 1] = pn[i] + (int)h->nblocks;
+        ps[i + 1] = ps[i] + (int)(((hx + 63) / 64) * ((p[i].ny + 3) / 4) * (long long)p[i].nz);
+        pt[i + 1] = pt[i] + h->tblocks;
+        pm[i + 1] = pm[i] + h->seam_tiles;
+        if (h->seam_levels > b->seam_levels) b->seam_levels = h->seam_levels;
+    }
+    b->tab = ws + tab_off;
+    b->prefix_node = (int *)(ws + pre_off);
+    b->prefix_sor = b->prefix_node + (n + 1);
+    b->prefix_total = b->prefix_sor + (n + 1);
+    b->prefix_seam = b->prefix_total + (n + 1);
+    b->grid_node = dim3((unsigned)pn[n]);
+    b->grid_sor = dim3((unsigned)ps[n]);
+    b->grid_total = dim3((unsigned)pt[n]);
+    b->grid_seam = dim3((unsigned)pm[n]);
+    if (hipMemcpy(b->prefix_node, pn.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->prefix_sor, ps.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->prefix_total, pt.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->prefix_seam, pm.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice) != hipSuccess) {
+        lbfd_batch_destroy(b);
+        return LBFD_EHIP;
+    }
+    st = dispatch_for(p[0].lattice, p[0].precision).batch_table(b);
+    if (st != LBFD_OK) {
+        lbfd_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return LBFD_OK;
+}
+
+lbfd_handle *lbfd_batch_instance(lbfd_batch *b, int32_t i)
+{
+    if (!b || i < 0 || i >= b->n) return nullptr;
+    return b->inst[i];
+}
+
+int lbfd_batch_step(lbfd_batch *b, int64_t n)
+{
+    if (!b || n < 0) return LBFD_EINVAL;
+    lbfd_handle *h0 = b->inst[0];
+    for (lbfd_handle *h : b->inst)
+        if (h->step != h0->step || h->fc != h0->fc || h->pc != h0->pc || h->fd_hist != h0->fd_hist)
+            return LBFD_EINVAL;
+    return dispatch_for(h0->p.lattice, h0->p.precision).batch_step(b, n);
 }
 
 const char *lbfd_strerror(int s)

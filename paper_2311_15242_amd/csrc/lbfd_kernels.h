@@ -162,6 +162,8 @@ template <class R> struct KP {
     R grav[3];
     R omega;
     R tol;
+    int seam;           // periodic axes of odd extent (bit a): seam classes of the SOR ordering
+    int sor_exact;      // omega = 1 without seam classes: the red residual is the whole residual
     R weno_eps, eps_n;
     R fd_eps;           // background support of the FD weights
     R upwind_eps;       // |u_a| band with upwind weights 1/2
@@ -190,18 +192,55 @@ __device__ __forceinline__ int xcd_tile(int i, int n)
     return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
 }
 
-// Node of this thread: a 1-D launch of gx * gy * nz tiles of blockDim.x by
-// blockDim.y nodes (x fastest), in XCD-aware order.
-template <class R> __device__ __forceinline__ Node node_id(const KP<R> &k)
+// Node of this thread in tile t of the gx * gy * nz tiles of blockDim.x by
+// blockDim.y nodes (x fastest).
+template <class R> __device__ __forceinline__ Node node_at(const KP<R> &k, int t)
 {
     Node n;
-    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int bx = t % k.gx, r = t / k.gx;
     n.x = bx * blockDim.x + threadIdx.x;
     n.y = (r % k.gy) * blockDim.y + threadIdx.y;
     n.z = r / k.gy;
     n.ok = n.x < k.nx && n.y < k.ny;
     return n;
+}
+
+// Node of this thread in a 1-D launch over all tiles, in XCD-aware order.
+template <class R> __device__ __forceinline__ Node node_id(const KP<R> &k)
+{
+    return node_at(k, xcd_tile((int)blockIdx.x, (int)gridDim.x));
+}
+
+// Time-level selectors shared by every instance of a batch at a step.
+struct StepArgs {
+    int lev, fc, pc, extrap;
+    long long step;
+};
+template <class R> __device__ __forceinline__ StepArgs step_args(const KP<R> &k)
+{
+    StepArgs s;
+    s.lev = k.lev;
+    s.fc = k.fc;
+    s.pc = k.pc;
+    s.extrap = k.extrap;
+    s.step = k.step;
+    return s;
+}
+
+// Instance and local tile of this workgroup in a batched launch: the tiles of all
+// instances are numbered consecutively (prefix[i] = first tile of instance i,
+// prefix[ninst] = total), in XCD-aware order over the whole range.
+__device__ __forceinline__ void batch_tile(const int *prefix, int ninst, int &inst, int &local)
+{
+    const int g = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    int lo = 0, hi = ninst;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    inst = lo;
+    local = g - prefix[lo];
 }
 
 template <class R> __device__ __forceinline__ long long lin(const KP<R> &k, int x, int y, int z)

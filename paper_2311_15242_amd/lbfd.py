@@ -18,7 +18,8 @@ PRECISION = {"fp64": 0, "fp32": 1, "fp16dev": 2, "bf16dev": 3}
 FIELDS = dict(f=0, rhoR=3, rhoB=4, rhoN=5, u=6, psi=7, phi=8, force=9, G=10, Sprev=11, Bprev=12)
 EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_init_fields", "lbfd_set_state", "lbfd_step",
             "lbfd_observables", "lbfd_read_field", "lbfd_profile", "lbfd_profile_read", "lbfd_destroy",
-            "lbfd_strerror"]
+            "lbfd_strerror", "lbfd_batch_workspace_bytes", "lbfd_batch_create", "lbfd_batch_instance",
+            "lbfd_batch_step", "lbfd_batch_destroy"]
 
 
 class LbfdError(RuntimeError):
@@ -95,6 +96,13 @@ def load(build_if_missing: bool = False):
     L.lbfd_destroy.restype = None
     L.lbfd_strerror.argtypes = [C.c_int]
     L.lbfd_strerror.restype = C.c_char_p
+    L.lbfd_batch_workspace_bytes.argtypes = [P(Params), C.c_int32, P(C.c_size_t)]
+    L.lbfd_batch_create.argtypes = [P(Params), C.c_int32, vp, C.c_size_t, vp, P(vp)]
+    L.lbfd_batch_instance.argtypes = [vp, C.c_int32]
+    L.lbfd_batch_instance.restype = vp
+    L.lbfd_batch_step.argtypes = [vp, C.c_int64]
+    L.lbfd_batch_destroy.argtypes = [vp]
+    L.lbfd_batch_destroy.restype = None
     _lib = L
     return L
 
@@ -146,40 +154,19 @@ def workspace_bytes(params: dict) -> int:
     return int(n.value)
 
 
-class Solver:
-    """One solver instance on one device: ``Solver(params).init_fields(init).step(n)``.
+class _Instance:
+    """Calls shared by a standalone solver and a member of a batch.
 
     Fields come back as FP64 numpy arrays of shape (nz, ny, nx), with a leading
     Q or D axis for populations and vectors."""
 
-    def __init__(self, params: dict, device: str = "cuda:0", stream=None):
-        import torch
-
+    def _bind(self, params: dict, h):
         self.p = dict(params)
-        self._ps = params_struct(self.p)
-        L = load()
-        nbytes = workspace_bytes(self.p)
-        self.device = torch.device(device)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        ptr = (base + 255) & ~255
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        h = C.c_void_p()
-        _check(L.lbfd_create(C.byref(self._ps), C.c_void_p(ptr), C.c_size_t(nbytes),
-                             C.c_void_p(self.stream.cuda_stream), C.byref(h)), "lbfd_create")
         self.h = h
         self.Q = 19 if self.p["lattice"] == 1 else 9
         self.D = 3 if self.p["lattice"] == 1 else 2
         self.shape = (int(self.p["nz"]), int(self.p["ny"]), int(self.p["nx"]))
         self.N = int(np.prod(self.shape))
-
-    def close(self):
-        if getattr(self, "h", None) and _lib is not None:
-            _lib.lbfd_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        self.close()
 
     def init_fields(self, init: dict):
         _check(load().lbfd_init_fields(self.h, C.byref(init_struct(init))), "lbfd_init_fields")
@@ -199,10 +186,6 @@ class Solver:
         _check(load().lbfd_set_state(self.h, ptr(f, self.Q * N), ptr(rhoR, N), ptr(rhoB, N), ptr(psi, N),
                                      ptr(phi, N), ptr(Sprev, N), ptr(Bprev, N), int(step), float(M0)),
                "lbfd_set_state")
-        return self
-
-    def step(self, n: int = 1):
-        _check(load().lbfd_step(self.h, int(n)), "lbfd_step")
         return self
 
     def observables(self, check=True) -> dict:
@@ -243,3 +226,97 @@ class Solver:
         _check(load().lbfd_profile_read(self.h, 16, names, ms.ctypes.data_as(C.POINTER(C.c_double)),
                                         cnt.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(nk)), "lbfd_profile_read")
         return {names[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(nk.value)}
+
+
+class Solver(_Instance):
+    """One solver instance on one device: ``Solver(params).init_fields(init).step(n)``."""
+
+    def __init__(self, params: dict, device: str = "cuda:0", stream=None):
+        import torch
+
+        self._ps = params_struct(params)
+        L = load()
+        nbytes = workspace_bytes(params)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        ptr = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L.lbfd_create(C.byref(self._ps), C.c_void_p(ptr), C.c_size_t(nbytes),
+                             C.c_void_p(self.stream.cuda_stream), C.byref(h)), "lbfd_create")
+        self._bind(params, h)
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.lbfd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self, n: int = 1):
+        _check(load().lbfd_step(self.h, int(n)), "lbfd_step")
+        return self
+
+
+class BatchMember(_Instance):
+    """Instance i of a Batch: initialised, observed and read like a Solver,
+    advanced only through Batch.step (its handle belongs to the batch)."""
+
+    def __init__(self, batch: "Batch", i: int, params: dict, h):
+        self.batch = batch
+        self.index = i
+        self._bind(params, h)
+
+
+class Batch:
+    """Independent instances advanced together, one launch per kernel class:
+    ``Batch([params0, params1, ...])``, then ``b[i].init_fields(...)`` and ``b.step(n)``."""
+
+    def __init__(self, params_list, device: str = "cuda:0", stream=None):
+        import torch
+
+        plist = [dict(p) for p in params_list]
+        n = len(plist)
+        arr = (Params * n)(*[params_struct(p) for p in plist])
+        self._arr = arr
+        L = load()
+        nb = C.c_size_t()
+        _check(L.lbfd_batch_workspace_bytes(arr, n, C.byref(nb)), "lbfd_batch_workspace_bytes")
+        nbytes = int(nb.value)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        b = C.c_void_p()
+        _check(L.lbfd_batch_create(arr, n, C.c_void_p(ptr), C.c_size_t(nbytes), C.c_void_p(self.stream.cuda_stream),
+                                   C.byref(b)), "lbfd_batch_create")
+        self.b = b
+        self.members = []
+        for i, p in enumerate(plist):
+            h = L.lbfd_batch_instance(b, i)
+            if not h:
+                raise LbfdError(LBFD_EINVAL, f"lbfd_batch_instance({i})")
+            self.members.append(BatchMember(self, i, p, C.c_void_p(h)))
+        self.nodes = sum(m.N for m in self.members)
+
+    def __len__(self):
+        return len(self.members)
+
+    def __getitem__(self, i) -> BatchMember:
+        return self.members[i]
+
+    def step(self, n: int = 1):
+        _check(load().lbfd_batch_step(self.b, int(n)), "lbfd_batch_step")
+        return self
+
+    def close(self):
+        if getattr(self, "b", None) and _lib is not None:
+            for m in self.members:
+                m.h = None
+            _lib.lbfd_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        self.close()

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared():
     txt = open(os.path.join(ROOT, "include", "lbfd.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(lbfd_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*|lbfd_\w+ \*)\s*(lbfd_\w+)\s*\(", txt, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -73,3 +73,41 @@ def test_precision_sizes(lib):
         sizes[prec] = lbfd.workspace_bytes(p)
     assert sizes["fp64"] > sizes["fp32"] > sizes["bf16dev"]
     assert sizes["fp16dev"] == sizes["bf16dev"]
+
+
+def _batch_bytes(lib, plist):
+    arr = (lbfd.Params * len(plist))(*[lbfd.params_struct(p) for p in plist])
+    nb = C.c_size_t()
+    st = lib.lbfd_batch_workspace_bytes(arr, len(plist), C.byref(nb))
+    return st, int(nb.value)
+
+
+def test_batch_workspace_and_validation(lib):
+    plist = [p for p, _ in W.batch_instances(W.load_manifest()[:5])]
+    st, nb = _batch_bytes(lib, plist)
+    assert st == lbfd.LBFD_OK
+    # instance slices (each 256-aligned) plus the parameter table and tile prefixes
+    singles = sum(-(-lbfd.workspace_bytes(p) // 256) * 256 for p in plist)
+    assert singles < nb < singles + 5 * 4096 + 4096
+    # lattice, precision, fd_enable and sor_max_sweeps are common to a batch
+    for key, val in (("lattice", W.D3Q19), ("precision", "fp32"), ("fd_enable", 0), ("sor_max_sweeps", 7)):
+        bad = list(plist)
+        bad[3] = W.finalize(dict(plist[3], **{key: val}))
+        assert _batch_bytes(lib, bad)[0] == lbfd.LBFD_EINVAL, key
+    # an invalid instance fails the batch; grids and physics may differ freely
+    assert _batch_bytes(lib, plist[:2] + [dict(plist[2], nx=2)])[0] == lbfd.LBFD_EINVAL
+    assert _batch_bytes(lib, [plist[0], dict(plist[0], gravity=[0.0, 0.0, 0.0], nx=40)])[0] == lbfd.LBFD_OK
+    # empty batch
+    nb = C.c_size_t()
+    assert lib.lbfd_batch_workspace_bytes(None, 0, C.byref(nb)) == lbfd.LBFD_EINVAL
+    h = C.c_void_p()
+    arr = (lbfd.Params * 1)(lbfd.params_struct(plist[0]))
+    assert lib.lbfd_batch_create(arr, 1, None, 0, None, C.byref(h)) == lbfd.LBFD_EWORKSPACE and not h.value
+    assert lib.lbfd_batch_instance(None, 0) is None
+
+
+def test_batch_manifest_is_the_seeded_draw():
+    m = W.load_manifest()
+    assert m == W.batch_manifest(64, 0)
+    assert all(128 <= x["W"] <= 256 and 256 <= x["H"] <= 768 for x in m)
+    assert all(1.0 <= x["Eo"] <= 50.0 and 0.01 <= x["Bi"] <= 10.0 for x in m)

@@ -1,0 +1,187 @@
+"""Batched instances (lbfd_batch_*) through the C ABI.
+
+A batch advances independent instances with one launch per kernel class. Each
+instance must follow the FP64 oracle as a single solver does (1e-10 relative
+after many steps), and must be bit-identical to the same instance stepped
+alone: the kernels run the same per-node code on the same tiles, and the
+total-surfactant sum uses the same workgroup split (a function of the grid
+size only), so no result may depend on the batch it runs in.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.parity import say, state_errors
+
+pytestmark = pytest.mark.gpu
+
+ALL_FIELDS = ("f", "rhoR", "rhoB", "u", "psi", "phi", "force", "G", "Sprev", "Bprev")
+
+
+@pytest.fixture(scope="module")
+def lbfd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2311_15242_amd import lbfd as L
+
+    L.load()
+    return L
+
+
+def walled_box_3d(prec, nx=23, ny=21, nz=19):
+    p = dict(lattice=W.D3Q19, nx=nx, ny=ny, nz=nz, bc=[W.WALL, W.WALL, W.WALL],
+             wall_u=[[0, 0, 0], [0, 0, 0], [0.01, 0, -0.005], [-0.01, 0, 0.005], [0, 0.008, 0], [0.004, -0.006, 0]],
+             rhoR0=0.3, rhoB0=1.0, muR0=0.05, muB0=0.12, sigma0=0.01, E0=0.4, Ds=0.05, Db=0.08,
+             ra=0.05, rd=0.01, gravity=[0.0, 2e-6, -1e-5], precision=prec)
+    return W.make(p, dict(drops=[(10.0, 9.5, 8.0, 5.5)], width=3.0, psi0=0.2, phi0_out=0.06, phi0_in=0.01))
+
+
+def instances_3d(prec):
+    return [walled_box_3d(prec),
+            W.bubble_rise(nx=24, ny=20, nz=32, radius=6.0, precision=prec),
+            W.make(dict(lattice=W.D3Q19, nx=20, ny=20, nz=20, sigma0=0.01, E0=0.5, Ds=0.05, Db=0.05, precision=prec),
+                   dict(drops=[(9.5, 9.5, 9.5, 6.0)], width=3.0, psi0=0.1, phi0_out=0.05, phi0_in=0.0))]
+
+
+def make_batch(L, inst):
+    b = L.Batch([p for p, _ in inst])
+    for m, (_, q) in zip(b.members, inst):
+        m.init_fields(q)
+    return b
+
+
+def assert_identical(a, s, what):
+    for name in ALL_FIELDS:
+        x, y = a.field(name), s.field(name)
+        if not np.array_equal(x, y):
+            d = float(np.abs(x - y).max())
+            raise AssertionError(f"{what}: field {name} differs from the single instance (max |diff| {d:.3e})")
+    oa, os_ = a.observables(), s.observables()
+    for k in ("mass_R", "mass_B", "total_surf", "drift_pre", "sor_sweeps", "status", "step"):
+        assert oa[k] == os_[k], (what, k, oa[k], os_[k])
+
+
+@pytest.mark.parametrize("case,steps", [("manifest2d_quarter", 60), ("mixed3d", 15)])
+def test_batch_fp64_matches_oracle(lbfd, case, steps):
+    """Uneven instances in one FP64 batch, each against its own oracle run: four
+    2-D bubble columns of the sweep's mix at a quarter of their size (ragged
+    tiles, different Eo and Bi), and three 3-D boxes (walls on every axis with
+    moving walls, a walled column, a periodic box)."""
+    inst = (W.batch_instances(W.load_manifest()[:4], precision="fp64", scale=0.25) if case.startswith("manifest")
+            else instances_3d("fp64"))
+    say(f"[batch fp64 vs oracle] {case}: " + ", ".join(f"{p['nx']}x{p['ny']}x{p['nz']}" for p, _ in inst))
+    b = make_batch(lbfd, inst)
+    b.step(steps)
+    for i, (p, q) in enumerate(inst):
+        o = oracle.Oracle(dict(p, precision="fp64")).init(q)
+        o.step(steps)
+        errs = state_errors(b[i], o)
+        say(i, errs)
+        assert max(errs.values()) < 1e-10, (i, errs)
+        ob = b[i].observables()
+        assert ob["status"] == 0 and ob["step"] == steps
+        assert abs(ob["total_surf"] - o.initial_total) <= 1e-12 * o.initial_total
+    b.close()
+
+
+@pytest.mark.parametrize("case,prec,steps", [("manifest2d_8", "fp64", 20), ("manifest2d_8", "bf16dev", 40),
+                                             ("mixed3d", "fp32", 12), ("mixed3d", "fp16dev", 12),
+                                             ("single_tiny", "fp64", 10)])
+def test_batch_identical_to_single(lbfd, case, prec, steps):
+    """Each instance of a batch is bit-identical to the same instance stepped
+    alone: full-size 2-D columns of the sweep (the first eight draws), the 3-D
+    boxes in the reduced-precision modes, and a batch of one tiny grid."""
+    if case == "manifest2d_8":
+        inst = W.batch_instances(W.load_manifest()[:8], precision=prec)
+    elif case == "mixed3d":
+        inst = instances_3d(prec)
+    else:
+        inst = [W.make(dict(lattice=W.D2Q9, nx=5, ny=7, bc=[W.WALL, W.PERIODIC, W.PERIODIC], sigma0=0.005,
+                            Ds=0.05, Db=0.05, precision=prec),
+                       dict(drops=[(2.0, 3.0, 0.0, 1.5)], width=2.0, psi0=0.1, phi0_out=0.05, phi0_in=0.0))]
+    say(f"[batch == single] {case} {prec} {steps} steps: {len(inst)} instances")
+    b = make_batch(lbfd, inst)
+    b.step(steps // 2)
+    b.step(steps - steps // 2)
+    for i, (p, q) in enumerate(inst):
+        s = lbfd.Solver(p).init_fields(q)
+        s.step(steps)
+        assert_identical(b[i], s, f"{case} instance {i}")
+        assert s.observables()["status"] == 0
+        s.close()
+    b.close()
+
+
+def test_full_sweep_batch_sampled(lbfd):
+    """All 64 instances of the committed sweep (BF16 deviations, FP32
+    arithmetic) in the launch configuration the benchmark times: every instance
+    keeps status 0 and its own total surfactant, and a sample of instances is
+    bit-identical to its single-instance run."""
+    inst = W.batch_instances(W.load_manifest(), precision="bf16dev")
+    say(f"[full sweep] {len(inst)} instances, {sum(p['nx'] * p['ny'] for p, _ in inst)} nodes")
+    b = make_batch(lbfd, inst)
+    M0 = [m.observables()["total_surf"] for m in b.members]
+    b.step(6)
+    for i, m in enumerate(b.members):
+        ob = m.observables()
+        assert ob["status"] == 0 and ob["step"] == 6, (i, ob["status"])
+        assert abs(ob["total_surf"] - M0[i]) <= 1e-12 * M0[i], i
+    for i in (0, 21, 42, 63):
+        p, q = inst[i]
+        s = lbfd.Solver(p).init_fields(q)
+        s.step(6)
+        assert_identical(b[i], s, f"sweep instance {i}")
+        s.close()
+    b.close()
+
+
+def test_batch_rejects_diverged_instances(lbfd):
+    """lbfd_batch_step refuses instances whose step counters differ (one was
+    stepped on its own) and works again once they agree."""
+    import ctypes as C
+
+    inst = W.batch_instances(W.load_manifest()[:2], precision="fp32", scale=0.2)
+    b = make_batch(lbfd, inst)
+    b.step(2)
+    L = lbfd.load()
+    assert L.lbfd_step(b[0].h, C.c_int64(1)) == lbfd.LBFD_OK
+    with pytest.raises(lbfd.LbfdError) as e:
+        b.step(1)
+    assert e.value.status == lbfd.LBFD_EINVAL
+    assert L.lbfd_step(b[1].h, C.c_int64(1)) == lbfd.LBFD_OK
+    b.step(1)
+    assert [m.observables()["step"] for m in b.members] == [4, 4]
+    with pytest.raises(lbfd.LbfdError):
+        b.step(-1)
+    assert L.lbfd_batch_instance(b.b, 2) is None and L.lbfd_batch_instance(b.b, -1) is None
+    b.close()
+
+
+def odd_periodic_box(prec):
+    """Periodic on all three axes with odd extents: every seam level of the SOR
+    ordering (last planes, their edges and the corner)."""
+    return W.make(dict(lattice=W.D3Q19, nx=13, ny=11, nz=9, rhoR0=0.4, muR0=0.06, sigma0=0.01, E0=0.4,
+                       Ds=0.05, Db=0.08, gravity=[2e-6, -3e-6, 1e-6], precision=prec),
+                  dict(drops=[(6.0, 5.0, 4.0, 3.5)], width=3.0, psi0=0.15, phi0_out=0.05, phi0_in=0.0))
+
+
+@pytest.mark.parametrize("case", ["odd_periodic_3d", "droplet70x37"])
+def test_odd_periodic_extents_deterministic(lbfd, case):
+    """Grids periodic along an axis of odd extent (the parity colouring wraps
+    onto itself there): two runs are bit-identical and both follow the oracle."""
+    p, q = (odd_periodic_box("fp64") if case == "odd_periodic_3d"
+            else W.droplet_adsorption(n=70, radius=11.0, precision="fp64", ny=37))
+    steps = 25
+    say(f"[odd periodic] {case} {p['nx']}x{p['ny']}x{p['nz']} {steps} steps")
+    a = lbfd.Solver(p).init_fields(q).step(steps)
+    b = lbfd.Solver(p).init_fields(q).step(steps)
+    assert_identical(a, b, case)
+    o = oracle.Oracle(dict(p, precision="fp64")).init(q)
+    o.step(steps)
+    errs = state_errors(a, o)
+    say(errs)
+    assert max(errs.values()) < 1e-10, errs
+    assert a.observables()["status"] == 0

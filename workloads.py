@@ -13,7 +13,10 @@ the initial drops and concentrations.
 from __future__ import annotations
 
 import copy
+import json
 import math
+import os
+import sys
 
 import numpy as np
 
@@ -156,6 +159,29 @@ def batch_manifest(count=64, seed=0):
     return out
 
 
+# The 64 draws of batch_manifest(64, 0), stored once so that every run uses the
+# same instances (rewrite with ``python workloads.py --write-manifest``).
+BATCH_MANIFEST = os.path.join(os.path.dirname(os.path.abspath(__file__)), "bubble_rise_batch64.json")
+
+
+def load_manifest(path: str = BATCH_MANIFEST):
+    with open(path) as fh:
+        return json.load(fh)["instances"]
+
+
+def batch_instances(manifest, precision="bf16dev", scale=1.0):
+    """2-D bubble-rise instances of a manifest: a W x H column walled in x,
+    periodic in y, bubble diameter W / 5, the 3-D column's other parameters.
+    ``scale`` shrinks W and H (small test batches of the same mix)."""
+    out = []
+    for m in manifest:
+        W = max(16, int(round(m["W"] * scale)))
+        H = max(32, int(round(m["H"] * scale)))
+        out.append(bubble_rise(nx=W, ny=H, radius=W / 10.0, Eo=m["Eo"], Bi=m["Bi"], lattice=D2Q9,
+                               precision=precision))
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Random states for property tests: populations near equilibrium weights with
 # a colour split, psi in [0, 0.5 psi_inf], phi in [0, 0.1]. Pure data.
@@ -183,3 +209,12 @@ def config(name: str, precision: str | None = None):
     if name == "bubble128x128x384":
         return bubble_rise(precision=precision or "bf16dev")
     raise KeyError(name)
+
+
+if __name__ == "__main__":
+    if sys.argv[1:] == ["--write-manifest"]:
+        with open(BATCH_MANIFEST, "w") as fh:
+            json.dump(dict(seed=0, count=64, draws="W ~ U{128..256}, H ~ U{256..768}, Eo ~ logU[1, 50], "
+                                                   "Bi ~ logU[0.01, 10], in that order per instance",
+                           instances=batch_manifest(64, 0)), fh, indent=1)
+            fh.write("\n")
