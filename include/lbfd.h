@@ -193,6 +193,15 @@ int lbfd_profile(lbfd_handle *h, int32_t enable);
 int lbfd_profile_read(lbfd_handle *h, int32_t max_kernels, const char **names, double *ms, int64_t *launches,
                       int32_t *n_kernels);
 
+/* Graph replay of lbfd_step (enable != 0, the default) or plain launches
+ * (enable = 0). A call that advances four or more steps, with profiling off,
+ * records two steps once per buffer-role state into a HIP graph (captured on
+ * a private stream of default priority) and replays it on the handle's
+ * stream; steps before the second one, or before an extrapolation history
+ * exists, and an odd last step are launched directly. The results are
+ * identical either way. Errors: EINVAL (null handle). */
+int lbfd_set_graphs(lbfd_handle *h, int32_t enable);
+
 /* Release the handle (not the caller's workspace or stream). */
 void lbfd_destroy(lbfd_handle *h);
 
@@ -228,6 +237,9 @@ lbfd_handle *lbfd_batch_instance(lbfd_batch *b, int32_t i);
 /* Advance every instance n >= 0 steps. All instances must be at the same step
  * (initialised, or set to the same step, together), else EINVAL. Asynchronous. */
 int lbfd_batch_step(lbfd_batch *b, int64_t n);
+
+/* Graph replay of lbfd_batch_step, as lbfd_set_graphs for one handle. */
+int lbfd_batch_set_graphs(lbfd_batch *b, int32_t enable);
 
 /* Release the batch and its instance handles (not the workspace or stream). */
 void lbfd_batch_destroy(lbfd_batch *b);

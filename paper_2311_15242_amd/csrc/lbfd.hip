@@ -22,6 +22,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <vector>
 
@@ -1298,6 +1299,29 @@ struct ProfRec { int kc; hipEvent_t a, b; };
 
 }  // namespace
 
+// Captured two-step graphs. The buffer roles (population, FD and time-level
+// selectors) repeat every two steps, so a graph of two steps recorded from one
+// role state replays from that state for as long as the handle lives (the
+// parameter blocks, buffers and launch budget never change after creation).
+// Replay needs steps past the Euler start and an extrapolation history, which
+// are the only other per-step inputs of the kernels.
+struct StepGraph {
+    int fc, pc, lev;
+    hipGraphExec_t exec;
+};
+struct StepGraphs {
+    bool on = true;                  // replay when a call advances four or more steps
+    hipStream_t cap = nullptr;       // private capture stream (the caller's may be the null stream)
+    std::vector<StepGraph> cache;
+    void release()
+    {
+        for (auto &g : cache) hipGraphExecDestroy(g.exec);
+        cache.clear();
+        if (cap) hipStreamDestroy(cap);
+        cap = nullptr;
+    }
+};
+
 struct lbfd_handle {
     lbfd_params p;
     int Q, D;
@@ -1322,6 +1346,7 @@ struct lbfd_handle {
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     double *obs_out;  // device, NRED doubles (inside the workspace)
+    StepGraphs graphs;
 };
 
 // A batch: independent instances (ordinary handles on slices of one workspace)
@@ -1337,6 +1362,7 @@ struct lbfd_batch {
     int *prefix_seam;   // device: first seam workgroup of each instance (n + 1 entries)
     dim3 grid_node, grid_sor, grid_total, grid_seam;
     int seam_levels;    // most seam levels of any instance
+    StepGraphs graphs;
 };
 
 namespace {
@@ -1680,7 +1706,7 @@ template <int LAT, class P> struct Impl {
         return e == hipSuccess ? LBFD_OK : LBFD_EHIP;
     }
 
-    static int step(lbfd_handle *h, long long nsteps)
+    static int step_eager(lbfd_handle *h, long long nsteps)
     {
         KP<R> &k = kp(h);
         for (long long t = 0; t < nsteps; ++t) {
@@ -1718,7 +1744,7 @@ template <int LAT, class P> struct Impl {
 
     // One step for every instance of a batch: the same sequence as step(), each
     // kernel class launched once over the tiles of all instances.
-    static int batch_step(lbfd_batch *b, long long nsteps)
+    static int batch_eager(lbfd_batch *b, long long nsteps)
     {
         lbfd_handle *h = b->inst[0];   // time levels are common; profiling goes to instance 0
         const KP<R> *tab = (const KP<R> *)b->tab;
@@ -1775,6 +1801,106 @@ template <int LAT, class P> struct Impl {
             LAUNCH(KC_FORCE, (kb_force<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sb);
         }
         return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    // Counters of a handle after two steps (what two eager steps leave behind).
+    static void advance_two(lbfd_handle *h)
+    {
+        if (h->p.fd_enable) h->fd_hist += 2;
+        h->step += 2;
+        sync_levels(h);
+    }
+
+    static bool replayable(const lbfd_handle *h)
+    {
+        return h->step >= 1 && (h->fd_hist >= 1 || !h->p.fd_enable);
+    }
+
+    // Record `two_steps` (which issues two steps on h->stream and advances the
+    // counters) on the private stream of `g`, restore the counters and return
+    // the instantiated graph, or nullptr when capture is unavailable.
+    template <class F>
+    static hipGraphExec_t capture(StepGraphs &g, std::vector<lbfd_handle *> &hs, F two_steps)
+    {
+        if (!g.cap && hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking) != hipSuccess) {
+            g.cap = nullptr;
+            return nullptr;
+        }
+        struct Saved { int fc, pc; long long step, fd_hist; hipStream_t stream; };
+        std::vector<Saved> sv;
+        for (lbfd_handle *x : hs) sv.push_back(Saved{x->fc, x->pc, x->step, x->fd_hist, x->stream});
+        for (lbfd_handle *x : hs) x->stream = g.cap;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        bool ok = hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            const int st = two_steps();
+            ok = hipStreamEndCapture(g.cap, &graph) == hipSuccess && st == LBFD_OK && graph;
+        }
+        if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) hipGraphDestroy(graph);
+        for (size_t i = 0; i < hs.size(); ++i) {
+            lbfd_handle *x = hs[i];
+            x->fc = sv[i].fc;
+            x->pc = sv[i].pc;
+            x->step = sv[i].step;
+            x->fd_hist = sv[i].fd_hist;
+            x->stream = sv[i].stream;
+            sync_levels(x);
+        }
+        (void)hipGetLastError();
+        return ok ? exec : nullptr;
+    }
+
+    static hipGraphExec_t graph_for(StepGraphs &g, std::vector<lbfd_handle *> &hs, const std::function<int()> &two)
+    {
+        const lbfd_handle *h = hs[0];
+        const int lev = (int)(h->step & 1);
+        for (auto &e : g.cache)
+            if (e.fc == h->fc && e.pc == h->pc && e.lev == lev) return e.exec;
+        hipGraphExec_t ex = capture(g, hs, two);
+        if (ex) g.cache.push_back(StepGraph{h->fc, h->pc, lev, ex});
+        return ex;
+    }
+
+    // Steps of one handle: eager launches, or replays of a captured two-step
+    // graph once the replay conditions hold (results are identical).
+    static int step(lbfd_handle *h, long long nsteps)
+    {
+        if (!h->graphs.on || h->prof || nsteps < 4) return step_eager(h, nsteps);
+        while (nsteps > 0 && !replayable(h)) {
+            const int st = step_eager(h, 1);
+            if (st != LBFD_OK) return st;
+            --nsteps;
+        }
+        std::vector<lbfd_handle *> hs{h};
+        hipGraphExec_t ex = nsteps >= 2 ? graph_for(h->graphs, hs, [h]() { return step_eager(h, 2); }) : nullptr;
+        if (!ex) return step_eager(h, nsteps);
+        for (; nsteps >= 2; nsteps -= 2) {
+            if (hipGraphLaunch(ex, h->stream) != hipSuccess) return LBFD_EHIP;
+            advance_two(h);
+        }
+        return nsteps ? step_eager(h, nsteps) : LBFD_OK;
+    }
+
+    static int batch_step(lbfd_batch *b, long long nsteps)
+    {
+        lbfd_handle *h = b->inst[0];
+        if (!b->graphs.on || h->prof || nsteps < 4) return batch_eager(b, nsteps);
+        while (nsteps > 0 && !replayable(h)) {
+            const int st = batch_eager(b, 1);
+            if (st != LBFD_OK) return st;
+            --nsteps;
+        }
+        // every instance launches on instance 0's stream, the only one captured
+        std::vector<lbfd_handle *> hs(b->inst.begin(), b->inst.end());
+        hipGraphExec_t ex = nsteps >= 2 ? graph_for(b->graphs, hs, [b]() { return batch_eager(b, 2); }) : nullptr;
+        if (!ex) return batch_eager(b, nsteps);
+        for (; nsteps >= 2; nsteps -= 2) {
+            if (hipGraphLaunch(ex, h->stream) != hipSuccess) return LBFD_EHIP;
+            for (lbfd_handle *x : b->inst) advance_two(x);
+        }
+        return nsteps ? batch_eager(b, nsteps) : LBFD_OK;
     }
 
     // Upload the instances' parameter blocks (per-step selectors are passed per launch).
@@ -2028,6 +2154,20 @@ int lbfd_read_field(lbfd_handle *h, int32_t field, double *host, size_t count)
     return sticky_status(h);
 }
 
+int lbfd_set_graphs(lbfd_handle *h, int32_t enable)
+{
+    if (!h) return LBFD_EINVAL;
+    h->graphs.on = enable != 0;
+    return LBFD_OK;
+}
+
+int lbfd_batch_set_graphs(lbfd_batch *b, int32_t enable)
+{
+    if (!b) return LBFD_EINVAL;
+    b->graphs.on = enable != 0;
+    return LBFD_OK;
+}
+
 int lbfd_profile(lbfd_handle *h, int32_t enable)
 {
     if (!h) return LBFD_EINVAL;
@@ -2068,6 +2208,7 @@ void lbfd_destroy(lbfd_handle *h)
 {
     if (!h) return;
     hipStreamSynchronize(h->stream);
+    h->graphs.release();
     for (auto &r : h->recs) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
     for (auto e : h->pool) hipEventDestroy(e);
     delete h;
@@ -2116,6 +2257,8 @@ int lbfd_batch_workspace_bytes(const lbfd_params *p, int32_t n, size_t *bytes)
 void lbfd_batch_destroy(lbfd_batch *b)
 {
     if (!b) return;
+    if (!b->inst.empty()) hipStreamSynchronize(b->inst[0]->stream);
+    b->graphs.release();
     for (lbfd_handle *h : b->inst) lbfd_destroy(h);
     delete b;
 }

@@ -19,7 +19,7 @@ FIELDS = dict(f=0, rhoR=3, rhoB=4, rhoN=5, u=6, psi=7, phi=8, force=9, G=10, Spr
 EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_init_fields", "lbfd_set_state", "lbfd_step",
             "lbfd_observables", "lbfd_read_field", "lbfd_profile", "lbfd_profile_read", "lbfd_destroy",
             "lbfd_strerror", "lbfd_batch_workspace_bytes", "lbfd_batch_create", "lbfd_batch_instance",
-            "lbfd_batch_step", "lbfd_batch_destroy"]
+            "lbfd_batch_step", "lbfd_batch_destroy", "lbfd_set_graphs", "lbfd_batch_set_graphs"]
 
 
 class LbfdError(RuntimeError):
@@ -103,6 +103,8 @@ def load(build_if_missing: bool = False):
     L.lbfd_batch_step.argtypes = [vp, C.c_int64]
     L.lbfd_batch_destroy.argtypes = [vp]
     L.lbfd_batch_destroy.restype = None
+    L.lbfd_set_graphs.argtypes = [vp, C.c_int32]
+    L.lbfd_batch_set_graphs.argtypes = [vp, C.c_int32]
     _lib = L
     return L
 
@@ -259,6 +261,11 @@ class Solver(_Instance):
         _check(load().lbfd_step(self.h, int(n)), "lbfd_step")
         return self
 
+    def graphs(self, enable: bool):
+        """Replay captured two-step HIP graphs in step(n >= 4) (default) or launch every kernel."""
+        _check(load().lbfd_set_graphs(self.h, int(bool(enable))), "lbfd_set_graphs")
+        return self
+
 
 class BatchMember(_Instance):
     """Instance i of a Batch: initialised, observed and read like a Solver,
@@ -309,6 +316,10 @@ class Batch:
 
     def step(self, n: int = 1):
         _check(load().lbfd_batch_step(self.b, int(n)), "lbfd_batch_step")
+        return self
+
+    def graphs(self, enable: bool):
+        _check(load().lbfd_batch_set_graphs(self.b, int(bool(enable))), "lbfd_batch_set_graphs")
         return self
 
     def close(self):
