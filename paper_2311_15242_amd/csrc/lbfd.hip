@@ -148,7 +148,7 @@ __device__ __forceinline__ void load_moments(const KP<typename P::R> &k, const t
     meq_sum<LAT, R>(k, rR, rB, uj, m);
 #pragma unroll
     for (int r = 0; r < L::Q; ++r)
-        if (!conserved_row<LAT>(r)) m[r] += to_real(ld(fs + (long long)state_slot<LAT>(r) * k.N, n));
+        if (!conserved_row<LAT>(r)) m[r] += to_real(ldu(fs + (long long)state_slot<LAT>(r) * k.N, n));
 }
 
 template <int LAT, class P>
@@ -163,7 +163,7 @@ __device__ __forceinline__ void store_moments(const KP<typename P::R> &k, typena
     meq_sum<LAT, R>(k, rR, rB, uj, mref);
 #pragma unroll
     for (int r = 0; r < L::Q; ++r)
-        if (!conserved_row<LAT>(r)) st(fs + (long long)state_slot<LAT>(r) * k.N, n, from_real<S>(m[r] - mref[r]));
+        if (!conserved_row<LAT>(r)) stu(fs + (long long)state_slot<LAT>(r) * k.N, n, from_real<S>(m[r] - mref[r]));
 }
 
 // Store the populations f of node n at the start of a step: as populations,
@@ -402,7 +402,7 @@ template <int LAT, class P> __device__ __forceinline__ void collide_body(const K
         for (int r = 0; r < Q; ++r) m[r] = 0;
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
-            const R fj = ld(fin + j * N, n);
+            const R fj = ldu(fin + j * N, n);
 #pragma unroll
             for (int r = 0; r < Q; ++r)
                 if (L::M[r][j] != 0) m[r] += R(L::M[r][j]) * fj;
@@ -527,8 +527,8 @@ template <int LAT, class P> __device__ __forceinline__ void collide_body(const K
         const uint32_t N32 = (uint32_t)N;
         const uint32_t dst = bo ? (uint32_t)(L::OPP[i] - lo) * N32 + n
                                 : (uint32_t)(i - lo) * N32 + n + (uint32_t)nb_delta(nb, ex, ey, ez);
-        if constexpr (P::DEV) st(fout + lo * N, dst, from_real<S>(v));
-        else st(fout + lo * N, dst, (S)v);
+        if constexpr (P::DEV) stu(fout + lo * N, dst, from_real<S>(v));
+        else stu(fout + lo * N, dst, (S)v);
     }
 }
 template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<typename P::R> k)
@@ -572,7 +572,7 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
         bool bo;
         const uint32_t src = source_of<LAT>(nb, n, q, bo);
         const R sgn = bo ? R(-1) : R(1);   // a reflected arrival left its source along -e_q
-        R fq = to_real(ld(fin + q * N, n));
+        R fq = to_real(ldu(fin + q * N, n));
         R as, c[3] = {0, 0, 0};
         if constexpr (P::DEV) {
             // decode with the reference of the node the population left
@@ -875,21 +875,23 @@ __device__ __forceinline__ void sor_node(const KP<typename P::R> &k, const SorOp
     }
 }
 
-// One tile (64 same-colour nodes along x by 4 rows, one z plane) of a colour half-sweep.
-// SEAM: the grid has seam classes (the test costs registers, so grids without are
-// served by a variant without it).
+// One tile of a colour half-sweep: 256 consecutive entries of the colour's index
+// space (i, y, z), i fastest, with x = 2 i + parity. A wavefront spans one row of
+// 64 same-colour nodes or, on narrow grids, runs on into the next rows, so no lane
+// idles at the end of a row. SEAM: the grid has seam classes (the test costs
+// registers, so grids without are served by a variant without it).
 template <int LAT, class P, bool SEAM>
 __device__ __forceinline__ void sor_tile(const KP<typename P::R> &k, const SorOps<typename P::R> &a, int tile,
                                          int color, const bool *conv, typename P::R *rloc, typename P::R *bloc)
 {
-    const int hx = (k.nx + 1) >> 1;
-    const int tx = (hx + 63) >> 6, ty = (k.ny + 3) >> 2;
-    const int li = threadIdx.x & 63, ly = threadIdx.x >> 6;
-    const int bx = tile % tx, rest = tile / tx;
-    const int by = rest % ty, z = rest / ty;
-    const int y = by * 4 + ly;
-    const int x = 2 * (bx * 64 + li) + ((y + z + color) & 1);
-    if (x >= k.nx || y >= k.ny) return;
+    const uint32_t hx = (uint32_t)(k.nx + 1) >> 1;
+    const uint32_t L = (uint32_t)tile * 256u + threadIdx.x;
+    if (L >= hx * (uint32_t)k.ny * (uint32_t)k.nz) return;
+    const uint32_t row = udiv(L, hx, k.inv_hx);
+    const uint32_t z = udiv(row, (uint32_t)k.ny, k.inv_ny);
+    const int y = (int)(row - z * (uint32_t)k.ny);
+    const int x = 2 * (int)(L - row * hx) + ((y + (int)z + color) & 1);
+    if (x >= k.nx) return;
     if (SEAM && on_seam<Lat<LAT>::D>(k, x, y, z)) return;   // updated with its seam class
     sor_node<LAT, P>(k, a, x, y, z, conv, rloc, bloc);
 }
@@ -939,7 +941,7 @@ __device__ __forceinline__ void sor_seam_node(const KP<typename P::R> &k, const 
 // Number of tiles of one colour of a half-sweep.
 template <class R> __host__ __device__ inline int sor_ntiles(const KP<R> &k)
 {
-    return (((k.nx + 1) / 2 + 63) / 64) * ((k.ny + 3) / 4) * k.nz;
+    return sor_tiles_of(k.nx, k.ny, k.nz);
 }
 
 // One colour half of a red-black SOR sweep of both implicit systems
@@ -1092,9 +1094,10 @@ __device__ __forceinline__ void total_part_body(const KP<typename P::R> &k, int 
     const long long N = k.N;
     double v[1] = {0.0};
     for (long long n = (long long)blk * blockDim.x + threadIdx.x; n < N; n += (long long)nblk * blockDim.x) {
-        double G = (double)(k.fld.G[level][n] + k.fd_eps);
-        double X = (double)((R(1) - k.fld.mac[level][2 * N + n]) + k.fd_eps);
-        double ps = mult * (double)k.fld.psi[buf][n], ph = mult * (double)k.fld.phi[buf][n];
+        const uint32_t i = (uint32_t)n;
+        double G = (double)(ld(k.fld.G[level], i) + k.fd_eps);
+        double X = (double)((R(1) - ld(k.fld.mac[level] + 2 * N, i)) + k.fd_eps);
+        double ps = mult * (double)ld(k.fld.psi[buf], i), ph = mult * (double)ld(k.fld.phi[buf], i);
         v[0] += G * ps + X * ph;
     }
     block_sum_store<1>(v, k.fld.part + blk);
@@ -1535,6 +1538,8 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
     k.omega = (R)p->sor_omega;
     k.tol = (R)p->sor_tol;
     k.seam = seam_axes(p);
+    k.inv_hx = 1.0 / (double)((p->nx + 1) / 2);
+    k.inv_ny = 1.0 / (double)p->ny;
     k.sor_exact = (p->sor_omega == 1.0 && k.seam == 0) ? 1 : 0;
     k.weno_eps = (R)p->weno_eps;
     k.eps_n = (R)p->eps_n;
@@ -2091,9 +2096,8 @@ int lbfd_create(const lbfd_params *p, void *d_workspace, size_t bytes, void *str
     seam_shape(p, &h->seam_tiles, &h->seam_levels);
     h->sweeps_launch = p->sor_max_sweeps;
     {
-        // tiles of one colour (64 x 4 nodes), capped at 8 workgroups of 256 per compute unit
-        long long hx = (p->nx + 1) / 2;
-        long long need = ((hx + 63) / 64) * ((p->ny + 3) / 4) * (long long)p->nz;
+        // tiles of one colour (256 nodes), capped at 8 workgroups of 256 per compute unit
+        long long need = sor_tiles_of(p->nx, p->ny, p->nz);
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess) {
             hipDeviceProp_t prop;
@@ -2231,7 +2235,7 @@ static int batch_layout(const lbfd_params *p, int32_t n, std::vector<size_t> *of
         if (offs) offs->push_back(o);
         o += align256(layout(&p[i]).total);
         node_tiles += (long long)((p[i].nx + BX - 1) / BX) * ((p[i].ny + BY - 1) / BY) * p[i].nz;
-        sor_tiles += (long long)(((p[i].nx + 1) / 2 + 63) / 64) * ((p[i].ny + 3) / 4) * p[i].nz;
+        sor_tiles += sor_tiles_of(p[i].nx, p[i].ny, p[i].nz);
     }
     // one launch covers the tiles of all instances: 256 lanes per tile, 32-bit lane ids
     if (node_tiles * 256 > (long long)UINT32_MAX || sor_tiles * 256 > (long long)UINT32_MAX) return LBFD_EINVAL;
@@ -2288,9 +2292,8 @@ int lbfd_batch_create(const lbfd_params *p, int32_t n, void *d_workspace, size_t
             return st;
         }
         b->inst.push_back(h);
-        const long long hx = (p[i].nx + 1) / 2;
         pn[i + 1] = pn[i] + (int)h->nblocks;
-        ps[i + 1] = ps[i] + (int)(((hx + 63) / 64) * ((p[i].ny + 3) / 4) * (long long)p[i].nz);
+        ps[i + 1] = ps[i] + sor_tiles_of(p[i].nx, p[i].ny, p[i].nz);
         pt[i + 1] = pt[i] + h->tblocks;
         pm[i + 1] = pm[i] + h->seam_tiles;
         if (h->seam_levels > b->seam_levels) b->seam_levels = h->seam_levels;

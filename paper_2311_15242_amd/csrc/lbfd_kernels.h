@@ -163,6 +163,7 @@ template <class R> struct KP {
     R omega;
     R tol;
     int seam;           // periodic axes of odd extent (bit a): seam classes of the SOR ordering
+    double inv_hx, inv_ny;  // 1 / ((nx + 1) / 2) and 1 / ny for the SOR index arithmetic
     int sor_exact;      // omega = 1 without seam classes: the red residual is the whole residual
     R weno_eps, eps_n;
     R fd_eps;           // background support of the FD weights
@@ -216,6 +217,24 @@ struct StepArgs {
     int lev, fc, pc, extrap;
     long long step;
 };
+// Tiles of 256 entries over one colour's index space ((nx + 1) / 2 x ny x nz);
+// entries past a row's last same-colour node are skipped by the kernels.
+__host__ __device__ inline int sor_tiles_of(int nx, int ny, int nz)
+{
+    const long long e = (long long)((nx + 1) / 2) * ny * nz;
+    return (int)((e + 255) / 256);
+}
+
+// a / d for a < 2^32 and d >= 1 from inv = 1 / d in FP64: the rounded product
+// is within a relative 2^-52 of a / d, which for a < 2^32 leaves its integer
+// part at the quotient or one below it; one correction step makes it exact.
+__device__ __forceinline__ uint32_t udiv(uint32_t a, uint32_t d, double inv)
+{
+    uint32_t q = (uint32_t)((double)a * inv);
+    if (a - q * d >= d) ++q;
+    return q;
+}
+
 template <class R> __device__ __forceinline__ StepArgs step_args(const KP<R> &k)
 {
     StepArgs s;
@@ -258,13 +277,49 @@ template <class R> __device__ __forceinline__ uint32_t *desc_dev_b(const KP<R> &
 // byte offset. This maps onto the scalar-base + vector-offset form of the
 // global loads and stores, and one offset serves every array with the same
 // element size. Requires idx * sizeof(T) < 2^32 (the host bounds the node count).
+// Global address space of the device pass (the host pass parses these templates
+// too and has no such address space).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LBFD_GLOBAL __attribute__((address_space(1)))
+#else
+#define LBFD_GLOBAL
+#endif
+
+// Element idx of a device array (a 32-bit byte offset from the base). Every
+// array these kernels touch is in global memory; the access goes through a
+// global-address-space pointer, so it is a global (not flat) access even when
+// the base was itself loaded from memory (the instance table of a batch).
 template <class T> __device__ __forceinline__ T ld(const T *base, uint32_t idx)
 {
-    return *(const T *)((const char *)base + idx * (uint32_t)sizeof(T));
+    typedef const LBFD_GLOBAL T GT;
+    return *(GT *)((const LBFD_GLOBAL char *)base + idx * (uint32_t)sizeof(T));
 }
 template <class T> __device__ __forceinline__ void st(T *base, uint32_t idx, const T &v)
 {
-    *(T *)((char *)base + idx * (uint32_t)sizeof(T)) = v;
+    typedef LBFD_GLOBAL T GT;
+    *(GT *)((LBFD_GLOBAL char *)base + idx * (uint32_t)sizeof(T)) = v;
+}
+
+// The same through a base that has one value in every lane (a plane of a
+// population array), pinned to scalar registers: otherwise the compiler may fold
+// the plane offset into per-lane 64-bit address arithmetic. The access goes
+// through a global-address-space pointer so it stays a global (not flat) one.
+template <class T> __device__ __forceinline__ LBFD_GLOBAL char *scalar_base(const T *p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (LBFD_GLOBAL char *)(((unsigned long long)hi << 32) | lo);
+}
+template <class T> __device__ __forceinline__ T ldu(const T *base, uint32_t idx)
+{
+    typedef const LBFD_GLOBAL T GT;
+    return *(GT *)(scalar_base(base) + idx * (uint32_t)sizeof(T));
+}
+template <class T> __device__ __forceinline__ void stu(T *base, uint32_t idx, const T &v)
+{
+    typedef LBFD_GLOBAL T GT;
+    *(GT *)(scalar_base(base) + idx * (uint32_t)sizeof(T)) = v;
 }
 
 template <class R> __device__ __forceinline__ uint32_t node_index(const KP<R> &k, const Node &nd)
