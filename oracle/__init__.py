@@ -87,6 +87,7 @@ def lib():
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_init.argtypes = [C.c_void_p, P(_Init)]
         L.orc_step.argtypes = [C.c_void_p, C.c_int64]
+        L.orc_fd_substeps.argtypes = [C.c_void_p, C.c_int64]
         L.orc_nodes.restype = C.c_int64
         L.orc_nodes.argtypes = [C.c_void_p]
         L.orc_lattice_q.argtypes = [C.c_void_p]
@@ -180,6 +181,13 @@ class Oracle:
         st = lib().orc_step(self.h, int(n))
         if st != 0:
             raise RuntimeError(f"orc_step failed ({st})")
+        return self
+
+    def fd_substeps(self, k):
+        """k FD updates of psi and phi with the flow frozen at the current state."""
+        st = lib().orc_fd_substeps(self.h, int(k))
+        if st != 0:
+            raise RuntimeError(f"orc_fd_substeps failed ({st})")
         return self
 
     def _count(self, name):

@@ -692,12 +692,12 @@ static double total_surfactant(const orc_state *s, const double *G, const double
    WENO3 convection (eqs 25-27), diffusion (eq 28), SOR solve and rescaling.
    Reading of the time levels: G^{t+1} comes from the populations just
    streamed; convection and sources use u, G, rhoN of the LB step just taken. */
+static int fd_transport(orc_state *s);
+
 static int fd_stage(orc_state *s)
 {
-    const orc_params *p = &s->p;
     long N = s->N;
     int D = s->D;
-    int status = ORC_OK;
 
     macro(s, s->fR2, s->fB2, s->tmp, s->divPhi, NULL, s->rhoN1, NULL); /* divPhi as scratch */
     for (int a = 0; a < D; ++a) op_deriv(s, s->rhoN1, -1, a, s->g1[a]);
@@ -709,6 +709,17 @@ static int fd_stage(orc_state *s)
         s->X0[n] = fd_weight(s, 1.0 - s->rhoN[n]);
         s->Gw[n] = fd_weight(s, s->G[n]);
     }
+    return fd_transport(s);
+}
+
+/* The transport itself, from the weights G1, X1 (time t+1), Gw, X0 (time t),
+   u and psi, phi at time t. */
+static int fd_transport(orc_state *s)
+{
+    const orc_params *p = &s->p;
+    long N = s->N;
+    int D = s->D;
+    int status = ORC_OK;
     /* fluxes Psi = psi |grad rhoN| u and Phi = phi (1 - rhoN) u at time t */
     for (int a = 0; a < D; ++a)
         for (long n = 0; n < N; ++n) {
@@ -865,6 +876,30 @@ static int step_once(orc_state *s)
     t = s->fB; s->fB = s->fB2; s->fB2 = t;
     s->step += 1;
     return st;
+}
+
+/* k transport updates of psi and phi with the flow frozen at the current state:
+   rhoN, G and u from the current populations, and the weights of the new time
+   level equal to those of the old one (G^{t+1} = G^t, X^{t+1} = X^t). The LB
+   populations and the step counter are left as they are. This defines the
+   quantity the learned surrogate approximates (k substeps of the FD update of
+   Sec 2.2 with the flow held fixed). */
+int orc_fd_substeps(orc_state *s, int64_t k)
+{
+    if (!s || k < 0) return ORC_EINVAL;
+    if (!s->p.fd_enable || k == 0) return ORC_OK;
+    force_stage(s);
+    for (long n = 0; n < s->N; ++n) {
+        s->Gw[n] = fd_weight(s, s->G[n]);
+        s->G1[n] = s->Gw[n];
+        s->X0[n] = fd_weight(s, 1.0 - s->rhoN[n]);
+        s->X1[n] = s->X0[n];
+    }
+    for (int64_t i = 0; i < k; ++i) {
+        int st = fd_transport(s);
+        if (st != ORC_OK) return st;
+    }
+    return ORC_OK;
 }
 
 int orc_step(orc_state *s, int64_t nsteps)

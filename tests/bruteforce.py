@@ -199,21 +199,29 @@ def step(p, st):
     rN1 = (rR1 / p["rhoR0"] - rB1 / p["rhoB0"]) / (rR1 / p["rhoR0"] + rB1 / p["rhoB0"])
     eps = p.get("fd_eps", 0.0)
     G1 = np.sqrt((grad(rN1, e, w, D) ** 2).sum(0)) + eps
-    X0, X1 = 1 - rN + eps, 1 - rN1 + eps
-    G = G + eps
-    divPsi = weno_div(psi * G * u, u, D, p["weno_eps"], p.get("upwind_eps", 0.0))
+    psi1, phi1, Sn, Bn, rhsP, Mt = fd_update(p, st, G + eps, 1 - rN + eps, G1, 1 - rN1 + eps, u, D)
+    out.update(psi=psi1, phi=phi1, Sprev=Sn, Bprev=Bn, G1=G1, rhsP=rhsP, Mt=Mt)
+    return out
+
+
+def fd_update(p, st, Gw, X0, G1, X1, u, D):
+    """One FD transport update (eqs 20-28) from psi, phi, Sprev, Bprev of st with
+    the weights Gw, X0 (time t) and G1, X1 (time t+1), dense direct solves."""
+    psi, phi = st["psi"], st["phi"]
+    pinf = p["psi_inf"]
+    divPsi = weno_div(psi * Gw * u, u, D, p["weno_eps"], p.get("upwind_eps", 0.0))
     divPhi = weno_div(phi * X0 * u, u, D, p["weno_eps"], p.get("upwind_eps", 0.0))
     if p["source_mode"] == 1:
         jj = p["ra"] * pinf * phi
     else:
         jj = p["ra"] * phi * (pinf - psi) - p["rd"] * psi
-    Sn = -divPsi + G * jj
-    Bn = -divPhi - G * jj
+    Sn = -divPsi + Gw * jj
+    Bn = -divPhi - Gw * jj
     if st["step"] == 0:
         eS, eB = Sn, Bn
     else:
         eS, eB = 1.5 * Sn - 0.5 * st["Sprev"], 1.5 * Bn - 0.5 * st["Bprev"]
-    A0p = implicit_matrix(G, -p["Ds"], D)      # diag(G) + (Ds/2) L_G
+    A0p = implicit_matrix(Gw, -p["Ds"], D)      # diag(G) + (Ds/2) L_G
     A0f = implicit_matrix(X0, -p["Db"], D)
     rhsP = A0p @ psi.reshape(-1) + eS.reshape(-1)
     rhsF = A0f @ phi.reshape(-1) + eB.reshape(-1)
@@ -230,5 +238,23 @@ def step(p, st):
     Mt = (G1 * psi1 + X1 * phi1).sum()
     if p["rescale"] and st["M0"] != 0:
         psi1, phi1 = psi1 * st["M0"] / Mt, phi1 * st["M0"] / Mt
-    out.update(psi=psi1, phi=phi1, Sprev=Sn, Bprev=Bn, G1=G1, rhsP=rhsP, Mt=Mt)
-    return out
+    return psi1, phi1, Sn, Bn, rhsP, Mt
+
+
+def fd_substeps(p, st, k):
+    """k FD updates with the flow frozen at state st (rhoN, G and u of its
+    populations; the new-level weights equal the old ones)."""
+    three = p["lattice"] == 1
+    D = 3 if three else 2
+    base = step(dict(p, fd_enable=0), st)     # u of the current populations
+    e, w, _ = lattice(three)
+    rR, rB = st["fR"].sum(0), st["fB"].sum(0)
+    rN = (rR / p["rhoR0"] - rB / p["rhoB0"]) / (rR / p["rhoR0"] + rB / p["rhoB0"])
+    eps = p.get("fd_eps", 0.0)
+    Gw = np.sqrt((grad(rN, e, w, D) ** 2).sum(0)) + eps
+    X0 = 1 - rN + eps
+    cur = dict(st)
+    for _ in range(k):
+        psi1, phi1, Sn, Bn, _, _ = fd_update(p, cur, Gw, X0, Gw, X0, base["u"], D)
+        cur = dict(cur, psi=psi1, phi=phi1, Sprev=Sn, Bprev=Bn)
+    return cur

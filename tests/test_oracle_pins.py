@@ -190,6 +190,28 @@ def test_whole_step_matches_bruteforce(lat, n, extra):
         assert np.abs(a - b).max() <= 1e-11 * np.abs(b).max(), name
 
 
+@pytest.mark.parametrize("lat,n", [(W.D2Q9, 8), (W.D3Q19, 5)])
+def test_frozen_flow_substeps_match_bruteforce(lat, n):
+    """k FD updates with the flow held at the current state (the quantity the
+    surrogate approximates) equal k brute-force updates with dense solves,
+    G^{t+1} = G^t and X^{t+1} = X^t, u from the current populations; the LB
+    populations do not move."""
+    p = tiny(lat, n=n, Ds=0.1, Db=0.3)
+    o = oracle.Oracle(p)
+    random_two_phase(o, 7)
+    st = bf_state(o, p)
+    o.set_clock(1, 1.0)
+    fR0 = o.field("fR").copy()
+    ref = bf.fd_substeps(p, st, 3)
+    o.fd_substeps(3)
+    for name in ("psi", "phi", "Sprev", "Bprev"):
+        a, b = o.field(name), ref[name]
+        assert np.abs(a - b).max() <= 1e-11 * np.abs(b).max(), name
+    assert np.array_equal(o.field("fR"), fR0)
+    # one substep differs from a full step's FD update (the weights do not move)
+    assert np.abs(bf.fd_substeps(p, st, 1)["psi"] - bf.step(p, st)["psi"]).max() > 1e-9
+
+
 def test_first_step_uses_euler():
     """Eq 23 at t = 0 (no S^{t-1}), eq 24 afterwards."""
     p = tiny(W.D2Q9)
