@@ -193,6 +193,19 @@ int lbfd_profile(lbfd_handle *h, int32_t enable);
 int lbfd_profile_read(lbfd_handle *h, int32_t max_kernels, const char **names, double *ms, int64_t *launches,
                       int32_t *n_kernels);
 
+/* Advance psi and phi by k >= 0 FD updates (Sec 2.2, eqs 20-28) with the flow
+ * frozen at the current state: rhoN, G and u of the current populations, the
+ * weights of the new time level equal to those of the current one. The LB
+ * populations and the step count do not change; the force is recomputed from
+ * the new psi. The quantity the learned surrogate approximates, and its
+ * fallback. No-op when fd_enable is 0. Errors: EINVAL (null handle, k < 0). */
+int lbfd_fd_substeps(lbfd_handle *h, int64_t k);
+
+/* Switch the FD part of lbfd_step off (enable = 0: the LB part advances with
+ * psi and phi held, as between the updates of the learned surrogate) or back
+ * on (the default). Errors: EINVAL (null handle). */
+int lbfd_set_fd(lbfd_handle *h, int32_t enable);
+
 /* Graph replay of lbfd_step (enable != 0, the default) or plain launches
  * (enable = 0). A call that advances four or more steps, with profiling off,
  * records two steps once per buffer-role state into a HIP graph (captured on

@@ -18,6 +18,7 @@
 //            (eq 9), buoyancy (Sec 3.4) and velocity (eq 10) of step n+1
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -28,6 +29,8 @@
 
 #include "lbfd.h"
 #include "lbfd_kernels.h"
+#include "lbfd_surrogate.h"
+#include "sg_conv.h"
 
 namespace lbfd {
 
@@ -1064,6 +1067,92 @@ template <class R> __global__ void kb_sor_done(const KP<R> *tab, int nsw)
 // Clears the residual and |rhs| slots (set-up, before the first step).
 template <class R> __global__ void k_sor_clear(KP<R> k, int nsw) { sor_slots_clear(k.fld.sorres, nsw); }
 
+
+// ============================================================== surrogate coupling
+
+// Input channels of the surrogate (psi/psi_inf, phi/phi_s, rhoN, u/u_s, zeros up to
+// 16) on the grid with a periodic halo of 4 nodes: feat is BF16 [nz+8][ny+8][nx+8][16].
+template <int LAT, class P>
+__global__ __launch_bounds__(256) void k_sg_features(KP<typename P::R> k, uint16_t *feat, float ipsi, float iphi,
+                                                    float iu)
+{
+    constexpr int D = Lat<LAT>::D;
+    const int nx = k.nx, ny = k.ny, nz = k.nz;
+    const long long px = nx + 8, py = ny + 8, pz = nz + 8;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= px * py * pz) return;
+    const int xp = (int)(t % px), yp = (int)((t / px) % py), zp = (int)(t / (px * py));
+    const int x = ((xp - 4) % nx + nx) % nx, y = ((yp - 4) % ny + ny) % ny, z = ((zp - 4) % nz + nz) % nz;
+    const long long N = k.N;
+    const uint32_t n = (uint32_t)(x + nx * (y + ny * z));
+    const double sc = k.fld.sc->scale;
+    float c[8];
+    c[0] = (float)(sc * (double)ld(k.fld.psi[k.pc], n)) * ipsi;
+    c[1] = (float)(sc * (double)ld(k.fld.phi[k.pc], n)) * iphi;
+    c[2] = (float)ld(k.fld.mac[k.lev] + 2 * N, n);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c[3 + a] = a < D ? (float)ld(k.fld.u + a * N, n) * iu : 0.0f;
+    c[6] = c[7] = 0.0f;
+    sg::u32x4 lo, zero = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lo[i] = (uint32_t)sg::f2bf(c[2 * i]) | ((uint32_t)sg::f2bf(c[2 * i + 1]) << 16);
+    sg::u32x4 *d = (sg::u32x4 *)(feat + t * sg::IN_CH);
+    d[0] = lo;
+    d[1] = zero;
+}
+
+// psi and phi of the current state (physical values), FP32 [N][2].
+template <class R> __global__ __launch_bounds__(256) void k_sg_snapshot(KP<R> k, float *snap)
+{
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (n >= k.N) return;
+    const double sc = k.fld.sc->scale;
+    snap[2 * n] = (float)(sc * (double)ld(k.fld.psi[k.pc], (uint32_t)n));
+    snap[2 * n + 1] = (float)(sc * (double)ld(k.fld.phi[k.pc], (uint32_t)n));
+}
+
+// Training tiles: the input crop of tile b from the feature grid (edge T + 8) and the
+// target over its T^3 output nodes: (psi, phi now - snap) / (dpsi_s, dphi_s).
+template <class R>
+__global__ __launch_bounds__(256) void k_sg_tiles(KP<R> k, const uint16_t *feat, const float *snap, const int *org,
+                                                 int T, uint16_t *tin, float *tgt, float idpsi, float idphi)
+{
+    const int b = blockIdx.y;
+    const int ox = org[3 * b], oy = org[3 * b + 1], oz = org[3 * b + 2];
+    const long long E = T + 8, nin = E * E * E, nout = (long long)T * T * T;
+    const long long px = k.nx + 8, py = k.ny + 8;
+    const double sc = k.fld.sc->scale;
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < nin; t += (long long)gridDim.x * 256) {
+        const long long i = t % E, j = (t / E) % E, l = t / (E * E);
+        const long long src = ((oz + l) * py + (oy + j)) * px + (ox + i);
+        const sg::u32x4 *s = (const sg::u32x4 *)(feat + src * sg::IN_CH);
+        sg::u32x4 *d = (sg::u32x4 *)(tin + ((long long)b * nin + t) * sg::IN_CH);
+        d[0] = s[0];
+        d[1] = s[1];
+    }
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < nout; t += (long long)gridDim.x * 256) {
+        const long long i = t % T, j = (t / T) % T, l = t / ((long long)T * T);
+        const uint32_t n = (uint32_t)((ox + i) + k.nx * ((oy + j) + (long long)k.ny * (oz + l)));
+        const float ps = (float)(sc * (double)ld(k.fld.psi[k.pc], n)), ph = (float)(sc * (double)ld(k.fld.phi[k.pc], n));
+        float *o = tgt + ((long long)b * nout + t) * 2;
+        o[0] = (ps - snap[2 * (long long)n]) * idpsi;
+        o[1] = (ph - snap[2 * (long long)n + 1]) * idphi;
+    }
+}
+
+// Candidate of a surrogate update into the other FD buffers: psi + dpsi_s o[.][0],
+// phi + dphi_s o[.][1] (physical values, as an FD update leaves them).
+template <class R>
+__global__ __launch_bounds__(256) void k_sg_apply(KP<R> k, const float *o, float dpsi, float dphi)
+{
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (n >= k.N) return;
+    const uint32_t i = (uint32_t)n;
+    const double sc = k.fld.sc->scale;
+    st(k.fld.psi[1 - k.pc], i, (R)(sc * (double)ld(k.fld.psi[k.pc], i) + (double)dpsi * (double)o[2 * n]));
+    st(k.fld.phi[1 - k.pc], i, (R)(sc * (double)ld(k.fld.phi[k.pc], i) + (double)dphi * (double)o[2 * n + 1]));
+}
+
 // ============================================================== reductions
 
 template <int NV> __device__ __forceinline__ void block_sum_store(double (&v)[NV], double *out)
@@ -1137,6 +1226,9 @@ template <class R> __device__ __forceinline__ void total_final_body(const KP<R> 
             sc->drift_pre = 0.0;
             sc->scale = 1.0;
             sc->scale_prev = 1.0;
+        } else if (mode == 2) {
+            // probe: the relative drift of a candidate only (nothing else changes)
+            sc->drift_pre = sc->M0 != 0.0 ? (M - sc->M0) / sc->M0 : 0.0;
         } else {
             sc->scale_prev = sc->scale;
             sc->Mlast = M;
@@ -1310,6 +1402,7 @@ struct ProfRec { int kc; hipEvent_t a, b; };
 // are the only other per-step inputs of the kernels.
 struct StepGraph {
     int fc, pc, lev;
+    bool fd_off;
     hipGraphExec_t exec;
 };
 struct StepGraphs {
@@ -1350,6 +1443,7 @@ struct lbfd_handle {
     std::vector<hipEvent_t> pool;
     double *obs_out;  // device, NRED doubles (inside the workspace)
     StepGraphs graphs;
+    bool fd_off = false;  // LB steps only (psi, phi held): surrogate mode between its updates
 };
 
 // A batch: independent instances (ordinary handles on slices of one workspace)
@@ -1711,6 +1805,113 @@ template <int LAT, class P> struct Impl {
         return e == hipSuccess ? LBFD_OK : LBFD_EHIP;
     }
 
+    // FD transport of one step (or substep): right-hand sides, the implicit solve
+    // by SOR half-sweeps, the sweep count and the total; psi, phi move to the other
+    // buffer. The weights of the new level are G[1 - lev] and rhoN of mac[1 - lev].
+    static void fd_block(lbfd_handle *h)
+    {
+        KP<R> &k = kp(h);
+        LAUNCH(KC_FD, (k_fd<LAT, P>), h->grid, h->block, k);
+        for (int s = 0; s < h->sweeps_launch; ++s) {
+            if (h->seam_levels == 0) {
+                LAUNCH(KC_SOR, (k_sor<LAT, P, false>), dim3(h->sor_blocks), dim3(256), k, 0, s);
+                LAUNCH(KC_SOR, (k_sor<LAT, P, false>), dim3(h->sor_blocks), dim3(256), k, 1, s);
+                continue;
+            }
+            LAUNCH(KC_SOR, (k_sor<LAT, P, true>), dim3(h->sor_blocks), dim3(256), k, 0, s);
+            LAUNCH(KC_SOR, (k_sor<LAT, P, true>), dim3(h->sor_blocks), dim3(256), k, 1, s);
+            for (int lv = 1; lv <= h->seam_levels; ++lv) {
+                LAUNCH(KC_SOR, (k_sor_seam<LAT, P>), dim3(h->seam_tiles), dim3(256), k, lv, 0, s);
+                LAUNCH(KC_SOR, (k_sor_seam<LAT, P>), dim3(h->seam_tiles), dim3(256), k, lv, 1, s);
+            }
+        }
+        LAUNCH(KC_OTHER, (k_sor_done<R>), dim3(1), dim3(64), k, h->sweeps_launch);
+        totals(h, 1 - k.lev, 1 - k.pc, 1.0, 1);
+        h->pc = 1 - h->pc;
+        h->fd_hist += 1;
+        sync_levels(h);
+    }
+
+    // k FD substeps with the flow frozen at the current state: the weights of the
+    // new level are set equal to those of the current one (the other level's
+    // buffers are free between steps), then k transport updates, then the force
+    // from the new psi. The LB populations and the step count do not change.
+    static int fd_substeps(lbfd_handle *h, long long ksub)
+    {
+        if (!h->p.fd_enable || ksub <= 0) return LBFD_OK;
+        // the first solve starts from the current value (the other buffer may hold a
+        // rejected surrogate candidate rather than the previous level)
+        h->fd_hist = 0;
+        sync_levels(h);
+        KP<R> &k = kp(h);
+        const int lev = k.lev;
+        const size_t rb = sizeof(R) * (size_t)h->N;
+        if (hipMemcpyAsync(k.fld.G[1 - lev], k.fld.G[lev], rb, hipMemcpyDeviceToDevice, h->stream) != hipSuccess ||
+            hipMemcpyAsync(k.fld.mac[1 - lev] + 2 * h->N, k.fld.mac[lev] + 2 * h->N, rb, hipMemcpyDeviceToDevice,
+                           h->stream) != hipSuccess)
+            return LBFD_EHIP;
+        for (long long t = 0; t < ksub; ++t) fd_block(h);
+        LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
+        return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    static int sg_features(lbfd_handle *h, uint16_t *feat, float ipsi, float iphi, float iu)
+    {
+        sync_levels(h);
+        const long long n = (long long)(h->p.nx + 8) * (h->p.ny + 8) * (h->p.nz + 8);
+        LAUNCH(KC_OTHER, (k_sg_features<LAT, P>), dim3((unsigned)((n + 255) / 256)), dim3(256), kp(h), feat, ipsi,
+               iphi, iu);
+        return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    static int sg_snapshot(lbfd_handle *h, float *snap)
+    {
+        sync_levels(h);
+        LAUNCH(KC_OTHER, (k_sg_snapshot<R>), dim3((unsigned)((h->N + 255) / 256)), dim3(256), kp(h), snap);
+        return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    static int sg_tiles(lbfd_handle *h, const uint16_t *feat, const float *snap, const int *dorg, int B, int T,
+                        uint16_t *tin, float *tgt, float idpsi, float idphi)
+    {
+        sync_levels(h);
+        LAUNCH(KC_OTHER, (k_sg_tiles<R>), dim3(64, (unsigned)B), dim3(256), kp(h), feat, snap, dorg, T, tin, tgt,
+               idpsi, idphi);
+        return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    // Write the candidate and probe its pre-rescale drift (left in the device scalars).
+    static int sg_candidate(lbfd_handle *h, const float *o, float dpsi, float dphi)
+    {
+        sync_levels(h);
+        KP<R> &k = kp(h);
+        LAUNCH(KC_OTHER, (k_sg_apply<R>), dim3((unsigned)((h->N + 255) / 256)), dim3(256), k, o, dpsi, dphi);
+        totals(h, k.lev, 1 - k.pc, 1.0, 2);
+        return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    // Keep the candidate: rescale as an FD update would, swap the buffers, recompute
+    // the force; the next solve starts from the old value (no extrapolation history).
+    static int sg_accept(lbfd_handle *h)
+    {
+        sync_levels(h);
+        KP<R> &k = kp(h);
+        totals(h, k.lev, 1 - k.pc, 1.0, 1);
+        h->pc = 1 - h->pc;
+        h->fd_hist = 0;
+        sync_levels(h);
+        LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
+        return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    static int read_scalars(lbfd_handle *h, DevScalars *out)
+    {
+        if (hipMemcpyAsync(out, kp(h).fld.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess)
+            return LBFD_EHIP;
+        return LBFD_OK;
+    }
+
     static int step_eager(lbfd_handle *h, long long nsteps)
     {
         KP<R> &k = kp(h);
@@ -1719,26 +1920,7 @@ template <int LAT, class P> struct Impl {
             LAUNCH(KC_COLLIDE, (k_collide<LAT, P>), h->grid, h->block, k);
             LAUNCH(KC_MACRO, (k_macro<LAT, P>), h->grid, h->block, k);
             LAUNCH(KC_GEOM, (k_geom<LAT, P>), h->grid, h->block, k, 1 - k.lev);
-            if (h->p.fd_enable) {
-                LAUNCH(KC_FD, (k_fd<LAT, P>), h->grid, h->block, k);
-                for (int s = 0; s < h->sweeps_launch; ++s) {
-                    if (h->seam_levels == 0) {
-                        LAUNCH(KC_SOR, (k_sor<LAT, P, false>), dim3(h->sor_blocks), dim3(256), k, 0, s);
-                        LAUNCH(KC_SOR, (k_sor<LAT, P, false>), dim3(h->sor_blocks), dim3(256), k, 1, s);
-                        continue;
-                    }
-                    LAUNCH(KC_SOR, (k_sor<LAT, P, true>), dim3(h->sor_blocks), dim3(256), k, 0, s);
-                    LAUNCH(KC_SOR, (k_sor<LAT, P, true>), dim3(h->sor_blocks), dim3(256), k, 1, s);
-                    for (int lv = 1; lv <= h->seam_levels; ++lv) {
-                        LAUNCH(KC_SOR, (k_sor_seam<LAT, P>), dim3(h->seam_tiles), dim3(256), k, lv, 0, s);
-                        LAUNCH(KC_SOR, (k_sor_seam<LAT, P>), dim3(h->seam_tiles), dim3(256), k, lv, 1, s);
-                    }
-                }
-                LAUNCH(KC_OTHER, (k_sor_done<R>), dim3(1), dim3(64), k, h->sweeps_launch);
-                totals(h, 1 - k.lev, 1 - k.pc, 1.0, 1);
-                h->pc = 1 - h->pc;
-                h->fd_hist += 1;
-            }
+            if (h->p.fd_enable && !h->fd_off) fd_block(h);
             h->fc = 1 - h->fc;
             h->step += 1;
             sync_levels(h);
@@ -1811,14 +1993,17 @@ template <int LAT, class P> struct Impl {
     // Counters of a handle after two steps (what two eager steps leave behind).
     static void advance_two(lbfd_handle *h)
     {
-        if (h->p.fd_enable) h->fd_hist += 2;
+        if (h->p.fd_enable && !h->fd_off) {
+            h->fd_hist += 2;
+            // two pc flips leave pc as it was
+        }
         h->step += 2;
         sync_levels(h);
     }
 
     static bool replayable(const lbfd_handle *h)
     {
-        return h->step >= 1 && (h->fd_hist >= 1 || !h->p.fd_enable);
+        return h->step >= 1 && (h->fd_hist >= 1 || !h->p.fd_enable || h->fd_off);
     }
 
     // Record `two_steps` (which issues two steps on h->stream and advances the
@@ -1862,9 +2047,9 @@ template <int LAT, class P> struct Impl {
         const lbfd_handle *h = hs[0];
         const int lev = (int)(h->step & 1);
         for (auto &e : g.cache)
-            if (e.fc == h->fc && e.pc == h->pc && e.lev == lev) return e.exec;
+            if (e.fc == h->fc && e.pc == h->pc && e.lev == lev && e.fd_off == h->fd_off) return e.exec;
         hipGraphExec_t ex = capture(g, hs, two);
-        if (ex) g.cache.push_back(StepGraph{h->fc, h->pc, lev, ex});
+        if (ex) g.cache.push_back(StepGraph{h->fc, h->pc, lev, h->fd_off, ex});
         return ex;
     }
 
@@ -2020,13 +2205,23 @@ struct Dispatch {
     int (*batch_step)(lbfd_batch *, long long);
     int (*batch_table)(lbfd_batch *);
     size_t kp_bytes;
+    int (*fd_substeps)(lbfd_handle *, long long);
+    int (*sg_features)(lbfd_handle *, uint16_t *, float, float, float);
+    int (*sg_snapshot)(lbfd_handle *, float *);
+    int (*sg_tiles)(lbfd_handle *, const uint16_t *, const float *, const int *, int, int, uint16_t *, float *, float,
+                    float);
+    int (*sg_candidate)(lbfd_handle *, const float *, float, float);
+    int (*sg_accept)(lbfd_handle *);
+    int (*read_scalars)(lbfd_handle *, DevScalars *);
 };
 
 template <int LAT, class P> Dispatch make_dispatch()
 {
-    return Dispatch{&Impl<LAT, P>::init,        &Impl<LAT, P>::set_state,  &Impl<LAT, P>::step,
-                    &Impl<LAT, P>::observables, &Impl<LAT, P>::read_field, &Impl<LAT, P>::batch_step,
-                    &Impl<LAT, P>::batch_table, sizeof(KP<typename P::R>)};
+    using I = Impl<LAT, P>;
+    return Dispatch{&I::init,        &I::set_state,   &I::step,        &I::observables, &I::read_field,
+                    &I::batch_step,  &I::batch_table, sizeof(KP<typename P::R>),
+                    &I::fd_substeps, &I::sg_features, &I::sg_snapshot, &I::sg_tiles,      &I::sg_candidate,
+                    &I::sg_accept,   &I::read_scalars};
 }
 
 Dispatch dispatch_for(int lat, int prec)
@@ -2156,6 +2351,13 @@ int lbfd_read_field(lbfd_handle *h, int32_t field, double *host, size_t count)
     int st = dispatch_for(h->p.lattice, h->p.precision).read_field(h, field, host, count);
     if (st != LBFD_OK) return st;
     return sticky_status(h);
+}
+
+int lbfd_set_fd(lbfd_handle *h, int32_t enable)
+{
+    if (!h) return LBFD_EINVAL;
+    h->fd_off = enable == 0;
+    return LBFD_OK;
 }
 
 int lbfd_set_graphs(lbfd_handle *h, int32_t enable)
@@ -2337,6 +2539,387 @@ int lbfd_batch_step(lbfd_batch *b, int64_t n)
         if (h->step != h0->step || h->fc != h0->fc || h->pc != h0->pc || h->fd_hist != h0->fd_hist)
             return LBFD_EINVAL;
     return dispatch_for(h0->p.lattice, h0->p.precision).batch_step(b, n);
+}
+
+// ------------------------------------------------------------------ frozen-flow substeps
+
+int lbfd_fd_substeps(lbfd_handle *h, int64_t k)
+{
+    if (!h || k < 0) return LBFD_EINVAL;
+    return dispatch_for(h->p.lattice, h->p.precision).fd_substeps(h, k);
+}
+
+// ------------------------------------------------------------------ learned surrogate
+
+struct lbfd_sg {
+    lbfd_sg_params p;
+    hipStream_t stream;
+    sg::Net net;
+    float *gflat;            // gradient in parameter order [n_params]
+    double *loss;            // FP64 loss accumulator
+    uint16_t *act[3];        // outputs of layers 1-3, BF16 [nodes][32]
+    uint16_t *dy[2];         // gradients of layer outputs, BF16 [nodes][32]
+    float *out;              // network output, FP32 [nodes][2]
+    uint16_t *feat;          // whole-field input grid, BF16 [nz+8][ny+8][nx+8][16]
+    int *org;                // tile origins [3 max_batch]
+    long long cap_act, cap_out, cap_feat;
+    long long t;             // Adam steps taken
+};
+
+static long long cube(long long e) { return e * e * e; }
+
+// Nodes of the outputs of layer l (1..4) for B grids of d x h x w input nodes.
+static long long layer_nodes(int l, long long B, long long d, long long h, long long w)
+{
+    return B * (d - 2 * l) * (h - 2 * l) * (w - 2 * l);
+}
+
+struct SgLayout {
+    size_t master, m, v, gflat, gw[sg::NL], gb[sg::NL], wb[sg::NL], wt[sg::NL], bias[sg::NL];
+    size_t loss, act[3], dy[2], out, feat, org, total;
+    long long cap_act, cap_out, cap_feat;
+};
+
+static int sg_layout(const lbfd_sg_params *p, SgLayout *L)
+{
+    if (!p || p->tile < 1 || p->tile > 64 || p->max_batch < 1 || p->k < 1) return LBFD_EINVAL;
+    if (!(p->psi_inf > 0 && p->phi_s > 0 && p->u_s > 0 && p->dpsi_s > 0 && p->dphi_s > 0)) return LBFD_EINVAL;
+    if (!(p->lr > 0 && p->beta1 >= 0 && p->beta1 < 1 && p->beta2 >= 0 && p->beta2 < 1 && p->adam_eps > 0))
+        return LBFD_EINVAL;
+    const bool field = p->field[0] > 0 || p->field[1] > 0 || p->field[2] > 0;
+    if (field && (p->field[0] < 1 || p->field[1] < 1 || p->field[2] < 1)) return LBFD_EINVAL;
+    const long long T = p->tile, B = p->max_batch;
+    long long ca = layer_nodes(1, B, T + 8, T + 8, T + 8), co = B * cube(T), cf = 0;
+    if (field) {
+        const long long fx = p->field[0] + 8, fy = p->field[1] + 8, fz = p->field[2] + 8;
+        ca = std::max(ca, layer_nodes(1, 1, fz, fy, fx));
+        co = std::max(co, layer_nodes(4, 1, fz, fy, fx));
+        cf = fx * fy * fz;
+    }
+    if (ca * sg::CO * 2 > (1LL << 40)) return LBFD_EINVAL;
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o += align256(b); return r; };
+    const size_t np = (size_t)sg::n_params();
+    L->master = take(4 * np);
+    L->m = take(4 * np);
+    L->v = take(4 * np);
+    L->gflat = take(4 * np);
+    for (int l = 0; l < sg::NL; ++l) {
+        L->gw[l] = take(4 * 27 * sg::CIN_PAD[l] * sg::CO);
+        L->gb[l] = take(4 * sg::CO);
+        L->wb[l] = take(2 * 27 * sg::CIN_PAD[l] * sg::CO);
+        L->wt[l] = take(2 * 27 * sg::CIN_PAD[l] * sg::CO);
+        L->bias[l] = take(4 * sg::CO);
+    }
+    L->loss = take(8);
+    for (int i = 0; i < 3; ++i) L->act[i] = take((size_t)ca * sg::CO * 2);
+    for (int i = 0; i < 2; ++i) L->dy[i] = take((size_t)ca * sg::CO * 2);
+    L->out = take((size_t)co * 2 * 4);
+    L->feat = take((size_t)cf * sg::IN_CH * 2);
+    L->org = take(sizeof(int) * 3 * (size_t)B);
+    L->total = o;
+    L->cap_act = ca;
+    L->cap_out = co;
+    L->cap_feat = cf;
+    return LBFD_OK;
+}
+
+int64_t lbfd_sg_n_params(void) { return sg::n_params(); }
+
+int lbfd_sg_workspace_bytes(const lbfd_sg_params *p, size_t *bytes)
+{
+    if (!bytes) return LBFD_EINVAL;
+    SgLayout L;
+    int st = sg_layout(p, &L);
+    if (st != LBFD_OK) return st;
+    *bytes = L.total;
+    return LBFD_OK;
+}
+
+int lbfd_sg_create(const lbfd_sg_params *p, void *d_workspace, size_t bytes, void *stream, lbfd_sg **out)
+{
+    if (!out) return LBFD_EINVAL;
+    *out = nullptr;
+    SgLayout L;
+    int st = sg_layout(p, &L);
+    if (st != LBFD_OK) return st;
+    if (!d_workspace || bytes < L.total || ((uintptr_t)d_workspace & 255) != 0) return LBFD_EWORKSPACE;
+    lbfd_sg *s = new (std::nothrow) lbfd_sg();
+    if (!s) return LBFD_ENOMEM;
+    char *ws = (char *)d_workspace;
+    s->p = *p;
+    s->stream = (hipStream_t)stream;
+    s->net.master = (float *)(ws + L.master);
+    s->net.m = (float *)(ws + L.m);
+    s->net.v = (float *)(ws + L.v);
+    for (int l = 0; l < sg::NL; ++l) {
+        s->net.gw[l] = (float *)(ws + L.gw[l]);
+        s->net.gb[l] = (float *)(ws + L.gb[l]);
+        s->net.wb[l] = (uint16_t *)(ws + L.wb[l]);
+        s->net.wt[l] = (uint16_t *)(ws + L.wt[l]);
+        s->net.bias[l] = (float *)(ws + L.bias[l]);
+    }
+    s->gflat = (float *)(ws + L.gflat);
+    s->loss = (double *)(ws + L.loss);
+    for (int i = 0; i < 3; ++i) s->act[i] = (uint16_t *)(ws + L.act[i]);
+    for (int i = 0; i < 2; ++i) s->dy[i] = (uint16_t *)(ws + L.dy[i]);
+    s->out = (float *)(ws + L.out);
+    s->feat = (uint16_t *)(ws + L.feat);
+    s->org = (int *)(ws + L.org);
+    s->cap_act = L.cap_act;
+    s->cap_out = L.cap_out;
+    s->cap_feat = L.cap_feat;
+    s->t = 0;
+    // weights, moments and the padded layouts start at zero
+    if (hipMemsetAsync(ws, 0, L.loss, s->stream) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) {
+        delete s;
+        return LBFD_EHIP;
+    }
+    *out = s;
+    return LBFD_OK;
+}
+
+void lbfd_sg_destroy(lbfd_sg *s)
+{
+    if (!s) return;
+    hipStreamSynchronize(s->stream);
+    delete s;
+}
+
+static int sg_pack(lbfd_sg *s, hipStream_t st, int adam)
+{
+    const double b1 = s->p.beta1, b2 = s->p.beta2;
+    const float c1 = adam ? (float)(1.0 - std::pow(b1, (double)s->t)) : 1.0f;
+    const float c2 = adam ? (float)(1.0 - std::pow(b2, (double)s->t)) : 1.0f;
+    hipLaunchKernelGGL(sg::k_adam_pack, dim3((unsigned)((sg::n_params() + 255) / 256)), dim3(256), 0, st, s->net,
+                       adam, (float)s->p.lr, (float)b1, (float)b2, (float)s->p.adam_eps, c1, c2);
+    return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+}
+
+int lbfd_sg_set_params(lbfd_sg *s, const float *host, int64_t n)
+{
+    if (!s || !host || n != sg::n_params()) return LBFD_EINVAL;
+    const size_t b = sizeof(float) * (size_t)n;
+    if (hipMemcpyAsync(s->net.master, host, b, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemsetAsync(s->net.m, 0, b, s->stream) != hipSuccess ||
+        hipMemsetAsync(s->net.v, 0, b, s->stream) != hipSuccess)
+        return LBFD_EHIP;
+    s->t = 0;
+    int st = sg_pack(s, s->stream, 0);
+    if (st != LBFD_OK) return st;
+    return hipStreamSynchronize(s->stream) == hipSuccess ? LBFD_OK : LBFD_EHIP;
+}
+
+int lbfd_sg_get_params(lbfd_sg *s, float *host, int64_t n)
+{
+    if (!s || !host || n != sg::n_params()) return LBFD_EINVAL;
+    if (hipMemcpyAsync(host, s->net.master, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, s->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return LBFD_EHIP;
+    return LBFD_OK;
+}
+
+static unsigned blocks_for(long long n, long long per) { return (unsigned)((n + per - 1) / per); }
+
+// Forward pass over B grids of d x h x w input nodes on stream st; the layer
+// outputs stay in s->act for a backward pass.
+static int sg_forward_on(lbfd_sg *s, hipStream_t st, const uint16_t *in, int B, int d, int h, int w, float *out)
+{
+    if (!s || !in || !out || B < 1 || d < 9 || h < 9 || w < 9) return LBFD_EINVAL;
+    const long long M1 = layer_nodes(1, B, d, h, w), M4 = layer_nodes(4, B, d, h, w);
+    if (M1 > s->cap_act || M4 > s->cap_out) return LBFD_EINVAL;
+    const void *x = in;
+    for (int l = 0; l < sg::NL; ++l) {
+        const int Di = d - 2 * l, Hi = h - 2 * l, Wi = w - 2 * l;
+        const long long M = layer_nodes(l + 1, B, d, h, w);
+        const dim3 grid(blocks_for(M, 256));
+        if (l == 0)
+            hipLaunchKernelGGL((sg::k_conv_fwd<16, true, false>), grid, dim3(256), 0, st, (const uint16_t *)x,
+                               s->net.wb[0], s->net.bias[0], (void *)s->act[0], Di, Hi, Wi, M);
+        else if (l < 3)
+            hipLaunchKernelGGL((sg::k_conv_fwd<32, true, false>), grid, dim3(256), 0, st, (const uint16_t *)x,
+                               s->net.wb[l], s->net.bias[l], (void *)s->act[l], Di, Hi, Wi, M);
+        else
+            hipLaunchKernelGGL((sg::k_conv_fwd<32, false, true>), grid, dim3(256), 0, st, (const uint16_t *)x,
+                               s->net.wb[3], s->net.bias[3], (void *)out, Di, Hi, Wi, M);
+        if (l < 3) x = s->act[l];
+    }
+    return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+}
+
+int lbfd_sg_forward(lbfd_sg *s, const uint16_t *d_in, int32_t B, int32_t d, int32_t h, int32_t w, float *d_out)
+{
+    return sg_forward_on(s, s ? s->stream : nullptr, d_in, B, d, h, w, d_out);
+}
+
+// Loss and gradients of B training tiles (gradients in s->net.gw / gb).
+static int sg_backward(lbfd_sg *s, const uint16_t *in, const float *tgt, int B)
+{
+    hipStream_t st = s->stream;
+    const int E = s->p.tile + 8;
+    int rc = sg_forward_on(s, st, in, B, E, E, E, s->out);
+    if (rc != LBFD_OK) return rc;
+    for (int l = 0; l < sg::NL; ++l) {
+        if (hipMemsetAsync(s->net.gw[l], 0, sizeof(float) * 27 * sg::CIN_PAD[l] * sg::CO, st) != hipSuccess ||
+            hipMemsetAsync(s->net.gb[l], 0, sizeof(float) * sg::CO, st) != hipSuccess)
+            return LBFD_EHIP;
+    }
+    if (hipMemsetAsync(s->loss, 0, sizeof(double), st) != hipSuccess) return LBFD_EHIP;
+    const long long M4 = layer_nodes(4, B, E, E, E);
+    const float scale = (float)(2.0 / (2.0 * (double)M4));
+    hipLaunchKernelGGL(sg::k_loss, dim3(std::min(1024u, blocks_for(M4, 256))), dim3(256), 0, st, s->out, tgt, M4,
+                       scale, s->loss, s->dy[0]);
+    int cur = 0;   // s->dy[cur]: gradient at the output of layer l + 1
+    for (int l = sg::NL - 1; l >= 0; --l) {
+        const int Di = E - 2 * l;
+        const long long M = layer_nodes(l + 1, B, E, E, E);
+        const uint16_t *x = l == 0 ? in : s->act[l - 1];
+        const long long S = std::min<long long>(256, std::max<long long>(1, (M + 4095) / 4096));
+        const long long per = ((M + S - 1) / S + 63) / 64 * 64;
+        if (l == 0)
+            hipLaunchKernelGGL((sg::k_conv_wgrad<16>), dim3(27, (unsigned)S), dim3(256), 0, st, x, s->dy[cur],
+                               s->net.gw[l], Di, Di, Di, M, per);
+        else
+            hipLaunchKernelGGL((sg::k_conv_wgrad<32>), dim3(27, (unsigned)S), dim3(256), 0, st, x, s->dy[cur],
+                               s->net.gw[l], Di, Di, Di, M, per);
+        hipLaunchKernelGGL(sg::k_bias_grad, dim3(std::min(1024u, blocks_for(M, 2048))), dim3(256), 0, st,
+                           s->dy[cur], M, s->net.gb[l]);
+        if (l > 0) {
+            const long long Mi = layer_nodes(l, B, E, E, E);
+            hipLaunchKernelGGL(sg::k_conv_dgrad, dim3(blocks_for(Mi, 256)), dim3(256), 0, st, s->dy[cur],
+                               s->net.wt[l], s->act[l - 1], s->dy[1 - cur], Di, Di, Di, Mi);
+            cur = 1 - cur;
+        }
+    }
+    return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+}
+
+static int sg_check_tiles(lbfd_sg *s, const uint16_t *in, const float *tgt, int B)
+{
+    if (!s || !in || !tgt || B < 1 || B > s->p.max_batch) return LBFD_EINVAL;
+    return LBFD_OK;
+}
+
+int lbfd_sg_gradient(lbfd_sg *s, const uint16_t *d_in, const float *d_target, int32_t B, double *loss,
+                     float *host_grad, int64_t n)
+{
+    int rc = sg_check_tiles(s, d_in, d_target, B);
+    if (rc != LBFD_OK) return rc;
+    if (!host_grad || n != sg::n_params()) return LBFD_EINVAL;
+    rc = sg_backward(s, d_in, d_target, B);
+    if (rc != LBFD_OK) return rc;
+    hipLaunchKernelGGL(sg::k_grad_flat, dim3(blocks_for(sg::n_params(), 256)), dim3(256), 0, s->stream, s->net,
+                       s->gflat);
+    double L = 0.0;
+    if (hipMemcpyAsync(host_grad, s->gflat, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, s->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(&L, s->loss, sizeof(double), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return LBFD_EHIP;
+    const long long E = s->p.tile;
+    if (loss) *loss = L / (2.0 * (double)B * (double)cube(E));
+    return LBFD_OK;
+}
+
+int lbfd_sg_train_step(lbfd_sg *s, const uint16_t *d_in, const float *d_target, int32_t B, double *loss)
+{
+    int rc = sg_check_tiles(s, d_in, d_target, B);
+    if (rc != LBFD_OK) return rc;
+    rc = sg_backward(s, d_in, d_target, B);
+    if (rc != LBFD_OK) return rc;
+    s->t += 1;
+    rc = sg_pack(s, s->stream, 1);
+    if (rc != LBFD_OK) return rc;
+    if (loss) {
+        double L = 0.0;
+        if (hipMemcpyAsync(&L, s->loss, sizeof(double), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+            hipStreamSynchronize(s->stream) != hipSuccess)
+            return LBFD_EHIP;
+        *loss = L / (2.0 * (double)B * (double)cube(s->p.tile));
+    }
+    return LBFD_OK;
+}
+
+static bool sg_periodic(const lbfd_handle *h)
+{
+    const int D = h->p.lattice == LBFD_D3Q19 ? 3 : 2;
+    for (int a = 0; a < D; ++a)
+        if (h->p.bc[a] != LBFD_PERIODIC) return false;
+    return true;
+}
+
+static bool sg_fits_field(const lbfd_sg *s, const lbfd_handle *h)
+{
+    return h->p.nx <= s->p.field[0] && h->p.ny <= s->p.field[1] && h->p.nz <= s->p.field[2];
+}
+
+int lbfd_sg_features(lbfd_handle *h, lbfd_sg *s, uint16_t *d_feat)
+{
+    if (!h || !s || !d_feat || !sg_periodic(h)) return LBFD_EINVAL;
+    return dispatch_for(h->p.lattice, h->p.precision)
+        .sg_features(h, d_feat, (float)(1.0 / s->p.psi_inf), (float)(1.0 / s->p.phi_s), (float)(1.0 / s->p.u_s));
+}
+
+int lbfd_sg_snapshot(lbfd_handle *h, lbfd_sg *s, float *d_snap)
+{
+    if (!h || !s || !d_snap) return LBFD_EINVAL;
+    return dispatch_for(h->p.lattice, h->p.precision).sg_snapshot(h, d_snap);
+}
+
+int lbfd_sg_tiles(lbfd_handle *h, lbfd_sg *s, const uint16_t *d_feat, const float *d_snap, const int32_t *host_org,
+                  int32_t B, uint16_t *d_in, float *d_target)
+{
+    if (!h || !s || !d_feat || !d_snap || !host_org || !d_in || !d_target || B < 1 || B > s->p.max_batch)
+        return LBFD_EINVAL;
+    const int T = s->p.tile;
+    for (int b = 0; b < B; ++b) {
+        const int x = host_org[3 * b], y = host_org[3 * b + 1], z = host_org[3 * b + 2];
+        if (x < 0 || y < 0 || z < 0 || x + T > h->p.nx || y + T > h->p.ny || z + T > h->p.nz) return LBFD_EINVAL;
+    }
+    if (hipMemcpyAsync(s->org, host_org, sizeof(int) * 3 * (size_t)B, hipMemcpyHostToDevice, h->stream) !=
+        hipSuccess)
+        return LBFD_EHIP;
+    return dispatch_for(h->p.lattice, h->p.precision)
+        .sg_tiles(h, d_feat, d_snap, s->org, B, T, d_in, d_target, (float)(1.0 / s->p.dpsi_s),
+                  (float)(1.0 / s->p.dphi_s));
+}
+
+int lbfd_sg_advance(lbfd_handle *h, lbfd_sg *s, int64_t nblocks, lbfd_sg_report *rep)
+{
+    if (!h || !s || nblocks < 0 || !h->p.fd_enable || !sg_periodic(h) || !sg_fits_field(s, h)) return LBFD_EINVAL;
+    Dispatch dp = dispatch_for(h->p.lattice, h->p.precision);
+    const int k = s->p.k;
+    for (int64_t blk = 0; blk < nblocks; ++blk) {
+        int rc = dp.sg_features(h, s->feat, (float)(1.0 / s->p.psi_inf), (float)(1.0 / s->p.phi_s),
+                                (float)(1.0 / s->p.u_s));
+        if (rc == LBFD_OK)
+            rc = sg_forward_on(s, h->stream, s->feat, 1, h->p.nz + 8, h->p.ny + 8, h->p.nx + 8, s->out);
+        if (rc == LBFD_OK) rc = dp.sg_candidate(h, s->out, (float)s->p.dpsi_s, (float)s->p.dphi_s);
+        DevScalars sc;
+        if (rc == LBFD_OK) rc = dp.read_scalars(h, &sc);
+        if (rc != LBFD_OK) return rc;
+        const double drift = sc.drift_pre;
+        const bool keep = std::isfinite(drift) && std::fabs(drift) <= s->p.drift_tol;
+        rc = keep ? dp.sg_accept(h) : dp.fd_substeps(h, k);
+        if (rc != LBFD_OK) return rc;
+        if (rep) {
+            rep->blocks += 1;
+            rep->last_drift = drift;
+            if (keep) {
+                rep->accepted += 1;
+                rep->max_drift = std::max(rep->max_drift, std::fabs(drift));
+            } else {
+                rep->fallbacks += 1;
+            }
+        }
+        const bool was = h->fd_off;
+        h->fd_off = true;
+        rc = dp.step(h, k);
+        h->fd_off = was;
+        if (rc != LBFD_OK) return rc;
+    }
+    return LBFD_OK;
 }
 
 const char *lbfd_strerror(int s)

@@ -1,0 +1,382 @@
+// Matrix-core kernels of the learned surrogate: 3x3x3 "valid" convolutions over
+// channels-last BF16 grids with FP32 accumulation (v_mfma_f32_32x32x16_bf16), their
+// two gradients, the loss and the Adam update. A method addition: the paper has no
+// surrogate; the network and its training are defined in the public header.
+//
+// Every layer is an implicit GEMM. Forward: rows = output nodes, columns = the 32
+// (padded) output channels, reduction over 27 taps x input channels; one wavefront
+// computes two 32 x 32 tiles, the layer's weights sit in LDS. Input gradient: rows =
+// input nodes, columns = input channels, reduction over taps x output channels
+// (the transposed weights). Weight gradient: one 32 x 32 tile (input x output
+// channels) per tap, reduction over nodes in 64-node chunks staged in LDS
+// transposed so every operand fragment is a 16-byte LDS read; partial tiles meet
+// in FP32 atomics.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbfd {
+namespace sg {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16;
+
+constexpr int NL = 4;                                  // layers
+constexpr int CO = 32;                                 // padded output channels of every layer
+constexpr int CIN_REAL[NL] = {6, 32, 32, 32};
+constexpr int CIN_PAD[NL] = {16, 32, 32, 32};
+constexpr int COUT_REAL[NL] = {32, 32, 32, 2};
+constexpr int IN_CH = 16;                              // channels of an input grid (6 used)
+
+__host__ __device__ constexpr long long layer_params(int l) { return 27LL * CIN_REAL[l] * COUT_REAL[l] + COUT_REAL[l]; }
+__host__ __device__ constexpr long long n_params()
+{
+    return layer_params(0) + layer_params(1) + layer_params(2) + layer_params(3);
+}
+
+// Round to nearest even; NaN stays NaN.
+__device__ __forceinline__ u16 f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u16)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 frag(const u16 *p) { return __builtin_bit_cast(bf16x8, *(const u32x4 *)p); }
+__device__ __forceinline__ bf16x8 frag_zero() { return __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u}); }
+
+// Row of the 32 x 32 result held by register r of a lane in lane group kg (the
+// column is the lane index mod 32).
+__device__ __forceinline__ int acc_row(int r, int kg) { return 8 * (r >> 2) + 4 * kg + (r & 3); }
+
+// Forward layer: out[m][o] = act(b[o] + sum_{tap,i} in[m + tap][i] w[tap][o][i]) over the
+// M = B (Di-2)(Hi-2)(Wi-2) output nodes. wb: BF16 [27][32][CIN] (input channel fastest).
+// out: BF16 [M][32], or with OUTF32 FP32 [M][2] (the first two channels, no activation).
+template <int CIN, bool RELU, bool OUTF32>
+__global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ in, const u16 *__restrict__ wb,
+                                                 const float *__restrict__ bias, void *__restrict__ out, int Di,
+                                                 int Hi, int Wi, long long M)
+{
+    constexpr int LDW = CIN + 8;   // padded LDS row
+    __shared__ __attribute__((aligned(16))) u16 sw[27 * CO * LDW];
+    for (int i = threadIdx.x; i < 27 * CO * (CIN / 8); i += 256) {
+        const int row = i / (CIN / 8), piece = i % (CIN / 8);
+        *(u32x4 *)&sw[row * LDW + piece * 8] = *(const u32x4 *)&wb[row * CIN + piece * 8];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int mr = lane & 31, kg = lane >> 5;
+    const int Do = Di - 2, Ho = Hi - 2, Wo = Wi - 2;
+    const long long m0 = ((long long)blockIdx.x * 4 + wave) * 64;
+    long long base[2];
+    bool ok[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const long long m = m0 + 32 * t + mr;
+        ok[t] = m < M;
+        long long r = ok[t] ? m : 0;
+        const int x = (int)(r % Wo);
+        r /= Wo;
+        const int y = (int)(r % Ho);
+        r /= Ho;
+        const int z = (int)(r % Do);
+        const long long b = r / Do;
+        base[t] = (((b * Di + z) * Hi + y) * (long long)Wi + x) * CIN + kg * 8;
+    }
+    f32x16 acc[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
+    for (int a = 0; a < 3; ++a)
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int tap = (a * 3 + p) * 3 + q;
+                const long long toff = ((long long)(a * Hi + p) * Wi + q) * CIN;
+#pragma unroll
+                for (int c = 0; c < CIN / 16; ++c) {
+                    const bf16x8 B = frag(&sw[(tap * CO + mr) * LDW + c * 16 + kg * 8]);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const bf16x8 A = ok[t] ? frag(in + base[t] + toff + c * 16) : frag_zero();
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[t], 0, 0, 0);
+                    }
+                }
+            }
+    const float bv = bias[mr];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const long long m = m0 + 32 * t + acc_row(r, kg);
+            if (m >= M) continue;
+            float v = acc[t][r] + bv;
+            if constexpr (OUTF32) {
+                if (mr < 2) ((float *)out)[m * 2 + mr] = v;
+            } else {
+                if (RELU) v = fmaxf(v, 0.0f);
+                ((u16 *)out)[m * CO + mr] = f2bf(v);
+            }
+        }
+}
+
+// Input gradient of a layer with 32 input channels, with the ReLU of the layer below
+// applied: dx[v][i] = [x[v][i] > 0] sum_{tap,o} dy[v - tap][o] w[tap][i][o], over the
+// Mi = B Di Hi Wi input nodes. wt: BF16 [27][32 (i)][32 (o)] (output channel fastest).
+// x: the layer's input (BF16 [Mi][32]); dy: BF16 [B][Di-2][Hi-2][Wi-2][32].
+__global__ __launch_bounds__(256) void k_conv_dgrad(const u16 *__restrict__ dy, const u16 *__restrict__ wt,
+                                                   const u16 *__restrict__ x, u16 *__restrict__ dx, int Di, int Hi,
+                                                   int Wi, long long Mi)
+{
+    constexpr int LDW = CO + 8;
+    __shared__ __attribute__((aligned(16))) u16 sw[27 * CO * LDW];
+    for (int i = threadIdx.x; i < 27 * CO * (CO / 8); i += 256) {
+        const int row = i / (CO / 8), piece = i % (CO / 8);
+        *(u32x4 *)&sw[row * LDW + piece * 8] = *(const u32x4 *)&wt[row * CO + piece * 8];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int mr = lane & 31, kg = lane >> 5;
+    const int Do = Di - 2, Ho = Hi - 2, Wo = Wi - 2;
+    const long long m0 = ((long long)blockIdx.x * 4 + wave) * 64;
+    int xx[2], yy[2], zz[2];
+    long long bb[2];
+    bool ok[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const long long m = m0 + 32 * t + mr;
+        ok[t] = m < Mi;
+        long long r = ok[t] ? m : 0;
+        xx[t] = (int)(r % Wi);
+        r /= Wi;
+        yy[t] = (int)(r % Hi);
+        r /= Hi;
+        zz[t] = (int)(r % Di);
+        bb[t] = r / Di;
+    }
+    f32x16 acc[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
+    for (int a = 0; a < 3; ++a)
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int tap = (a * 3 + p) * 3 + q;
+                long long src[2];
+                bool in_range[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int z = zz[t] - a, y = yy[t] - p, x = xx[t] - q;
+                    in_range[t] = ok[t] && z >= 0 && z < Do && y >= 0 && y < Ho && x >= 0 && x < Wo;
+                    src[t] = in_range[t] ? ((((bb[t] * Do + z) * Ho + y) * (long long)Wo + x) * CO + kg * 8) : 0;
+                }
+#pragma unroll
+                for (int c = 0; c < CO / 16; ++c) {
+                    const bf16x8 B = frag(&sw[(tap * CO + mr) * LDW + c * 16 + kg * 8]);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const bf16x8 A = in_range[t] ? frag(dy + src[t] + c * 16) : frag_zero();
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[t], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const long long m = m0 + 32 * t + acc_row(r, kg);
+            if (m >= Mi) continue;
+            const u16 xv = x[m * CO + mr];
+            const bool active = (xv & 0x8000u) == 0 && xv != 0;   // x > 0 (x is a ReLU output)
+            dx[m * CO + mr] = active ? f2bf(acc[t][r]) : (u16)0;
+        }
+}
+
+// Weight gradient of a layer: dw[tap][i][o] += sum_v x[v + tap][i] dy[v][o] over the
+// output nodes [v0, v1) of this block's split; grid (27 taps, splits). x: BF16 layer
+// input [B][Di][Hi][Wi][CIN]; dy: BF16 [M][32]; dw: FP32 [27][CIN][32].
+template <int CIN>
+__global__ __launch_bounds__(256) void k_conv_wgrad(const u16 *__restrict__ x, const u16 *__restrict__ dy,
+                                                   float *__restrict__ dw, int Di, int Hi, int Wi, long long M,
+                                                   long long per_split)
+{
+    constexpr int LDV = 64 + 8;
+    __shared__ __attribute__((aligned(16))) u16 xs[32 * LDV];   // [channel][node]
+    __shared__ __attribute__((aligned(16))) u16 ds[32 * LDV];
+    __shared__ float red[3][16][64];
+    const int tap = blockIdx.x;
+    const int a = tap / 9, p = (tap / 3) % 3, q = tap % 3;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int mr = lane & 31, kg = lane >> 5;
+    const int Do = Di - 2, Ho = Hi - 2, Wo = Wi - 2;
+    const long long v_begin = (long long)blockIdx.y * per_split;
+    long long v_end = v_begin + per_split;
+    if (v_end > M) v_end = M;
+    if (CIN < 32)
+        for (int i = threadIdx.x; i < (32 - CIN) * LDV; i += 256) xs[CIN * LDV + i] = 0;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    const int j = threadIdx.x & 63, part = threadIdx.x >> 6;   // staging: node j, channels part*8..+7
+    for (long long v0 = v_begin; v0 < v_end; v0 += 64) {
+        const long long m = v0 + j;
+        const bool ok = m < v_end;
+        u32x4 xv = {0u, 0u, 0u, 0u}, dv = {0u, 0u, 0u, 0u};
+        if (ok) {
+            long long r = m;
+            const int xo = (int)(r % Wo);
+            r /= Wo;
+            const int yo = (int)(r % Ho);
+            r /= Ho;
+            const int zo = (int)(r % Do);
+            const long long b = r / Do;
+            const long long src = (((b * Di + zo + a) * Hi + yo + p) * (long long)Wi + xo + q) * CIN;
+            if (part * 8 < CIN) xv = *(const u32x4 *)&x[src + part * 8];
+            dv = *(const u32x4 *)&dy[m * CO + part * 8];
+        }
+        const u16 *xe = (const u16 *)&xv, *de = (const u16 *)&dv;
+        if (part * 8 < CIN)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) xs[(part * 8 + e) * LDV + j] = xe[e];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ds[(part * 8 + e) * LDV + j] = de[e];
+        __syncthreads();
+        const bf16x8 A = frag(&xs[mr * LDV + 16 * wave + 8 * kg]);
+        const bf16x8 B = frag(&ds[mr * LDV + 16 * wave + 8 * kg]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc, 0, 0, 0);
+        __syncthreads();
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[wave - 1][r][lane] = acc[r];
+    __syncthreads();
+    if (wave == 0)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float s = acc[r] + red[0][r][lane] + red[1][r][lane] + red[2][r][lane];
+            const int i = acc_row(r, kg);
+            if (i < CIN && s != 0.0f) atomicAdd(&dw[((long long)tap * CIN + i) * CO + mr], s);
+        }
+}
+
+// Bias gradient: db[o] += sum over nodes of dy[v][o] (BF16 [M][32]).
+__global__ __launch_bounds__(256) void k_bias_grad(const u16 *__restrict__ dy, long long M, float *__restrict__ db)
+{
+    __shared__ float sh[8][32];
+    const int o = threadIdx.x & 31, g = threadIdx.x >> 5;
+    float s = 0.0f;
+    for (long long m = (long long)blockIdx.x * 8 + g; m < M; m += (long long)gridDim.x * 8) s += bf2f(dy[m * CO + o]);
+    sh[g][o] = s;
+    __syncthreads();
+    if (g == 0) {
+        for (int k = 1; k < 8; ++k) s += sh[k][o];
+        atomicAdd(&db[o], s);
+    }
+}
+
+// Loss: squared error of the output o (FP32 [M][2]) against t, summed into *acc (FP64),
+// and the output gradient dy = scale (o - t) as BF16 [M][32] (channels 2.. zero).
+__global__ __launch_bounds__(256) void k_loss(const float *__restrict__ o, const float *__restrict__ t, long long M,
+                                             float scale, double *__restrict__ acc, u16 *__restrict__ dy)
+{
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (long long m = (long long)blockIdx.x * 256 + threadIdx.x; m < M; m += (long long)gridDim.x * 256) {
+        const float r0 = o[2 * m] - t[2 * m], r1 = o[2 * m + 1] - t[2 * m + 1];
+        s += (double)r0 * r0 + (double)r1 * r1;
+        u32x4 head = {(uint32_t)f2bf(scale * r0) | ((uint32_t)f2bf(scale * r1) << 16), 0u, 0u, 0u};
+        u32x4 zero = {0u, 0u, 0u, 0u};
+        u32x4 *d = (u32x4 *)&dy[m * CO];
+        d[0] = head;
+        d[1] = zero;
+        d[2] = zero;
+        d[3] = zero;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(acc, sh[0]);
+}
+
+// Device views of the parameters. Master weights in parameter order; gradients and
+// the BF16 copies in the padded layouts of the kernels above.
+struct Net {
+    float *master, *m, *v;      // FP32 [n_params]
+    float *gw[NL];              // FP32 [27][CIN_PAD][32] weight gradients
+    float *gb[NL];              // FP32 [32] bias gradients
+    u16 *wb[NL];                // BF16 [27][32][CIN_PAD] forward weights
+    u16 *wt[NL];                // BF16 [27][CIN_PAD][32] transposed weights
+    float *bias[NL];            // FP32 [32]
+};
+
+// Where parameter index k lives: layer, and either (tap, i, o) of a weight or o of a bias.
+__device__ __forceinline__ void param_site(long long k, int &l, int &tap, int &i, int &o, bool &is_bias)
+{
+    l = 0;
+    while (l < NL - 1 && k >= layer_params(l)) k -= layer_params(l++);
+    const long long nw = 27LL * CIN_REAL[l] * COUT_REAL[l];
+    is_bias = k >= nw;
+    if (is_bias) {
+        o = (int)(k - nw);
+        tap = i = 0;
+    } else {
+        o = (int)(k % COUT_REAL[l]);
+        const long long r = k / COUT_REAL[l];
+        i = (int)(r % CIN_REAL[l]);
+        tap = (int)(r / CIN_REAL[l]);
+    }
+}
+
+// Adam step (adam != 0, t = step count after this step) or a plain copy of the master
+// weights (adam == 0), then the BF16 copies and FP32 biases the kernels read.
+__global__ __launch_bounds__(256) void k_adam_pack(Net net, int adam, float lr, float b1, float b2, float eps,
+                                                  float c1, float c2)
+{
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n_params()) return;
+    int l, tap, i, o;
+    bool is_bias;
+    param_site(k, l, tap, i, o, is_bias);
+    float w = net.master[k];
+    if (adam) {
+        const float g = is_bias ? net.gb[l][o] : net.gw[l][((long long)tap * CIN_PAD[l] + i) * CO + o];
+        const float m = b1 * net.m[k] + (1.0f - b1) * g;
+        const float v = b2 * net.v[k] + (1.0f - b2) * g * g;
+        net.m[k] = m;
+        net.v[k] = v;
+        w -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+        net.master[k] = w;
+    }
+    if (is_bias) {
+        net.bias[l][o] = w;
+    } else {
+        const u16 h = f2bf(w);
+        net.wb[l][((long long)tap * CO + o) * CIN_PAD[l] + i] = h;
+        net.wt[l][((long long)tap * CIN_PAD[l] + i) * CO + o] = h;
+    }
+}
+
+// Gradients in parameter order (for export).
+__global__ __launch_bounds__(256) void k_grad_flat(Net net, float *out)
+{
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n_params()) return;
+    int l, tap, i, o;
+    bool is_bias;
+    param_site(k, l, tap, i, o, is_bias);
+    out[k] = is_bias ? net.gb[l][o] : net.gw[l][((long long)tap * CIN_PAD[l] + i) * CO + o];
+}
+
+}  // namespace sg
+}  // namespace lbfd

@@ -19,7 +19,11 @@ FIELDS = dict(f=0, rhoR=3, rhoB=4, rhoN=5, u=6, psi=7, phi=8, force=9, G=10, Spr
 EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_init_fields", "lbfd_set_state", "lbfd_step",
             "lbfd_observables", "lbfd_read_field", "lbfd_profile", "lbfd_profile_read", "lbfd_destroy",
             "lbfd_strerror", "lbfd_batch_workspace_bytes", "lbfd_batch_create", "lbfd_batch_instance",
-            "lbfd_batch_step", "lbfd_batch_destroy", "lbfd_set_graphs", "lbfd_batch_set_graphs"]
+            "lbfd_batch_step", "lbfd_batch_destroy", "lbfd_set_graphs", "lbfd_batch_set_graphs",
+            "lbfd_fd_substeps", "lbfd_set_fd",
+            "lbfd_sg_n_params", "lbfd_sg_workspace_bytes", "lbfd_sg_create", "lbfd_sg_set_params",
+            "lbfd_sg_get_params", "lbfd_sg_forward", "lbfd_sg_gradient", "lbfd_sg_train_step", "lbfd_sg_features",
+            "lbfd_sg_snapshot", "lbfd_sg_tiles", "lbfd_sg_advance", "lbfd_sg_destroy"]
 
 
 class LbfdError(RuntimeError):
@@ -67,6 +71,18 @@ class Obs(C.Structure):
 _lib = None
 
 
+class SgParams(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("max_batch", C.c_int32), ("field", C.c_int32 * 3), ("k", C.c_int32),
+                ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("adam_eps", C.c_double),
+                ("psi_inf", C.c_double), ("phi_s", C.c_double), ("u_s", C.c_double), ("dpsi_s", C.c_double),
+                ("dphi_s", C.c_double), ("drift_tol", C.c_double)]
+
+
+class SgReport(C.Structure):
+    _fields_ = [("blocks", C.c_int64), ("accepted", C.c_int64), ("fallbacks", C.c_int64),
+                ("max_drift", C.c_double), ("last_drift", C.c_double)]
+
+
 def library_path() -> str:
     return _build.LIB
 
@@ -105,6 +121,24 @@ def load(build_if_missing: bool = False):
     L.lbfd_batch_destroy.restype = None
     L.lbfd_set_graphs.argtypes = [vp, C.c_int32]
     L.lbfd_batch_set_graphs.argtypes = [vp, C.c_int32]
+    L.lbfd_fd_substeps.argtypes = [vp, C.c_int64]
+    L.lbfd_set_fd.argtypes = [vp, C.c_int32]
+    i32, i64, szp = C.c_int32, C.c_int64, P(C.c_size_t)
+    L.lbfd_sg_n_params.restype = i64
+    L.lbfd_sg_n_params.argtypes = []
+    L.lbfd_sg_workspace_bytes.argtypes = [P(SgParams), szp]
+    L.lbfd_sg_create.argtypes = [P(SgParams), vp, C.c_size_t, vp, P(vp)]
+    L.lbfd_sg_set_params.argtypes = [vp, P(C.c_float), i64]
+    L.lbfd_sg_get_params.argtypes = [vp, P(C.c_float), i64]
+    L.lbfd_sg_forward.argtypes = [vp, vp, i32, i32, i32, i32, vp]
+    L.lbfd_sg_gradient.argtypes = [vp, vp, vp, i32, P(C.c_double), P(C.c_float), i64]
+    L.lbfd_sg_train_step.argtypes = [vp, vp, vp, i32, P(C.c_double)]
+    L.lbfd_sg_features.argtypes = [vp, vp, vp]
+    L.lbfd_sg_snapshot.argtypes = [vp, vp, vp]
+    L.lbfd_sg_tiles.argtypes = [vp, vp, vp, vp, P(i32), i32, vp, vp]
+    L.lbfd_sg_advance.argtypes = [vp, vp, i64, P(SgReport)]
+    L.lbfd_sg_destroy.argtypes = [vp]
+    L.lbfd_sg_destroy.restype = None
     _lib = L
     return L
 
@@ -188,6 +222,16 @@ class _Instance:
         _check(load().lbfd_set_state(self.h, ptr(f, self.Q * N), ptr(rhoR, N), ptr(rhoB, N), ptr(psi, N),
                                      ptr(phi, N), ptr(Sprev, N), ptr(Bprev, N), int(step), float(M0)),
                "lbfd_set_state")
+        return self
+
+    def set_fd(self, enable: bool):
+        """Switch the FD part of step() off (psi, phi held) or on."""
+        _check(load().lbfd_set_fd(self.h, int(bool(enable))), "lbfd_set_fd")
+        return self
+
+    def fd_substeps(self, k: int):
+        """k FD updates of psi and phi with the flow frozen at the current state."""
+        _check(load().lbfd_fd_substeps(self.h, int(k)), "lbfd_fd_substeps")
         return self
 
     def observables(self, check=True) -> dict:
@@ -331,3 +375,104 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Surrogate:
+    """The learned surrogate of k frozen-flow FD substeps (weights, Adam state and
+    work buffers on one device workspace). Tensors passed in are torch device
+    tensors: inputs as int16/uint16-sized BF16 bit patterns (torch.bfloat16 is
+    accepted as is), targets and outputs FP32."""
+
+    DEFAULTS = dict(tile=32, max_batch=8, field=(0, 0, 0), k=8, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8,
+                    psi_inf=1.0, phi_s=0.1, u_s=0.01, dpsi_s=0.01, dphi_s=0.001, drift_tol=1e-6)
+
+    def __init__(self, device: str = "cuda:0", stream=None, **kw):
+        import torch
+
+        cfg = dict(self.DEFAULTS)
+        cfg.update(kw)
+        self.cfg = cfg
+        ps = SgParams()
+        for k, v in cfg.items():
+            if k == "field":
+                for a in range(3):
+                    ps.field[a] = int(v[a])
+            else:
+                setattr(ps, k, v)
+        self._ps = ps
+        L = load()
+        nb = C.c_size_t()
+        _check(L.lbfd_sg_workspace_bytes(C.byref(ps), C.byref(nb)), "lbfd_sg_workspace_bytes")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L.lbfd_sg_create(C.byref(ps), C.c_void_p(ptr), C.c_size_t(int(nb.value)),
+                                C.c_void_p(self.stream.cuda_stream), C.byref(h)), "lbfd_sg_create")
+        self.h = h
+        self.n = int(L.lbfd_sg_n_params())
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.lbfd_sg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(load().lbfd_sg_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size),
+               "lbfd_sg_set_params")
+        return self
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.n, dtype=np.float32)
+        _check(load().lbfd_sg_get_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size),
+               "lbfd_sg_get_params")
+        return a
+
+    def forward(self, x, out):
+        B, d, h, w, c = x.shape
+        assert c == 16 and x.is_contiguous() and out.is_contiguous()
+        _check(load().lbfd_sg_forward(self.h, _dptr(x), B, d, h, w, _dptr(out)), "lbfd_sg_forward")
+        return out
+
+    def gradient(self, x, t):
+        g = np.zeros(self.n, dtype=np.float32)
+        loss = C.c_double()
+        _check(load().lbfd_sg_gradient(self.h, _dptr(x), _dptr(t), x.shape[0], C.byref(loss),
+                                       g.ctypes.data_as(C.POINTER(C.c_float)), g.size), "lbfd_sg_gradient")
+        return loss.value, g
+
+    def train_step(self, x, t, want_loss=True):
+        loss = C.c_double()
+        _check(load().lbfd_sg_train_step(self.h, _dptr(x), _dptr(t), x.shape[0],
+                                         C.byref(loss) if want_loss else None), "lbfd_sg_train_step")
+        return loss.value if want_loss else None
+
+    def features(self, solver, feat):
+        _check(load().lbfd_sg_features(solver.h, self.h, _dptr(feat)), "lbfd_sg_features")
+        return feat
+
+    def snapshot(self, solver, snap):
+        _check(load().lbfd_sg_snapshot(solver.h, self.h, _dptr(snap)), "lbfd_sg_snapshot")
+        return snap
+
+    def tiles(self, solver, feat, snap, origins, x, t):
+        org = np.ascontiguousarray(np.asarray(origins, dtype=np.int32).reshape(-1))
+        B = org.size // 3
+        _check(load().lbfd_sg_tiles(solver.h, self.h, _dptr(feat), _dptr(snap),
+                                    org.ctypes.data_as(C.POINTER(C.c_int32)), B, _dptr(x), _dptr(t)), "lbfd_sg_tiles")
+        return x, t
+
+    def advance(self, solver, nblocks: int) -> dict:
+        rep = SgReport()
+        _check(load().lbfd_sg_advance(solver.h, self.h, int(nblocks), C.byref(rep)), "lbfd_sg_advance")
+        return dict(blocks=rep.blocks, accepted=rep.accepted, fallbacks=rep.fallbacks, max_drift=rep.max_drift,
+                    last_drift=rep.last_drift)

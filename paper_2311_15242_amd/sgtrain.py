@@ -1,0 +1,107 @@
+"""Snapshot tiles from the solver and training of the learned surrogate.
+
+Orchestration only: the features, the frozen-flow FD substeps that make the
+targets, the tile crops, the network and Adam all run in liblbfd.so's kernels.
+Tiles are torch device tensors (inputs as int16 tensors holding BF16 bit
+patterns, targets FP32).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import lbfd
+
+
+def feature_buffers(solver):
+    import torch
+
+    p = solver.p
+    nf = (p["nz"] + 8) * (p["ny"] + 8) * (p["nx"] + 8) * 16
+    feat = torch.empty(nf, dtype=torch.int16, device=solver.device)
+    snap = torch.empty(2 * solver.N, dtype=torch.float32, device=solver.device)
+    return feat, snap
+
+
+def snapshot_tiles(solver, sg, n_tiles: int, rng, bufs=None):
+    """n_tiles training tiles of the solver's current state: inputs from the
+    state now, targets from the state after k frozen-flow FD substeps (the
+    solver's psi and phi are left advanced by those substeps)."""
+    import torch
+
+    p = solver.p
+    T = sg.cfg["tile"]
+    feat, snap = bufs if bufs is not None else feature_buffers(solver)
+    sg.features(solver, feat)
+    sg.snapshot(solver, snap)
+    solver.fd_substeps(sg.cfg["k"])
+    hi = np.array([p["nx"] - T + 1, p["ny"] - T + 1, p["nz"] - T + 1])
+    org = rng.integers(0, hi, size=(n_tiles, 3)).astype(np.int32)
+    X = torch.empty((n_tiles, T + 8, T + 8, T + 8, 16), dtype=torch.int16, device=solver.device)
+    Y = torch.empty((n_tiles, T, T, T, 2), dtype=torch.float32, device=solver.device)
+    mb = sg.cfg["max_batch"]
+    for a in range(0, n_tiles, mb):
+        b = min(n_tiles, a + mb)
+        sg.tiles(solver, feat, snap, org[a:b], X[a:b], Y[a:b])
+    return X, Y
+
+
+def change_scales(solver, k: int, quantile: float = 0.999):
+    """Scales of the target channels from one probe: the given quantile of
+    |change| of psi and phi over k frozen-flow substeps (the probe's substeps
+    are applied to the solver)."""
+    psi0, phi0 = solver.field("psi"), solver.field("phi")
+    solver.fd_substeps(k)
+    dpsi = np.abs(solver.field("psi") - psi0)
+    dphi = np.abs(solver.field("phi") - phi0)
+    return float(max(np.quantile(dpsi, quantile), 1e-12)), float(max(np.quantile(dphi, quantile), 1e-12))
+
+
+def train(sg, X, Y, steps: int, batch: int, rng, log_every: int = 0):
+    """Adam steps on random minibatches of the tiles; returns the loss history
+    (one value per logged step, each read back from the device)."""
+    import torch
+
+    n = X.shape[0]
+    hist = []
+    for it in range(steps):
+        idx = torch.as_tensor(rng.choice(n, size=min(batch, n), replace=False), device=X.device)
+        xb = X.index_select(0, idx).contiguous()
+        yb = Y.index_select(0, idx).contiguous()
+        want = log_every > 0 and (it % log_every == 0 or it == steps - 1)
+        loss = sg.train_step(xb, yb, want_loss=want)
+        if want:
+            hist.append((it, loss))
+    return hist
+
+
+def tile_error(sg, X, Y):
+    """Relative L2 error of the network's tile outputs against the targets, and
+    that of predicting no change at all (the trivial predictor)."""
+    import torch
+
+    mb = sg.cfg["max_batch"]
+    T = sg.cfg["tile"]
+    num = den = 0.0
+    for a in range(0, X.shape[0], mb):
+        b = min(X.shape[0], a + mb)
+        out = torch.empty((b - a, T, T, T, 2), dtype=torch.float32, device=X.device)
+        sg.forward(X[a:b].contiguous(), out)
+        num += float(((out - Y[a:b]) ** 2).sum().item())
+        den += float((Y[a:b] ** 2).sum().item())
+    return float(np.sqrt(num / max(den, 1e-300))), 1.0
+
+
+def initial_params(seed: int = 0, out_scale: float = 0.1):
+    """He-normal weights, zero biases, a small last layer (parameter order of the C ABI)."""
+    rng = np.random.default_rng(seed)
+    layers = ((6, 32), (32, 32), (32, 32), (32, 2))
+    parts = []
+    for li, (ci, co) in enumerate(layers):
+        w = rng.standard_normal(27 * ci * co) * np.sqrt(2.0 / (27 * ci))
+        if li == len(layers) - 1:
+            w *= out_scale
+        parts += [w, np.zeros(co)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+__all__ = ["feature_buffers", "snapshot_tiles", "change_scales", "train", "tile_error", "initial_params", "lbfd"]

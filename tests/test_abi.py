@@ -14,8 +14,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared():
-    txt = open(os.path.join(ROOT, "include", "lbfd.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*|lbfd_\w+ \*)\s*(lbfd_\w+)\s*\(", txt, re.M)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in sorted(os.listdir(inc)):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(inc, fn)).read()
+            names |= set(re.findall(r"^\s*(?:int|int64_t|void|const char \*|lbfd_\w+ \*)\s*(lbfd_\w+)\s*\(",
+                                    txt, re.M))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")

@@ -145,6 +145,39 @@ def bubble_rise(nx=128, ny=128, nz=384, radius=16.0, Eo=10.0, Mo=0.1, Bi=1.0,
 
 
 # ----------------------------------------------------------------------------
+# Periodic box with several bubbles at seeded non-overlapping positions (the
+# snapshot source of the learned surrogate): D3Q19, the bubble column's
+# parameters (density and viscosity ratio 10, Mo at Eo = 1, Pe = 10, k = 1,
+# phi0 = 0.5, E0 = 0.5), Eo and Bi as given. Positions are drawn in order with
+# numpy's default_rng(seed) inside the box, rejecting any bubble closer than 1.5
+# diameters (periodic distance) to an earlier one.
+# ----------------------------------------------------------------------------
+def multi_bubble(n=256, count=8, diameter=24.0, Eo=10.0, Bi=1.0, seed=0, precision="fp32", **over):
+    radius = diameter / 2.0
+    rng = np.random.default_rng(seed)
+    centres = []
+    tries = 0
+    while len(centres) < count:
+        tries += 1
+        if tries > 100000:
+            raise ValueError("bubbles do not fit")
+        c = rng.uniform(radius + 2.0, n - radius - 2.0, 3)   # whole bubbles (the initial profile does not wrap)
+        ok = True
+        for d in centres:
+            dd = np.abs(c - np.asarray(d))
+            dd = np.minimum(dd, n - dd)
+            if float(np.sqrt((dd * dd).sum())) < 1.5 * diameter:
+                ok = False
+                break
+        if ok:
+            centres.append(tuple(float(v) for v in c))
+    p, q = bubble_rise(nx=n, ny=n, nz=n, radius=radius, Eo=Eo, Bi=Bi, precision=precision, **over)
+    p["bc"] = [PERIODIC, PERIODIC, PERIODIC]
+    q = dict(q, drops=[(x, y, z, radius) for x, y, z in centres])
+    return p, q
+
+
+# ----------------------------------------------------------------------------
 # Seeded batch of uneven 2-D bubble-rise instances (draw order W, H, Eo, Bi).
 # ----------------------------------------------------------------------------
 def batch_manifest(count=64, seed=0):
