@@ -20,6 +20,11 @@ The printed JSON line also carries:
                 droplet 128 x 128 FP64), same timing method
   batched       the parameter sweep of 64 uneven 2-D bubble columns as one
                 batch against the same instances run one after another
+  surrogate     the learned surrogate of 8 frozen-flow FD substeps on the
+                periodic multi-bubble box: training on the solver's own
+                snapshots, held-out error, one whole-grid application against
+                the 8 FD substeps it replaces (and its matrix-core rate), and
+                surrogate mode against plain stepping
 """
 from __future__ import annotations
 
@@ -29,6 +34,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -119,6 +126,137 @@ def timed_run(p, q, steps, warmup, profile, only=None):
         raise RuntimeError(f"solver status {ob['status']} in the timed region")
     s.close()
     return ms, prof, ob
+
+
+def conv_flops(d, h, w, B=1):
+    """Multiply-adds x 2 of the surrogate on B grids of d x h x w input nodes, counted
+    with the real channel counts (6 -> 32 -> 32 -> 32 -> 2)."""
+    chans = ((6, 32), (32, 32), (32, 32), (32, 2))
+    f = 0
+    for l, (ci, co) in enumerate(chans):
+        f += 2 * 27 * ci * co * B * (d - 2 * l - 2) * (h - 2 * l - 2) * (w - 2 * l - 2)
+    return float(f)
+
+
+def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, seed=0):
+    """The learned surrogate on the multi-bubble periodic box (D3Q19 n^3, 8 bubbles
+    of diameter 24, Eo 10, Bi 1, FP32 solver): snapshot tiles from the solver,
+    training on the GPU, the held-out error against the FD substeps it replaces,
+    the time of one whole-grid application against k = 8 FD substeps, and
+    surrogate mode against FD-substep mode (the same lagged coupling with the FD
+    update) and against plain stepping."""
+    import torch
+
+    import workloads as W
+    from paper_2311_15242_amd import lbfd, sgtrain
+
+    k = 8
+    say = lambda *a: print("[surrogate]", *a, file=sys.stderr, flush=True)
+    rng = np.random.default_rng(seed)
+    p, q = W.multi_bubble(n=n, count=8, diameter=24.0, Eo=10.0, Bi=1.0, seed=seed, precision="fp32")
+    N = n ** 3
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        ev0.record()
+        r = fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1), r
+
+    s = lbfd.Solver(p).init_fields(q)
+    s.step(100)
+    dps, dph = sgtrain.change_scales(s, k)
+    sg = lbfd.Surrogate(tile=32, max_batch=8, field=(n, n, n), k=k, lr=1e-3, phi_s=0.5, u_s=0.005,
+                        dpsi_s=dps, dphi_s=dph, drift_tol=1e-6)
+    sg.set_params(sgtrain.initial_params(seed))
+    bufs = sgtrain.feature_buffers(s)
+    Xs, Ys = [], []
+    t0 = time.time()
+    for i in range(snapshots):
+        s.step(25)
+        X, Y = sgtrain.snapshot_tiles(s, sg, tiles_per_snap, rng, bufs)
+        Xs.append(X)
+        Ys.append(Y)
+    X, Y = torch.cat(Xs), torch.cat(Ys)
+    del Xs, Ys
+    s.step(25)
+    Xh, Yh = sgtrain.snapshot_tiles(s, sg, 32, rng, bufs)
+    torch.cuda.synchronize()
+    t_data = time.time() - t0
+    say(f"{X.shape[0]} training tiles in {t_data:.1f} s")
+    e0, _ = sgtrain.tile_error(sg, Xh, Yh)
+    ms_train, hist = timed(lambda: sgtrain.train(sg, X, Y, train_steps, 8, rng, log_every=max(1, train_steps // 4)))
+    e1, _ = sgtrain.tile_error(sg, Xh, Yh)
+    say(f"trained {train_steps} steps in {ms_train / 1e3:.1f} s: held-out error {e0:.3f} -> {e1:.3f}")
+    del X, Y
+    # one whole-grid application (features + network) against the k FD substeps it replaces
+    feat, _ = bufs
+    out = torch.empty((n, n, n, 2), dtype=torch.float32, device="cuda")
+    x = feat.view(1, n + 8, n + 8, n + 8, 16)
+    sg.features(s, feat)
+    sg.forward(x, out)
+    reps = 5
+    ms_inf = timed(lambda: [(sg.features(s, feat), sg.forward(x, out)) for _ in range(reps)])[0] / reps
+    ms_net = timed(lambda: sg.forward(x, out))[0]
+    ms_fd = timed(lambda: s.fd_substeps(k))[0]
+    fd_drift = s.observables()["drift_pre"]   # pre-rescale drift of the last FD substep
+    s.close()
+    del s
+    # surrogate mode and its references from one warm state (deterministic runs)
+    def warm():
+        r = lbfd.Solver(p).init_fields(q)
+        r.step(200)
+        return r
+
+    def fd_mode(r):
+        for _ in range(blocks):
+            r.fd_substeps(k)
+            r.set_fd(False).step(k).set_fd(True)
+
+    a = warm()
+    ms_strict, rep_strict = timed(lambda: sg.advance(a, blocks))
+    a.close()
+    a = warm()
+    sg.set_drift_tol(1e-3)
+    ms_open, rep_open = timed(lambda: sg.advance(a, blocks))
+    psi_a = a.field("psi")
+    a.close()
+    b = warm()
+    psi0 = b.field("psi")
+    ms_fdm, _ = timed(lambda: fd_mode(b))
+    psi_b = b.field("psi")
+    b.close()
+    c = warm()
+    ms_plain, _ = timed(lambda: c.step(blocks * k))
+    psi_c = c.field("psi")
+    c.close()
+    nrm = lambda v: float(np.sqrt((v * v).sum()))
+    say(f"mode: strict {rep_strict}, open {rep_open}")
+    flops = conv_flops(n + 8, n + 8, n + 8)
+    steps = blocks * k
+    mlups = lambda ms: round(N * steps / (ms / 1e3) / 1e6, 1)
+    return dict(
+        workload=f"multi_bubble {n}^3 periodic D3Q19, 8 bubbles D=24, Eo=10, Bi=1, FP32 solver; k={k} substeps",
+        tiles_train=snapshots * tiles_per_snap, tiles_heldout=int(Xh.shape[0]), data_s=round(t_data, 2),
+        train_steps=train_steps, batch=8, train_ms=round(ms_train, 1),
+        train_tiles_per_s=round(train_steps * 8 / (ms_train / 1e3), 1),
+        train_tflops=round(3.0 * conv_flops(40, 40, 40, 8) * train_steps / (ms_train / 1e3) / 1e12, 2),
+        loss_first=hist[0][1], loss_last=hist[-1][1],
+        heldout_rel_error_untrained=round(e0, 4), heldout_rel_error=round(e1, 4),
+        inference_ms=round(ms_inf, 3), network_ms=round(ms_net, 3), fd_substeps_ms=round(ms_fd, 3),
+        inference_speedup=round(ms_fd / ms_inf, 3), fd_substep_drift=fd_drift,
+        network_mfma=dict(bound="mfma", achieved=round(flops / (ms_net / 1e3) / 1e12, 2), peak=2500.0,
+                          unit="TFLOP/s", frac=round(flops / (ms_net / 1e3) / 1e12 / 2500.0, 4)),
+        mode_steps=steps,
+        mode_strict=dict(drift_tol=1e-6, accepted=rep_strict["accepted"], fallbacks=rep_strict["fallbacks"],
+                         last_drift=rep_strict["last_drift"], mlups=mlups(ms_strict)),
+        mode_open=dict(drift_tol=1e-3, accepted=rep_open["accepted"], fallbacks=rep_open["fallbacks"],
+                       max_drift=rep_open["max_drift"], mlups=mlups(ms_open),
+                       psi_rel_error_vs_fd_mode=round(nrm(psi_a - psi_b) / max(nrm(psi_b - psi0), 1e-300), 4)),
+        fd_mode_mlups=mlups(ms_fdm), plain_mlups=mlups(ms_plain),
+        fd_mode_psi_rel_error_vs_plain=round(nrm(psi_b - psi_c) / max(nrm(psi_c - psi0), 1e-300), 4))
 
 
 def cpu_baseline(p, q, budget_s):
@@ -343,6 +481,12 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance parameter sweep")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate measurement")
+    ap.add_argument("--sg-size", type=int, default=256)
+    ap.add_argument("--sg-snapshots", type=int, default=16)
+    ap.add_argument("--sg-tiles", type=int, default=64)
+    ap.add_argument("--sg-train-steps", type=int, default=3000)
+    ap.add_argument("--sg-blocks", type=int, default=4)
     ap.add_argument("--omega", type=float, default=None, help="SOR relaxation factor (default: the workload's)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (scales rocprofv3 byte counters)")
@@ -439,6 +583,9 @@ def main():
         out["secondary"] = sec
     if not args.no_batch:
         out["batched"] = batch_bench(args.batch_steps, args.warmup, args.sor_sweeps)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_bench(args.sg_size, args.sg_snapshots, args.sg_tiles, args.sg_train_steps,
+                                           args.sg_blocks)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, q, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -38,7 +38,7 @@ typedef struct lbfd_sg lbfd_sg;
 
 typedef struct {
     int32_t tile;       /* output edge of a training tile (its input edge is tile + 8), 1..64 */
-    int32_t max_batch;  /* most tiles per lbfd_sg_forward_tiles / train call, >= 1 */
+    int32_t max_batch;  /* most tiles per lbfd_sg_gradient / lbfd_sg_train_step / lbfd_sg_tiles call, >= 1 */
     int32_t field[3];   /* largest solver grid (nx, ny, nz) for the whole-field calls; 0s: none */
     int32_t k;          /* FD substeps one application replaces (>= 1) */
     double lr, beta1, beta2, adam_eps;             /* Adam */
@@ -99,8 +99,7 @@ int lbfd_sg_snapshot(lbfd_handle *h, lbfd_sg *s, float *d_snap);
  * wrote it) and targets (psi, phi of the solver now minus d_snap, scaled by
  * dpsi_s, dphi_s) over the tile's output nodes. Tile b has its output corner
  * at node (org[3b], org[3b+1], org[3b+2]) = (x, y, z) with x + tile <= nx,
- * y + tile <= ny, z + tile <= nz (2-D: z = 0 and tile = 1 in z is not
- * supported; use a 3-D grid). */
+ * y + tile <= ny, z + tile <= nz (so training tiles come from 3-D grids). */
 int lbfd_sg_tiles(lbfd_handle *h, lbfd_sg *s, const uint16_t *d_feat, const float *d_snap,
                   const int32_t *host_org, int32_t B, uint16_t *d_in, float *d_target);
 
@@ -113,6 +112,9 @@ int lbfd_sg_tiles(lbfd_handle *h, lbfd_sg *s, const uint16_t *d_feat, const floa
  * rep (if not NULL) accumulates counts over the call. Synchronises once per
  * block (the drift check is read on the host). */
 int lbfd_sg_advance(lbfd_handle *h, lbfd_sg *s, int64_t nblocks, lbfd_sg_report *rep);
+
+/* Change the fallback threshold of lbfd_sg_advance (tol >= 0). */
+int lbfd_sg_set_drift_tol(lbfd_sg *s, double tol);
 
 /* Release the surrogate (not the workspace or stream). */
 void lbfd_sg_destroy(lbfd_sg *s);

@@ -2733,7 +2733,7 @@ static int sg_forward_on(lbfd_sg *s, hipStream_t st, const uint16_t *in, int B, 
     for (int l = 0; l < sg::NL; ++l) {
         const int Di = d - 2 * l, Hi = h - 2 * l, Wi = w - 2 * l;
         const long long M = layer_nodes(l + 1, B, d, h, w);
-        const dim3 grid(blocks_for(M, 256));
+        const dim3 grid(blocks_for(M, sg::FWD_NODES));
         if (l == 0)
             hipLaunchKernelGGL((sg::k_conv_fwd<16, true, false>), grid, dim3(256), 0, st, (const uint16_t *)x,
                                s->net.wb[0], s->net.bias[0], (void *)s->act[0], Di, Hi, Wi, M);
@@ -2883,6 +2883,13 @@ int lbfd_sg_tiles(lbfd_handle *h, lbfd_sg *s, const uint16_t *d_feat, const floa
     return dispatch_for(h->p.lattice, h->p.precision)
         .sg_tiles(h, d_feat, d_snap, s->org, B, T, d_in, d_target, (float)(1.0 / s->p.dpsi_s),
                   (float)(1.0 / s->p.dphi_s));
+}
+
+int lbfd_sg_set_drift_tol(lbfd_sg *s, double tol)
+{
+    if (!s || !(tol >= 0.0)) return LBFD_EINVAL;
+    s->p.drift_tol = tol;
+    return LBFD_OK;
 }
 
 int lbfd_sg_advance(lbfd_handle *h, lbfd_sg *s, int64_t nblocks, lbfd_sg_report *rep)

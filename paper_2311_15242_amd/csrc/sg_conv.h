@@ -54,14 +54,24 @@ __device__ __forceinline__ bf16x8 frag_zero() { return __builtin_bit_cast(bf16x8
 // column is the lane index mod 32).
 __device__ __forceinline__ int acc_row(int r, int kg) { return 8 * (r >> 2) + 4 * kg + (r & 3); }
 
+// Output tiles of 32 nodes per wavefront in the forward layer.
+#ifndef LBFD_SG_FWD_NT
+#define LBFD_SG_FWD_NT 4
+#endif
+constexpr int FWD_NT = LBFD_SG_FWD_NT;
+constexpr int FWD_NODES = 4 * 32 * FWD_NT;   // output nodes per workgroup
+
 // Forward layer: out[m][o] = act(b[o] + sum_{tap,i} in[m + tap][i] w[tap][o][i]) over the
 // M = B (Di-2)(Hi-2)(Wi-2) output nodes. wb: BF16 [27][32][CIN] (input channel fastest).
 // out: BF16 [M][32], or with OUTF32 FP32 [M][2] (the first two channels, no activation).
+// Each wavefront computes FWD_NT tiles of 32 nodes x 32 channels; every weight
+// fragment read from LDS feeds FWD_NT matrix instructions.
 template <int CIN, bool RELU, bool OUTF32>
 __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ in, const u16 *__restrict__ wb,
                                                  const float *__restrict__ bias, void *__restrict__ out, int Di,
                                                  int Hi, int Wi, long long M)
 {
+    constexpr int NT = FWD_NT;
     constexpr int LDW = CIN + 8;   // padded LDS row
     __shared__ __attribute__((aligned(16))) u16 sw[27 * CO * LDW];
     for (int i = threadIdx.x; i < 27 * CO * (CIN / 8); i += 256) {
@@ -72,11 +82,11 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ in, co
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int mr = lane & 31, kg = lane >> 5;
     const int Do = Di - 2, Ho = Hi - 2, Wo = Wi - 2;
-    const long long m0 = ((long long)blockIdx.x * 4 + wave) * 64;
-    long long base[2];
-    bool ok[2];
+    const long long m0 = ((long long)blockIdx.x * 4 + wave) * (32 * NT);
+    const u16 *src[NT];
+    bool ok[NT];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NT; ++t) {
         const long long m = m0 + 32 * t + mr;
         ok[t] = m < M;
         long long r = ok[t] ? m : 0;
@@ -86,11 +96,11 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ in, co
         r /= Ho;
         const int z = (int)(r % Do);
         const long long b = r / Do;
-        base[t] = (((b * Di + z) * Hi + y) * (long long)Wi + x) * CIN + kg * 8;
+        src[t] = in + (((b * Di + z) * Hi + y) * (long long)Wi + x) * CIN + kg * 8;
     }
-    f32x16 acc[2];
+    f32x16 acc[NT];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
     for (int a = 0; a < 3; ++a)
@@ -102,16 +112,16 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ in, co
 #pragma unroll
                 for (int c = 0; c < CIN / 16; ++c) {
                     const bf16x8 B = frag(&sw[(tap * CO + mr) * LDW + c * 16 + kg * 8]);
+                    bf16x8 A[NT];
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        const bf16x8 A = ok[t] ? frag(in + base[t] + toff + c * 16) : frag_zero();
-                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[t], 0, 0, 0);
-                    }
+                    for (int t = 0; t < NT; ++t) A[t] = ok[t] ? frag(src[t] + toff + c * 16) : frag_zero();
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[t], B, acc[t], 0, 0, 0);
                 }
             }
     const float bv = bias[mr];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const long long m = m0 + 32 * t + acc_row(r, kg);

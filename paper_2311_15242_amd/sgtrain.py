@@ -22,20 +22,37 @@ def feature_buffers(solver):
     return feat, snap
 
 
-def snapshot_tiles(solver, sg, n_tiles: int, rng, bufs=None):
+def tile_origins(solver, T: int, n_tiles: int, rng, interface_share: float = 0.75, g_min: float = 0.05):
+    """Output corners of n_tiles tiles: a share of them centred on random nodes of
+    the interface (|grad rhoN| >= g_min, where psi and phi change), the rest
+    uniform over the grid. On a grid with a few small bubbles a uniform draw
+    would give mostly tiles where nothing happens."""
+    p = solver.p
+    hi = np.array([p["nx"] - T + 1, p["ny"] - T + 1, p["nz"] - T + 1])
+    org = rng.integers(0, hi, size=(n_tiles, 3))
+    n_if = int(round(interface_share * n_tiles))
+    if n_if > 0:
+        G = solver.field("G")
+        z, y, x = np.nonzero(G >= g_min)
+        if x.size:
+            pick = rng.integers(0, x.size, size=n_if)
+            c = np.stack([x[pick], y[pick], z[pick]], axis=1) - T // 2
+            org[:n_if] = np.clip(c, 0, hi - 1)
+    return org.astype(np.int32)
+
+
+def snapshot_tiles(solver, sg, n_tiles: int, rng, bufs=None, interface_share: float = 0.75):
     """n_tiles training tiles of the solver's current state: inputs from the
     state now, targets from the state after k frozen-flow FD substeps (the
     solver's psi and phi are left advanced by those substeps)."""
     import torch
 
-    p = solver.p
     T = sg.cfg["tile"]
     feat, snap = bufs if bufs is not None else feature_buffers(solver)
+    org = tile_origins(solver, T, n_tiles, rng, interface_share)
     sg.features(solver, feat)
     sg.snapshot(solver, snap)
     solver.fd_substeps(sg.cfg["k"])
-    hi = np.array([p["nx"] - T + 1, p["ny"] - T + 1, p["nz"] - T + 1])
-    org = rng.integers(0, hi, size=(n_tiles, 3)).astype(np.int32)
     X = torch.empty((n_tiles, T + 8, T + 8, T + 8, 16), dtype=torch.int16, device=solver.device)
     Y = torch.empty((n_tiles, T, T, T, 2), dtype=torch.float32, device=solver.device)
     mb = sg.cfg["max_batch"]
@@ -104,4 +121,4 @@ def initial_params(seed: int = 0, out_scale: float = 0.1):
     return np.concatenate(parts).astype(np.float32)
 
 
-__all__ = ["feature_buffers", "snapshot_tiles", "change_scales", "train", "tile_error", "initial_params", "lbfd"]
+__all__ = ["feature_buffers", "tile_origins", "snapshot_tiles", "change_scales", "train", "tile_error", "initial_params", "lbfd"]
