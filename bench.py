@@ -15,6 +15,9 @@ The printed JSON line also carries:
                 region) against 8 TB/s; traffic = measured HBM bytes per launch
                 from the rocprofv3 counter summary under profiles/ (null if the
                 kernel sources changed since it was taken)
+  step_bandwidth the algorithmic bytes of one whole step (every kernel, SOR
+                half-sweeps counted for the sweeps that ran) x MLUPS, against
+                8 TB/s
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
   secondary     the 2-D workloads (shear 512 x 256 in FP64 / FP32 / FP16-dev,
                 droplet 128 x 128 FP64), same timing method
@@ -558,6 +561,15 @@ def main():
                          gbs=round(algorithmic_bytes(k, p) * N * v[1] / (v[0] / 1e3) / 1e9, 1) if v[0] > 0 else 0.0)
                  for k, v in prof.items() if v[1] > 0}
 
+    # whole-step bandwidth: the algorithmic bytes of every kernel of one step (SOR
+    # half-sweeps counted for the sweeps that ran) x lattice updates per second
+    sweeps_run = max(ob["sor_sweeps"]) + 1 if p["fd_enable"] else 0
+    step_bytes = sum(algorithmic_bytes(k, p) for k in ("collide", "macro", "geom", "force")) + \
+        (algorithmic_bytes("fd", p) + algorithmic_bytes("total", p) + 2 * sweeps_run * algorithmic_bytes("sor", p)
+         if p["fd_enable"] else 0.0)
+    step_gbs = step_bytes * value * 1e6 / 1e9
+    step_bw = dict(bytes_per_lup=round(step_bytes, 1), sor_half_sweeps_counted=2 * sweeps_run,
+                   achieved=round(step_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(step_gbs / HBM_PEAK_GBS, 4))
     out = dict(metric="MLUPS (LBM+FD step)", value=round(value, 2), unit="MLUPS", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_plain / args.steps, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32" if p["precision"] != "fp64" else "f64",
@@ -566,7 +578,7 @@ def main():
                            grid=[p["nx"], p["ny"], p["nz"]], storage=p["precision"],
                            sor_sweeps_launched=p["sor_max_sweeps"], sor_sweeps_used=ob["sor_sweeps"],
                            parallelism="single GPU"),
-               roofline=roof, kernels=breakdown,
+               roofline=roof, step_bandwidth=step_bw, kernels=breakdown,
                ms_per_step_profiled=round(ms_prof / args.steps, 4))
 
     if not args.no_secondary:

@@ -193,6 +193,14 @@ int lbfd_profile(lbfd_handle *h, int32_t enable);
 int lbfd_profile_read(lbfd_handle *h, int32_t max_kernels, const char **names, double *ms, int64_t *launches,
                       int32_t *n_kernels);
 
+/* Overwrite one FD field from count = N FP64 host values in node order:
+ * LBFD_FIELD_PSI or LBFD_FIELD_PHI (physical values; the force is recomputed
+ * from the new psi) or LBFD_FIELD_SPREV / LBFD_FIELD_BPREV (the AB2 source
+ * histories of eq 24). The rescaling target M0 is kept. Other fields:
+ * LBFD_EUNSUPPORTED (use lbfd_set_state). Synchronous. Errors: EINVAL (count
+ * or null pointer), EHIP. */
+int lbfd_write_field(lbfd_handle *h, int32_t field, const double *host, size_t count);
+
 /* Advance psi and phi by k >= 0 FD updates (Sec 2.2, eqs 20-28) with the flow
  * frozen at the current state: rhoN, G and u of the current populations, the
  * weights of the new time level equal to those of the current one. The LB

@@ -1068,6 +1068,22 @@ template <class R> __global__ void kb_sor_done(const KP<R> *tab, int nsw)
 template <class R> __global__ void k_sor_clear(KP<R> k, int nsw) { sor_slots_clear(k.fld.sorres, nsw); }
 
 
+// One FD field from FP64 values: psi and phi given as physical values (stored
+// divided by the current scale factor), the AB2 histories as they are.
+template <class R> __global__ __launch_bounds__(256) void k_import_fd(KP<R> k, int field, const double *src)
+{
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (n >= k.N) return;
+    const uint32_t i = (uint32_t)n;
+    const double sc = k.fld.sc->scale;
+    switch (field) {
+    case LBFD_FIELD_PSI: st(k.fld.psi[k.pc], i, (R)(src[n] / sc)); break;
+    case LBFD_FIELD_PHI: st(k.fld.phi[k.pc], i, (R)(src[n] / sc)); break;
+    case LBFD_FIELD_SPREV: st(k.fld.Sp, i, (R)src[n]); break;
+    default: st(k.fld.Bp, i, (R)src[n]); break;
+    }
+}
+
 // ============================================================== surrogate coupling
 
 // Input channels of the surrogate (psi/psi_inf, phi/phi_s, rhoN, u/u_s, zeros up to
@@ -2174,6 +2190,25 @@ template <int LAT, class P> struct Impl {
         return L + B > 0 ? (L - B) / (L + B) : 0.0;
     }
 
+    // psi, phi (the force is recomputed from the new psi) or the AB2 histories.
+    static int write_field(lbfd_handle *h, int field, const double *host, size_t count)
+    {
+        if (field != LBFD_FIELD_PSI && field != LBFD_FIELD_PHI && field != LBFD_FIELD_SPREV &&
+            field != LBFD_FIELD_BPREV)
+            return LBFD_EUNSUPPORTED;
+        if (!host || count != (size_t)h->N) return LBFD_EINVAL;
+        double *d = nullptr;
+        if (hipMalloc(&d, count * sizeof(double)) != hipSuccess) return LBFD_EHIP;
+        sync_levels(h);
+        KP<R> &k = kp(h);
+        hipMemcpyAsync(d, host, count * sizeof(double), hipMemcpyHostToDevice, h->stream);
+        LAUNCH(KC_OTHER, (k_import_fd<R>), dim3((unsigned)((h->N + 255) / 256)), dim3(256), k, field, d);
+        if (field == LBFD_FIELD_PSI) LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
+        hipError_t e = hipStreamSynchronize(h->stream);
+        hipFree(d);
+        return e == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
     static int read_field(lbfd_handle *h, int field, double *host, size_t count)
     {
         int comps = field == LBFD_FIELD_F ? h->Q : (field == LBFD_FIELD_U || field == LBFD_FIELD_FORCE) ? h->D : 1;
@@ -2202,6 +2237,7 @@ struct Dispatch {
     int (*step)(lbfd_handle *, long long);
     int (*observables)(lbfd_handle *, lbfd_obs *);
     int (*read_field)(lbfd_handle *, int, double *, size_t);
+    int (*write_field)(lbfd_handle *, int, const double *, size_t);
     int (*batch_step)(lbfd_batch *, long long);
     int (*batch_table)(lbfd_batch *);
     size_t kp_bytes;
@@ -2219,7 +2255,7 @@ template <int LAT, class P> Dispatch make_dispatch()
 {
     using I = Impl<LAT, P>;
     return Dispatch{&I::init,        &I::set_state,   &I::step,        &I::observables, &I::read_field,
-                    &I::batch_step,  &I::batch_table, sizeof(KP<typename P::R>),
+                    &I::write_field, &I::batch_step,  &I::batch_table, sizeof(KP<typename P::R>),
                     &I::fd_substeps, &I::sg_features, &I::sg_snapshot, &I::sg_tiles,      &I::sg_candidate,
                     &I::sg_accept,   &I::read_scalars};
 }
@@ -2542,6 +2578,12 @@ int lbfd_batch_step(lbfd_batch *b, int64_t n)
 }
 
 // ------------------------------------------------------------------ frozen-flow substeps
+
+int lbfd_write_field(lbfd_handle *h, int32_t field, const double *host, size_t count)
+{
+    if (!h) return LBFD_EINVAL;
+    return dispatch_for(h->p.lattice, h->p.precision).write_field(h, field, host, count);
+}
 
 int lbfd_fd_substeps(lbfd_handle *h, int64_t k)
 {

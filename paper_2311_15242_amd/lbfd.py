@@ -20,7 +20,7 @@ EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_init_fields", "lbfd_set
             "lbfd_observables", "lbfd_read_field", "lbfd_profile", "lbfd_profile_read", "lbfd_destroy",
             "lbfd_strerror", "lbfd_batch_workspace_bytes", "lbfd_batch_create", "lbfd_batch_instance",
             "lbfd_batch_step", "lbfd_batch_destroy", "lbfd_set_graphs", "lbfd_batch_set_graphs",
-            "lbfd_fd_substeps", "lbfd_set_fd",
+            "lbfd_fd_substeps", "lbfd_set_fd", "lbfd_write_field",
             "lbfd_sg_n_params", "lbfd_sg_workspace_bytes", "lbfd_sg_create", "lbfd_sg_set_params",
             "lbfd_sg_get_params", "lbfd_sg_forward", "lbfd_sg_gradient", "lbfd_sg_train_step", "lbfd_sg_features",
             "lbfd_sg_snapshot", "lbfd_sg_tiles", "lbfd_sg_advance", "lbfd_sg_destroy", "lbfd_sg_set_drift_tol"]
@@ -123,6 +123,7 @@ def load(build_if_missing: bool = False):
     L.lbfd_batch_set_graphs.argtypes = [vp, C.c_int32]
     L.lbfd_fd_substeps.argtypes = [vp, C.c_int64]
     L.lbfd_set_fd.argtypes = [vp, C.c_int32]
+    L.lbfd_write_field.argtypes = [vp, C.c_int32, dp, C.c_size_t]
     i32, i64, szp = C.c_int32, C.c_int64, P(C.c_size_t)
     L.lbfd_sg_n_params.restype = i64
     L.lbfd_sg_n_params.argtypes = []
@@ -223,6 +224,13 @@ class _Instance:
         _check(load().lbfd_set_state(self.h, ptr(f, self.Q * N), ptr(rhoR, N), ptr(rhoB, N), ptr(psi, N),
                                      ptr(phi, N), ptr(Sprev, N), ptr(Bprev, N), int(step), float(M0)),
                "lbfd_set_state")
+        return self
+
+    def write_field(self, name: str, values):
+        """Overwrite psi, phi (physical values) or Sprev / Bprev from FP64 host data."""
+        a = np.ascontiguousarray(values, dtype=np.float64).reshape(-1)
+        _check(load().lbfd_write_field(self.h, FIELDS[name], a.ctypes.data_as(C.POINTER(C.c_double)), a.size),
+               f"lbfd_write_field({name})")
         return self
 
     def set_fd(self, enable: bool):

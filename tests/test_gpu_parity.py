@@ -302,3 +302,40 @@ def test_nonfinite_is_reported(lbfd):
     s.step(1)
     ob = s.observables(check=False)
     assert ob["status"] == lbfd.LBFD_ENONFINITE
+
+
+def test_write_field_round_trip_and_parity(lbfd):
+    """lbfd_write_field: psi and phi written as physical values read back as
+    written; a run from the written state follows the oracle given the same
+    fields; populations are refused."""
+    say("[write_field]")
+    p, q = CASES_2D["bubble2d48x80"]("fp64")
+    s = lbfd.Solver(p).init_fields(q).step(3)
+    o = oracle.Oracle(dict(p, precision="fp64")).init(q).step(3)
+    rng = np.random.default_rng(21)
+    psi = np.clip(s.field("psi") + 0.01 * rng.random(s.shape), 0.0, 0.9)
+    phi = s.field("phi") * (1.0 + 0.01 * rng.random(s.shape))
+    s.write_field("psi", psi).write_field("phi", phi)
+    assert np.abs(s.field("psi") - psi).max() <= 1e-15 and np.abs(s.field("phi") - phi).max() <= 1e-15
+    o.set_field("psi", psi)
+    o.set_field("phi", phi)
+    s.step(10)
+    o.step(10)
+    errs = state_errors(s, o)
+    say(errs)
+    assert max(errs.values()) < 1e-10, errs
+    with pytest.raises(lbfd.LbfdError) as e:
+        s.write_field("f", np.zeros(9 * s.N))
+    assert e.value.status == -7
+
+
+def test_nonfinite_written_into_psi_is_reported(lbfd):
+    """A NaN written into psi through lbfd_write_field reaches the total of the
+    next step, which sets LBFD_ENONFINITE."""
+    say("[ENONFINITE via write_field]")
+    p, q = W.droplet_adsorption(n=32, radius=8.0)
+    s = lbfd.Solver(p).init_fields(q).step(2)
+    psi = s.field("psi")
+    psi[0, 16, 16] = np.nan
+    s.write_field("psi", psi).step(1)
+    assert s.observables(check=False)["status"] == lbfd.LBFD_ENONFINITE
