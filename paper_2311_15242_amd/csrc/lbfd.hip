@@ -2606,6 +2606,7 @@ struct lbfd_sg {
     int *org;                // tile origins [3 max_batch]
     long long cap_act, cap_out, cap_feat;
     long long t;             // Adam steps taken
+    bool brick = true;       // brick kernels on wide grids
 };
 
 static long long cube(long long e) { return e * e * e; }
@@ -2775,6 +2776,23 @@ static int sg_forward_on(lbfd_sg *s, hipStream_t st, const uint16_t *in, int B, 
     for (int l = 0; l < sg::NL; ++l) {
         const int Di = d - 2 * l, Hi = h - 2 * l, Wi = w - 2 * l;
         const long long M = layer_nodes(l + 1, B, d, h, w);
+        if (Wi - 2 >= 2 * sg::BRX && s->brick) {
+            // wide grids: output bricks with their input staged in LDS
+            const int nbx = (Wi - 2 + sg::BRX - 1) / sg::BRX, nby = (Hi - 2 + sg::BRY - 1) / sg::BRY,
+                      nbz = (Di - 2 + sg::BRZ - 1) / sg::BRZ;
+            const dim3 grid((unsigned)((long long)nbx * nby * nbz * B));
+            if (l == 0)
+                hipLaunchKernelGGL((sg::k_conv_fwd_brick<16, true, false>), grid, dim3(256), 0, st, (const uint16_t *)x,
+                                   s->net.wb[0], s->net.bias[0], (void *)s->act[0], Di, Hi, Wi, nbx, nby, nbz);
+            else if (l < 3)
+                hipLaunchKernelGGL((sg::k_conv_fwd_brick<32, true, false>), grid, dim3(256), 0, st, (const uint16_t *)x,
+                                   s->net.wb[l], s->net.bias[l], (void *)s->act[l], Di, Hi, Wi, nbx, nby, nbz);
+            else
+                hipLaunchKernelGGL((sg::k_conv_fwd_brick<32, false, true>), grid, dim3(256), 0, st, (const uint16_t *)x,
+                                   s->net.wb[3], s->net.bias[3], (void *)out, Di, Hi, Wi, nbx, nby, nbz);
+            if (l < 3) x = s->act[l];
+            continue;
+        }
         const dim3 grid(blocks_for(M, sg::FWD_NODES));
         if (l == 0)
             hipLaunchKernelGGL((sg::k_conv_fwd<16, true, false>), grid, dim3(256), 0, st, (const uint16_t *)x,

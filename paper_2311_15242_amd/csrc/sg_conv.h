@@ -136,6 +136,102 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ in, co
         }
 }
 
+// The same layer on grids wide enough for bricks: a workgroup stages the input
+// nodes of a 32 x 4 x BRZ output brick (34 x 6 x (BRZ + 2) nodes, zeros outside
+// the grid) in LDS once, and its wavefronts read every input fragment of the 27
+// taps from there; each wavefront owns BRZ rows of 32 nodes, so each weight
+// fragment feeds BRZ matrix instructions. Weight fragments come from LDS
+// (BR_WLDS) or from global memory (L2 resident). Same summation order as
+// k_conv_fwd.
+#ifndef LBFD_SG_BRZ
+#define LBFD_SG_BRZ 2
+#endif
+#ifndef LBFD_SG_BR_WLDS
+#define LBFD_SG_BR_WLDS 0
+#endif
+constexpr int BRX = 32, BRY = 4, BRZ = LBFD_SG_BRZ;
+template <int CIN, bool RELU, bool OUTF32>
+__global__ __launch_bounds__(256) void k_conv_fwd_brick(const u16 *__restrict__ in, const u16 *__restrict__ wb,
+                                                       const float *__restrict__ bias, void *__restrict__ out,
+                                                       int Di, int Hi, int Wi, int nbx, int nby, int nbz)
+{
+    constexpr int NT = BRZ;       // rows per wavefront (4 wavefronts x BRZ rows = BRY x BRZ)
+    constexpr int CP = CIN + 8;   // padded node stride in LDS
+    constexpr int EX = BRX + 2, EY = BRY + 2, EZ = BRZ + 2;
+    constexpr bool WLDS = LBFD_SG_BR_WLDS != 0;
+    constexpr int LDW = CIN + 8;
+    __shared__ __attribute__((aligned(16))) u16 sx[EZ * EY * EX * CP];
+    __shared__ __attribute__((aligned(16))) u16 sw[WLDS ? 27 * CO * LDW : 8];
+    const int Do = Di - 2, Ho = Hi - 2, Wo = Wi - 2;
+    int bid = blockIdx.x;
+    const int bxi = bid % nbx;
+    bid /= nbx;
+    const int byi = bid % nby;
+    bid /= nby;
+    const int bzi = bid % nbz;
+    const long long b = bid / nbz;
+    const int x0 = bxi * BRX, y0 = byi * BRY, z0 = bzi * BRZ;
+    for (int i = threadIdx.x; i < EZ * EY * EX * (CIN / 8); i += 256) {
+        const int piece = i % (CIN / 8), node = i / (CIN / 8);
+        const int ex = node % EX, ey = (node / EX) % EY, ez = node / (EX * EY);
+        const int gx = x0 + ex, gy = y0 + ey, gz = z0 + ez;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (gx < Wi && gy < Hi && gz < Di)
+            v = *(const u32x4 *)&in[(((b * Di + gz) * Hi + gy) * (long long)Wi + gx) * CIN + piece * 8];
+        *(u32x4 *)&sx[node * CP + piece * 8] = v;
+    }
+    if constexpr (WLDS)
+        for (int i = threadIdx.x; i < 27 * CO * (CIN / 8); i += 256) {
+            const int row = i / (CIN / 8), piece = i % (CIN / 8);
+            *(u32x4 *)&sw[row * LDW + piece * 8] = *(const u32x4 *)&wb[row * CIN + piece * 8];
+        }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int mr = lane & 31, kg = lane >> 5;
+    f32x16 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
+    for (int a = 0; a < 3; ++a)
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int tap = (a * 3 + p) * 3 + q;
+#pragma unroll
+                for (int c = 0; c < CIN / 16; ++c) {
+                    const bf16x8 B = WLDS ? frag(&sw[(tap * CO + mr) * LDW + c * 16 + kg * 8])
+                                          : frag(wb + (tap * CO + mr) * CIN + c * 16 + kg * 8);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        // wavefront w owns y row w of the brick, at every z of the brick
+                        const int yr = wave, zr = t;
+                        const bf16x8 A = frag(&sx[(((zr + a) * EY + (yr + p)) * EX + (mr + q)) * CP + c * 16 + kg * 8]);
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[t], 0, 0, 0);
+                    }
+                }
+            }
+    const float bv = bias[mr];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int y = y0 + wave, z = z0 + t;
+        if (y >= Ho || z >= Do) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int x = x0 + acc_row(r, kg);
+            if (x >= Wo) continue;
+            const long long m = ((b * Do + z) * Ho + y) * (long long)Wo + x;
+            float v = acc[t][r] + bv;
+            if constexpr (OUTF32) {
+                if (mr < 2) ((float *)out)[m * 2 + mr] = v;
+            } else {
+                if (RELU) v = fmaxf(v, 0.0f);
+                ((u16 *)out)[m * CO + mr] = f2bf(v);
+            }
+        }
+    }
+}
+
 // Input gradient of a layer with 32 input channels, with the ReLU of the layer below
 // applied: dx[v][i] = [x[v][i] > 0] sum_{tap,o} dy[v - tap][o] w[tap][i][o], over the
 // Mi = B Di Hi Wi input nodes. wt: BF16 [27][32 (i)][32 (o)] (output channel fastest).

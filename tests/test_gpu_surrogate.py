@@ -231,3 +231,21 @@ def test_advance_accepts_and_conserves(lbfd):
     ob = s.observables()
     assert ob["status"] == 0 and ob["step"] == 14
     assert abs(ob["total_surf"] - M0) <= 1e-3 * M0
+
+
+def test_forward_wide_grid_matches_reference(lbfd):
+    """Grids at least 64 output nodes wide run the brick kernels (input staged in
+    LDS per 32 x 4 x 2 output brick); ragged in every direction."""
+    import torch
+
+    rng = np.random.default_rng(13)
+    ps = gpu_params(OS.init_params(5, out_scale=1.0))
+    x6 = bf16(rng.uniform(-1.0, 1.0, (1, 11, 14, 75, 6)))
+    sg = make_sg(lbfd, tile=4, max_batch=1, field=(67, 6, 3))
+    sg.set_params(OS.flatten(ps))
+    out = torch.empty((1, 3, 6, 67, 2), dtype=torch.float32, device="cuda")
+    sg.forward(bf16_tensor(padded_input(x6)), out)
+    ref, _ = ref_forward(ps, x6)
+    err = float(np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max())
+    say(f"wide forward max rel err {err:.2e}")
+    assert err < 5e-3
