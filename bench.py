@@ -157,6 +157,9 @@ def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, seed=0):
     say = lambda *a: print("[surrogate]", *a, file=sys.stderr, flush=True)
     rng = np.random.default_rng(seed)
     p, q = W.multi_bubble(n=n, count=8, diameter=24.0, Eo=10.0, Bi=1.0, seed=seed, precision="fp32")
+    # SOR launch budget as for the headline workload, with a wider margin: the first
+    # frozen-flow substep starts its solve without an extrapolated guess
+    p["sor_max_sweeps"] = sweep_budget(p, q, 20, margin=4)
     N = n ** 3
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -204,7 +207,10 @@ def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, seed=0):
     ms_inf = timed(lambda: [(sg.features(s, feat), sg.forward(x, out)) for _ in range(reps)])[0] / reps
     ms_net = timed(lambda: sg.forward(x, out))[0]
     ms_fd = timed(lambda: s.fd_substeps(k))[0]
-    fd_drift = s.observables()["drift_pre"]   # pre-rescale drift of the last FD substep
+    ob = s.observables(check=False)
+    if ob["status"] != 0:
+        raise RuntimeError(f"FD substeps: solver status {ob['status']}")
+    fd_drift = ob["drift_pre"]   # pre-rescale drift of the last FD substep
     s.close()
     del s
     # surrogate mode and its references from one warm state (deterministic runs)
@@ -218,21 +224,30 @@ def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, seed=0):
             r.fd_substeps(k)
             r.set_fd(False).step(k).set_fd(True)
 
+    def ok(r, what):
+        st = r.observables(check=False)["status"]
+        if st != 0:
+            raise RuntimeError(f"{what}: solver status {st}")
+
     a = warm()
     ms_strict, rep_strict = timed(lambda: sg.advance(a, blocks))
+    ok(a, "surrogate mode (strict gate)")
     a.close()
     a = warm()
     sg.set_drift_tol(1e-3)
     ms_open, rep_open = timed(lambda: sg.advance(a, blocks))
+    ok(a, "surrogate mode (open gate)")
     psi_a = a.field("psi")
     a.close()
     b = warm()
     psi0 = b.field("psi")
     ms_fdm, _ = timed(lambda: fd_mode(b))
+    ok(b, "FD-substep mode")
     psi_b = b.field("psi")
     b.close()
     c = warm()
     ms_plain, _ = timed(lambda: c.step(blocks * k))
+    ok(c, "plain stepping")
     psi_c = c.field("psi")
     c.close()
     nrm = lambda v: float(np.sqrt((v * v).sum()))
@@ -242,6 +257,7 @@ def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, seed=0):
     mlups = lambda ms: round(N * steps / (ms / 1e3) / 1e6, 1)
     return dict(
         workload=f"multi_bubble {n}^3 periodic D3Q19, 8 bubbles D=24, Eo=10, Bi=1, FP32 solver; k={k} substeps",
+        sor_sweeps_launched=p["sor_max_sweeps"],
         tiles_train=snapshots * tiles_per_snap, tiles_heldout=int(Xh.shape[0]), data_s=round(t_data, 2),
         train_steps=train_steps, batch=8, train_ms=round(ms_train, 1),
         train_tiles_per_s=round(train_steps * 8 / (ms_train / 1e3), 1),
