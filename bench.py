@@ -278,6 +278,51 @@ def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, seed=0):
         fd_mode_psi_rel_error_vs_plain=round(nrm(psi_b - psi_c) / max(nrm(psi_c - psi0), 1e-300), 4))
 
 
+def rise_validation(R, precision, max_steps, chunk, tol, cases=(0.4, 0.2, 0.1)):
+    """Clean buoyant bubble (Eo = 1, Mo = 0.1, density and viscosity ratio 10) in
+    walled channels of 2R/L_x = 0.4, 0.2 and 0.1 (L_x x L_y x L_z = 5R x 5R x 10R,
+    10R x 10R x 10R, 20R x 20R x 10R, periodic in z, Sec 3.4): the rise velocity of
+    eq 33 until it changes by less than tol over one chunk of steps, divided by
+    the Hadamard-Rybczynski velocity of eq 35. The FD part is off (no surfactant)."""
+    import workloads as W
+    from paper_2311_15242_amd import lbfd
+
+    say = lambda *a: print("[rise]", *a, file=sys.stderr, flush=True)
+    out = []
+    for ratio in cases:
+        m = int(round(2.0 / ratio))
+        p, q = W.bubble_rise(nx=m * R, ny=m * R, nz=10 * R, radius=float(R), Eo=1.0, Mo=0.1, clean=True,
+                             precision=precision, fd_enable=0)
+        g = -p["gravity"][2]
+        drho = p["rhoB0"] - p["rhoR0"]
+        muB, muR = p["muB0"], p["muR0"]
+        u_th = (2.0 / 3.0) * g * drho * R * R / muB * (muB + muR) / (2.0 * muB + 3.0 * muR)
+        s = lbfd.Solver(p).init_fields(q)
+        hist = []
+        steps = 0
+        t0 = time.time()
+        while steps < max_steps:
+            s.step(chunk)
+            steps += chunk
+            ob = s.observables()
+            u = ob["velocity"][2]
+            hist.append(u / u_th)
+            if len(hist) >= 3 and abs(hist[-1] - hist[-2]) <= tol * abs(hist[-1]) and \
+                    abs(hist[-2] - hist[-3]) <= tol * abs(hist[-2]):
+                break
+        uz_mean = float(s.field("u")[2].mean())
+        say(f"2R/Lx={ratio}: U/U_th={hist[-1]:.4f}, mean u_z/U_th={uz_mean / u_th:.4f} after {steps} steps "
+            f"({time.time() - t0:.1f} s)")
+        out.append(dict(confinement=ratio, grid=[p["nx"], p["ny"], p["nz"]], steps=steps, u_over_uth=round(hist[-1], 4),
+                        mean_uz_over_uth=round(uz_mean / u_th, 4),
+                        u_th=u_th, re=2.0 * p["rhoB0"] * hist[-1] * u_th * R / muB,
+                        converged=len(hist) >= 3 and abs(hist[-1] - hist[-2]) <= tol * abs(hist[-1]),
+                        history=[round(v, 4) for v in hist[::max(1, len(hist) // 12)]]))
+        s.close()
+    return dict(workload=f"clean bubble rise, R={R}, Eo=1, Mo=0.1, {precision}", paper=[0.552, 0.811, 0.937],
+                cases=out)
+
+
 def cpu_baseline(p, q, budget_s):
     """The oracle as it stands, timed on the host cores: whole steps of the same
     workload (FP64), as many as fit the time budget (at least one)."""
@@ -501,6 +546,13 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance parameter sweep")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate measurement")
+    ap.add_argument("--validate-rise", type=int, default=0, metavar="R",
+                    help="clean bubble terminal velocity against Hadamard-Rybczynski at three confinements (radius R)")
+    ap.add_argument("--rise-precision", default="fp32")
+    ap.add_argument("--rise-max-steps", type=int, default=80000)
+    ap.add_argument("--rise-chunk", type=int, default=2000)
+    ap.add_argument("--rise-tol", type=float, default=2e-3)
+    ap.add_argument("--rise-cases", default="0.4,0.2,0.1", help="confinement ratios 2R/L_x to run")
     ap.add_argument("--sg-size", type=int, default=256)
     ap.add_argument("--sg-snapshots", type=int, default=16)
     ap.add_argument("--sg-tiles", type=int, default=64)
@@ -537,6 +589,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_calibration_bytes=n * 4, repeats=5)))
+        return
+    if args.validate_rise:
+        cases = tuple(float(c) for c in args.rise_cases.split(","))
+        print(json.dumps(rise_validation(args.validate_rise, args.rise_precision, args.rise_max_steps,
+                                         args.rise_chunk, args.rise_tol, cases)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "

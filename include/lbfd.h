@@ -82,7 +82,7 @@ typedef struct {
     double Ds, Db;               /* interface and bulk surfactant diffusivities (eqs 20-21) */
     double ra, rd;               /* adsorption and desorption coefficients (eq 22) */
     int32_t source_mode;         /* 0: j of eq 22; 1: adsorption only, j = ra psi_inf phi (Sec 3.1) */
-    double gravity[3];           /* body force F_b = (rho - rhoB0) * gravity (Sec 3.4) */
+    double gravity[3];           /* body force F_b = (rho - rho_ref) * gravity (Sec 3.4; see buoyancy_ref) */
     double sor_omega;            /* SOR relaxation factor (1.2 in Sec 2.2) */
     double sor_tol;              /* stop at max|residual| <= sor_tol * max|rhs| (red-black ordering;
                                     with sor_omega = 1 the test after sweep s is the red residual at
@@ -99,6 +99,9 @@ typedef struct {
                                     function and the bulk indicator of eqs 20-21 vanish */
     double upwind_eps;           /* |u_a| <= upwind_eps weighs both WENO differences by 1/2 (eq 25 is
                                     0/0 at u = 0); 1e-12 keeps rounding noise out of the upwind choice */
+    int32_t buoyancy_ref;        /* F_b = (rho - rho_ref) gravity with rho_ref = rhoB0 (0, as printed in
+                                    Sec 3.4) or the mean density of the domain (1: no net force on a
+                                    periodic domain; fixed when the fields are initialised or set) */
 } lbfd_params;
 
 /* Initial state: up to 16 red drops or bubbles with a tanh colour profile of

@@ -47,7 +47,7 @@ class _Params(C.Structure):
         ("sor_omega", C.c_double), ("sor_tol", C.c_double), ("sor_max_sweeps", C.c_int32),
         ("weno_eps", C.c_double), ("rescale", C.c_int32), ("fd_enable", C.c_int32),
         ("q_literal", C.c_int32), ("eps_n", C.c_double), ("recolour_literal", C.c_int32),
-        ("fd_eps", C.c_double), ("upwind_eps", C.c_double),
+        ("fd_eps", C.c_double), ("upwind_eps", C.c_double), ("buoyancy_ref", C.c_int32),
     ]
 
 
@@ -136,6 +136,7 @@ def params_struct(p: dict) -> _Params:
         setattr(s, k, float(p[k]))
     for k in ("source_mode", "sor_max_sweeps", "rescale", "fd_enable", "q_literal", "recolour_literal"):
         setattr(s, k, int(p[k]))
+    s.buoyancy_ref = int(p.get("buoyancy_ref", 0))
     return s
 
 

@@ -53,6 +53,8 @@ typedef struct {
     int32_t recolour_literal; /* eq 11 weight: 0 = local rest equilibrium per unit density (reading), 1 = lattice w_i */
     double fd_eps;          /* background added to the FD weights G = |grad rhoN| and X = 1 - rhoN */
     double upwind_eps;      /* |u_a| at or below this takes both one-sided WENO differences by halves */
+    int32_t buoyancy_ref;   /* F_b = (rho - rho_ref) g: 0 = rhoB0 as printed (Sec 3.4), 1 = the mean
+                               density of the domain (no net force on a periodic domain) */
 } orc_params;
 
 typedef struct {
@@ -332,6 +334,13 @@ static void force_stage(orc_state *s)
     for (int a = 0; a < D; ++a) op_deriv(s, s->psi, -1, a, s->gpsi[a]);
 
     double sig_min = p->sigma_min_ratio * p->sigma0;
+    /* reference density of the buoyancy: rhoB0, or the domain mean (exactly conserved) */
+    double rho_ref = p->rhoB0;
+    if (p->buoyancy_ref == 1) {
+        double m = 0.0;
+        for (long n = 0; n < N; ++n) m += s->rho[n];
+        rho_ref = m / (double)N;
+    }
     /* CMC below eq 8: the psi at which sigma reaches sigma_min. */
     double cmc = p->E0 > 0.0 ? p->psi_inf * (1.0 - exp(-(1.0 - p->sigma_min_ratio) / p->E0)) : p->psi_inf;
     FOR_NODES(s) {
@@ -351,8 +360,9 @@ static void force_stage(orc_state *s)
         }
         double rho = s->rho[n];
         for (int a = 0; a < D; ++a) {
-            /* Sec 3.4: F_b = (rho - rhoB0) g k, added like F_s. Reading: gravity is a signed vector. */
-            s->F[a][n] = Fs[a] + (rho - p->rhoB0) * p->gravity[a];
+            /* Sec 3.4: F_b = (rho - rhoB0) g k, added like F_s. Reading: gravity is a signed vector.
+               buoyancy_ref = 1 takes the mean density of the domain instead of rhoB0. */
+            s->F[a][n] = Fs[a] + (rho - rho_ref) * p->gravity[a];
             s->u[a][n] = (s->j[a][n] + 0.5 * s->F[a][n]) / rho; /* eq 10 */
         }
         /* eq 43 and the mu-s_v relation of Appendix A (delta_t = 1). */

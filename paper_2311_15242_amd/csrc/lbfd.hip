@@ -344,7 +344,7 @@ template <int LAT, class P> __device__ __forceinline__ void force_body(const KP<
     const R rho = rR + rB, irho = R(1) / rho;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        R Fa = Fs[a] + (rho - k.rhoB0) * k.grav[a];
+        R Fa = Fs[a] + (rho - k.rho_ref) * k.grav[a];
         const R ua = (ld(mac + (3 + a) * N, n) + R(0.5) * Fa) * irho;
         st(k.fld.F + a * N, n, Fa);
         st(k.fld.u + a * N, n, ua);
@@ -1460,6 +1460,7 @@ struct lbfd_handle {
     double *obs_out;  // device, NRED doubles (inside the workspace)
     StepGraphs graphs;
     bool fd_off = false;  // LB steps only (psi, phi held): surrogate mode between its updates
+    bool kp_dirty = false;  // the parameter block changed after creation (a batch re-uploads its table)
 };
 
 // A batch: independent instances (ordinary handles on slices of one workspace)
@@ -1542,6 +1543,7 @@ int check_params(const lbfd_params *p)
     for (int a = 0; a < 3; ++a)
         if (p->bc[a] != LBFD_PERIODIC && p->bc[a] != LBFD_WALL) return LBFD_EINVAL;
     if (p->lattice == LBFD_D2Q9 && p->bc[2] != LBFD_PERIODIC) return LBFD_EINVAL;
+    if (p->buoyancy_ref != 0 && p->buoyancy_ref != 1) return LBFD_EINVAL;
     return LBFD_OK;
 }
 
@@ -1645,6 +1647,7 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
     k.Ds = (R)p->Ds; k.Db = (R)p->Db; k.ra = (R)p->ra; k.rd = (R)p->rd;
     k.source_mode = p->source_mode;
     for (int a = 0; a < 3; ++a) k.grav[a] = (R)p->gravity[a];
+    k.rho_ref = (R)p->rhoB0;   // the domain mean replaces it when the fields are set (buoyancy_ref = 1)
     k.omega = (R)p->sor_omega;
     k.tol = (R)p->sor_tol;
     k.seam = seam_axes(p);
@@ -1768,8 +1771,27 @@ template <int LAT, class P> struct Impl {
         LAUNCH(KC_GEOM, (k_geom<LAT, P>), h->grid, h->block, k, k.lev);
         clear_scalars(h);
         totals(h, k.lev, k.pc, 1.0, 0);
+        if (h->p.buoyancy_ref == 1) {
+            // the domain-mean density (exactly conserved) as the buoyancy reference
+            lbfd_obs o;
+            const int st = observables(h, &o);
+            if (st != LBFD_OK && st != LBFD_ENONFINITE && st != LBFD_ESOR) return st;
+            set_rho_ref(h, (o.mass_R + o.mass_B) / (double)h->N);
+        }
         LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
         return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    // A parameter-block change after creation: captured graphs hold the old block.
+    static void set_rho_ref(lbfd_handle *h, double v)
+    {
+        kp(h).rho_ref = (R)v;
+        h->kp_dirty = true;
+        if (!h->graphs.cache.empty()) {
+            hipStreamSynchronize(h->stream);
+            for (auto &g : h->graphs.cache) hipGraphExecDestroy(g.exec);
+            h->graphs.cache.clear();
+        }
     }
 
     static void clear_scalars(lbfd_handle *h)
@@ -1808,6 +1830,11 @@ template <int LAT, class P> struct Impl {
         LAUNCH(KC_OTHER, (k_import<LAT, P>), h->grid, h->block, k, df, drR, drB, dps, dph, Sp ? dS : nullptr,
                Bp ? dB : nullptr);
         LAUNCH(KC_OTHER, (k_sor_clear<R>), dim3(1), dim3(256), k, h->sweeps_launch);
+        if (h->p.buoyancy_ref == 1) {
+            double m = 0.0;
+            for (long long n = 0; n < N; ++n) m += rR[n] + rB[n];
+            set_rho_ref(h, m / (double)N);
+        }
         derived(h);
         DevScalars z;
         std::memset(&z, 0, sizeof(z));
@@ -2571,10 +2598,22 @@ int lbfd_batch_step(lbfd_batch *b, int64_t n)
 {
     if (!b || n < 0) return LBFD_EINVAL;
     lbfd_handle *h0 = b->inst[0];
-    for (lbfd_handle *h : b->inst)
+    bool dirty = false;
+    for (lbfd_handle *h : b->inst) {
         if (h->step != h0->step || h->fc != h0->fc || h->pc != h0->pc || h->fd_hist != h0->fd_hist)
             return LBFD_EINVAL;
-    return dispatch_for(h0->p.lattice, h0->p.precision).batch_step(b, n);
+        dirty = dirty || h->kp_dirty;
+    }
+    Dispatch dp = dispatch_for(h0->p.lattice, h0->p.precision);
+    if (dirty) {
+        // a parameter block changed after the table was written (the buoyancy reference)
+        if (hipStreamSynchronize(h0->stream) != hipSuccess) return LBFD_EHIP;
+        const int st = dp.batch_table(b);
+        if (st != LBFD_OK) return st;
+        for (lbfd_handle *h : b->inst) h->kp_dirty = false;
+        b->graphs.release();
+    }
+    return dp.batch_step(b, n);
 }
 
 // ------------------------------------------------------------------ frozen-flow substeps

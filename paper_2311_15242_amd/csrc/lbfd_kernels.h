@@ -160,6 +160,7 @@ template <class R> struct KP {
     R Ds, Db, ra, rd;
     int source_mode;
     R grav[3];
+    R rho_ref;          // reference density of the buoyancy (rhoB0, or the domain mean)
     R omega;
     R tol;
     int seam;           // periodic axes of odd extent (bit a): seam classes of the SOR ordering

@@ -339,3 +339,35 @@ def test_nonfinite_written_into_psi_is_reported(lbfd):
     psi[0, 16, 16] = np.nan
     s.write_field("psi", psi).step(1)
     assert s.observables(check=False)["status"] == lbfd.LBFD_ENONFINITE
+
+
+@pytest.mark.parametrize("path", ["init", "set_state", "batch"])
+def test_mean_density_buoyancy_reference(lbfd, path):
+    """buoyancy_ref = 1 (the domain-mean density replaces rhoB0 in F_b) against
+    the oracle, FP64, on a periodic box with gravity and a bubble; the reference
+    is fixed by lbfd_init_fields, by lbfd_set_state, and reaches the table of a
+    batch."""
+    say(f"[buoyancy_ref=1] {path}")
+    p, q = W.make(dict(lattice=W.D3Q19, nx=16, ny=14, nz=18, rhoR0=0.2, muR0=0.03, muB0=0.1, sigma0=0.005,
+                       Ds=0.05, Db=0.05, gravity=[0.0, 1e-5, -4e-5], buoyancy_ref=1, precision="fp64"),
+                  dict(drops=[(7.5, 6.5, 6.0, 4.5)], width=3.0, psi0=0.1, phi0_out=0.05, phi0_in=0.0))
+    o = oracle.Oracle(dict(p, precision="fp64")).init(q)
+    if path == "init":
+        s = lbfd.Solver(p).init_fields(q)
+    elif path == "set_state":
+        s = lbfd.Solver(p).init_fields(q)
+        s0 = lbfd.Solver(dict(p, buoyancy_ref=0)).init_fields(q)
+        s.set_state(s0.field("f"), s0.field("rhoR"), s0.field("rhoB"), s0.field("psi"), s0.field("phi"), step=0,
+                    M0=s0.observables()["total_surf"])
+    else:
+        b = lbfd.Batch([p, dict(p, buoyancy_ref=0)])
+        b[0].init_fields(q)
+        b[1].init_fields(q)
+        b.step(25)
+        s = b[0]
+    if path != "batch":
+        s.step(25)
+    o.step(25)
+    errs = state_errors(s, o)
+    say(errs)
+    assert max(errs.values()) < 1e-10, errs

@@ -610,3 +610,34 @@ def test_source_budget_of_one_step(mode):
     dF = (X1 * o.field("phi")).sum() - (X0 * phi0).sum()
     assert dP == pytest.approx(j * G0.sum(), rel=1e-10)
     assert dF == pytest.approx(-j * G0.sum(), rel=1e-10)
+
+
+@pytest.mark.parametrize("ref", [0, 1])
+def test_buoyancy_momentum_budget(ref):
+    """Sec 3.4 buoyancy on a periodic box without surface tension: the raw
+    momentum sum(f e) grows each step by exactly sum((rho - rho_ref) g) of the
+    step's start, which is zero with the domain-mean reference (buoyancy_ref =
+    1) and not with rhoB0 (the printed form)."""
+    p = tiny(W.D3Q19, n=8, rhoR0=0.3, rhoB0=1.0, muR0=0.05, sigma0=0.0, E0=0.0, fd_enable=0,
+             gravity=[0.0, 0.0, -1e-4], buoyancy_ref=ref)
+    q = dict(drops=[(3.5, 3.5, 3.5, 2.5)], width=2.0, psi0=0.0, phi0_out=0.0, phi0_in=0.0)
+    o = oracle.Oracle(p).init(W.make(p, q)[1])
+    e = o.lattice()["e"].astype(float)
+    g = np.array(p["gravity"])
+
+    def momentum_and_force():
+        f = o.field("fR") + o.field("fB")
+        P = np.tensordot(e.T, f.reshape(f.shape[0], -1), axes=1).sum(1)
+        rho = f.sum(0)
+        rref = rho.mean() if ref else p["rhoB0"]
+        return P, (rho - rref).sum() * g
+
+    for _ in range(3):
+        P0, F = momentum_and_force()
+        o.step(1)
+        P1, _ = momentum_and_force()
+        assert np.abs((P1 - P0) - F).max() <= 1e-12 * max(np.abs(F).max(), 1e-3)
+        if ref:
+            assert np.abs(F).max() <= 1e-14
+        else:
+            assert np.abs(F[2]) > 1e-4

@@ -38,6 +38,7 @@ BASE_PARAMS = dict(
     weno_eps=1e-6, rescale=1, fd_enable=1, q_literal=0, eps_n=1e-12, recolour_literal=0,
     fd_eps=1e-10,                # background support of the FD weights (FP32 modes: 1e-6)
     upwind_eps=1e-12,            # |u| band in which the WENO upwind weights are 1/2 each
+    buoyancy_ref=0,              # buoyancy reference density: 0 = rhoB0 (Sec 3.4), 1 = domain mean
     precision="fp64",
 )
 
