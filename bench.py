@@ -325,6 +325,47 @@ def rise_validation(R, precision, max_steps, chunk, tol, cases=(0.4, 0.2, 0.1), 
                 paper=[0.552, 0.811, 0.937], cases=out)
 
 
+def ygb_validation(R, precision, max_steps, chunk, tol, widths=(5, 10)):
+    """Drop migration in the imposed surfactant gradient of Sec 3.2 (linear
+    tension law, psi held at the ramp of eq 31, walls in x and y, L_z = 10R):
+    the migration velocity of eq 33 until it changes by less than tol over two
+    chunks of steps, divided by the YGB velocity of eq 32."""
+    import workloads as W
+    from paper_2311_15242_amd import lbfd
+
+    say = lambda *a: print("[ygb]", *a, file=sys.stderr, flush=True)
+    out = []
+    for wr in widths:
+        p, q = W.ygb_migration(R=R, width=wr, precision=precision)
+        u_ygb = 2.0 * p["sigma0"] * p["E0"] * R / (p["nz"] * (6.0 * p["muR0"] + 9.0 * p["muB0"]))
+        s = lbfd.Solver(p).init_fields(q).write_field("psi", W.migration_psi(p))
+        hist = []
+        steps = 0
+        t0 = time.time()
+        while steps < max_steps:
+            s.step(chunk)
+            steps += chunk
+            hist.append(s.observables()["velocity"][2] / u_ygb)
+            if len(hist) % 5 == 0:
+                say(f"  L_x = {wr}R: {steps} steps, U/U_YGB={hist[-1]:.4f}")
+            if len(hist) >= 3 and abs(hist[-1] - hist[-2]) <= tol * abs(hist[-1]) and \
+                    abs(hist[-2] - hist[-3]) <= tol * abs(hist[-2]):
+                break
+        ob = s.observables()
+        uz_mean = float(s.field("u")[2].mean())
+        say(f"L_x = {wr}R: U/U_YGB={hist[-1]:.4f}, mean u_z/U_YGB={uz_mean / u_ygb:.4f} after {steps} steps "
+            f"({time.time() - t0:.1f} s)")
+        out.append(dict(width=wr, grid=[p["nx"], p["ny"], p["nz"]], steps=steps, u_over_uygb=round(hist[-1], 4),
+                        mean_uz_over_uygb=round(uz_mean / u_ygb, 4), u_ygb=u_ygb,
+                        tau=round(hist[-1] * u_ygb * steps / R, 3),
+                        drift_z=round(ob["centroid"][2] - q["drops"][0][2], 3),
+                        converged=len(hist) >= 3 and abs(hist[-1] - hist[-2]) <= tol * abs(hist[-1]),
+                        history=[round(v, 4) for v in hist[::max(1, len(hist) // 12)]]))
+        s.close()
+    return dict(workload=f"drop migration in an imposed surfactant gradient, R={R}, {precision}",
+                paper=[0.958, 0.993], cases=out)
+
+
 def cpu_baseline(p, q, budget_s):
     """The oracle as it stands, timed on the host cores: whole steps of the same
     workload (FP64), as many as fit the time budget (at least one)."""
@@ -556,6 +597,13 @@ def main():
     ap.add_argument("--rise-tol", type=float, default=2e-3)
     ap.add_argument("--rise-cases", default="0.4,0.2,0.1", help="confinement ratios 2R/L_x to run")
     ap.add_argument("--rise-buoyancy-ref", type=int, default=0, help="0: rhoB0 as printed; 1: domain-mean density")
+    ap.add_argument("--validate-ygb", type=int, default=0, metavar="R",
+                    help="drop migration in an imposed gradient (Sec 3.2) at drop radius R, against eq 32")
+    ap.add_argument("--ygb-precision", default="fp32")
+    ap.add_argument("--ygb-max-steps", type=int, default=200000)
+    ap.add_argument("--ygb-chunk", type=int, default=2000)
+    ap.add_argument("--ygb-tol", type=float, default=1e-3)
+    ap.add_argument("--ygb-widths", default="5,10", help="box widths L_x = L_y in units of R")
     ap.add_argument("--sg-size", type=int, default=256)
     ap.add_argument("--sg-snapshots", type=int, default=16)
     ap.add_argument("--sg-tiles", type=int, default=64)
@@ -592,6 +640,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_calibration_bytes=n * 4, repeats=5)))
+        return
+    if args.validate_ygb:
+        widths = tuple(float(c) for c in args.ygb_widths.split(","))
+        print(json.dumps(ygb_validation(args.validate_ygb, args.ygb_precision, args.ygb_max_steps,
+                                        args.ygb_chunk, args.ygb_tol, widths)), flush=True)
         return
     if args.validate_rise:
         cases = tuple(float(c) for c in args.rise_cases.split(","))

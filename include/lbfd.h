@@ -102,6 +102,8 @@ typedef struct {
     int32_t buoyancy_ref;        /* F_b = (rho - rho_ref) gravity with rho_ref = rhoB0 (0, as printed in
                                     Sec 3.4) or the mean density of the domain (1: no net force on a
                                     periodic domain; fixed when the fields are initialised or set) */
+    int32_t eos_mode;            /* 0: Langmuir law of eq 8, floored at sigma_min beyond the CMC;
+                                    1: linear law sigma = sigma0 (1 - E0 psi / psi_inf) of Sec 3.2 */
 } lbfd_params;
 
 /* Initial state: up to 16 red drops or bubbles with a tanh colour profile of

@@ -48,6 +48,7 @@ class _Params(C.Structure):
         ("weno_eps", C.c_double), ("rescale", C.c_int32), ("fd_enable", C.c_int32),
         ("q_literal", C.c_int32), ("eps_n", C.c_double), ("recolour_literal", C.c_int32),
         ("fd_eps", C.c_double), ("upwind_eps", C.c_double), ("buoyancy_ref", C.c_int32),
+        ("eos_mode", C.c_int32),
     ]
 
 
@@ -137,6 +138,7 @@ def params_struct(p: dict) -> _Params:
     for k in ("source_mode", "sor_max_sweeps", "rescale", "fd_enable", "q_literal", "recolour_literal"):
         setattr(s, k, int(p[k]))
     s.buoyancy_ref = int(p.get("buoyancy_ref", 0))
+    s.eos_mode = int(p.get("eos_mode", 0))
     return s
 
 

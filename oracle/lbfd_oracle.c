@@ -55,6 +55,8 @@ typedef struct {
     double upwind_eps;      /* |u_a| at or below this takes both one-sided WENO differences by halves */
     int32_t buoyancy_ref;   /* F_b = (rho - rho_ref) g: 0 = rhoB0 as printed (Sec 3.4), 1 = the mean
                                density of the domain (no net force on a periodic domain) */
+    int32_t eos_mode;       /* 0: Langmuir law of eq 8 with the CMC floor; 1: the linear law
+                               sigma = sigma0 (1 - E0 psi / psi_inf) of Sec 3.2, no floor */
 } orc_params;
 
 typedef struct {
@@ -348,6 +350,14 @@ static void force_stage(orc_state *s)
         double psi = s->psi[n], Fs[3] = {0, 0, 0};
         if (p->E0 == 0.0) {
             for (int a = 0; a < D; ++a) Fs[a] = -0.5 * p->sigma0 * s->kappa[n] * s->g[a][n];
+        } else if (p->eos_mode == 1) {
+            /* Sec 3.2: sigma linear in psi, so d sigma / d psi = -sigma0 E0 / psi_inf everywhere */
+            double sigma = p->sigma0 * (1.0 - p->E0 * psi / p->psi_inf);
+            double ndg = 0.0;
+            for (int a = 0; a < D; ++a) ndg += s->nrm[a][n] * s->gpsi[a][n];
+            double mar = 0.5 * s->G[n] * p->sigma0 * p->E0 / p->psi_inf;
+            for (int a = 0; a < D; ++a)
+                Fs[a] = -0.5 * sigma * s->kappa[n] * s->g[a][n] - mar * (s->gpsi[a][n] - ndg * s->nrm[a][n]);
         } else if (psi < cmc) {
             double sigma = p->sigma0 * (1.0 + p->E0 * log(1.0 - psi / p->psi_inf));
             double ndg = 0.0;
@@ -1081,6 +1091,7 @@ double orc_sigma(const orc_state *s, double psi)
 {
     const orc_params *p = &s->p;
     if (p->E0 == 0.0) return p->sigma0;
+    if (p->eos_mode == 1) return p->sigma0 * (1.0 - p->E0 * psi / p->psi_inf); /* Sec 3.2 */
     return fmax(p->sigma0 * (1.0 + p->E0 * log(1.0 - psi / p->psi_inf)), p->sigma_min_ratio * p->sigma0); /* eq 8 */
 }
 

@@ -328,6 +328,15 @@ template <int LAT, class P> __device__ __forceinline__ void force_body(const KP<
     if (k.E0 == R(0)) {
 #pragma unroll
         for (int a = 0; a < D; ++a) Fs[a] = R(-0.5) * k.sigma0 * kappa * g[a];
+    } else if (k.eos_linear) {
+        // Sec 3.2: d sigma / d psi = -sigma0 E0 / psi_inf at every psi
+        R sigma = k.sigma0 * (R(1) - k.E0 * psi / k.psi_inf);
+        R ndg = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) ndg += nv[a] * gp[a];
+        R mar = R(0.5) * G * k.sigma0 * k.E0 / k.psi_inf;
+#pragma unroll
+        for (int a = 0; a < D; ++a) Fs[a] = R(-0.5) * sigma * kappa * g[a] - mar * (gp[a] - ndg * nv[a]);
     } else if (psi < k.cmc) {
         R sigma = k.sigma0 * (R(1) + k.E0 * log(R(1) - psi / k.psi_inf));
         R ndg = 0;
@@ -1544,6 +1553,7 @@ int check_params(const lbfd_params *p)
         if (p->bc[a] != LBFD_PERIODIC && p->bc[a] != LBFD_WALL) return LBFD_EINVAL;
     if (p->lattice == LBFD_D2Q9 && p->bc[2] != LBFD_PERIODIC) return LBFD_EINVAL;
     if (p->buoyancy_ref != 0 && p->buoyancy_ref != 1) return LBFD_EINVAL;
+    if (p->eos_mode != 0 && p->eos_mode != 1) return LBFD_EINVAL;
     return LBFD_OK;
 }
 
@@ -1644,6 +1654,7 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
     k.sigma0 = (R)p->sigma0; k.E0 = (R)p->E0; k.psi_inf = (R)p->psi_inf;
     k.sigma_min = (R)(p->sigma_min_ratio * p->sigma0);
     k.cmc = (R)(p->E0 > 0 ? p->psi_inf * (1.0 - std::exp(-(1.0 - p->sigma_min_ratio) / p->E0)) : p->psi_inf);
+    k.eos_linear = p->eos_mode == 1;
     k.Ds = (R)p->Ds; k.Db = (R)p->Db; k.ra = (R)p->ra; k.rd = (R)p->rd;
     k.source_mode = p->source_mode;
     for (int a = 0; a < 3; ++a) k.grav[a] = (R)p->gravity[a];

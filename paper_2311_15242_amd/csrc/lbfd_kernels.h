@@ -157,6 +157,7 @@ template <class R> struct KP {
     R beta;
     int recolour_literal;
     R sigma0, E0, psi_inf, sigma_min, cmc;
+    int eos_linear;     // sigma = sigma0 (1 - E0 psi / psi_inf) without a floor (Sec 3.2)
     R Ds, Db, ra, rd;
     int source_mode;
     R grav[3];

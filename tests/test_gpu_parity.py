@@ -208,13 +208,14 @@ def test_walled_boxes_fp64(lbfd, case, steps):
 
 
 @pytest.mark.parametrize("variant", ["omega1.2", "source_adsorption", "q_literal", "recolour_literal",
-                                     "clean_E0", "minimal_4x4x4"])
+                                     "clean_E0", "linear_eos", "minimal_4x4x4"])
 def test_switches_and_edge_sizes_fp64(lbfd, variant):
     """Parameter switches and edge sizes, FP64 against the oracle: the paper's
     SOR factor 1.2 (both colours tested for convergence), the adsorption-only
     source of Sec 3.1, the printed 3-D correction factor and recolouring weight
-    (the literal forms of the paper), a clean interface (E0 = 0), and the
-    smallest grid the library accepts."""
+    (the literal forms of the paper), a clean interface (E0 = 0), the linear
+    tension law of Sec 3.2 with psi transported, and the smallest grid the
+    library accepts."""
     say(f"[switch {variant}]")
     steps = 20
     if variant == "omega1.2":
@@ -229,6 +230,8 @@ def test_switches_and_edge_sizes_fp64(lbfd, variant):
         steps = 60
     elif variant == "clean_E0":
         p, q = walled_box_3d("fp64", E0=0.0)
+    elif variant == "linear_eos":
+        p, q = walled_box_3d("fp64", eos_mode=1, E0=0.6)
     else:
         p, q = W.make(dict(lattice=W.D3Q19, nx=4, ny=4, nz=4, bc=[W.WALL, W.PERIODIC, W.WALL],
                            rhoR0=0.5, rhoB0=1.0, sigma0=0.005, Ds=0.05, Db=0.05, precision="fp64"),
@@ -371,3 +374,29 @@ def test_mean_density_buoyancy_reference(lbfd, path):
     errs = state_errors(s, o)
     say(errs)
     assert max(errs.values()) < 1e-10, errs
+
+
+@pytest.mark.parametrize("prec,tol_u", [("fp64", 1e-10), ("fp32", 2e-3)])
+def test_imposed_gradient_migration(lbfd, prec, tol_u):
+    """The migration set-up of Sec 3.2 at R = 4 (20 x 20 x 40): the linear law,
+    psi held at the ramp of eq 31 (FD off), walls in x and y, against the
+    oracle given the same ramp. psi stays as written; the drop starts to move
+    up the gradient (u_z of eq 33 > 0). FP32 bound: populations of about 0.3
+    carry a rounding of about 2e-8 per step, some 1e-7 after 40 steps, against
+    a largest |u| of about 1e-4."""
+    say(f"[imposed-gradient migration {prec}]")
+    p, q = W.ygb_migration(R=4, precision=prec)
+    ramp = W.migration_psi(p)
+    s = lbfd.Solver(p).init_fields(q).write_field("psi", ramp)
+    o = oracle.Oracle(dict(p, precision="fp64")).init(q)
+    o.set_field("psi", ramp)
+    s.step(40)
+    o.step(40)
+    u, uo = s.field("u"), o.field("u")
+    err_u = float(np.abs(u - uo).max() / np.abs(uo).max())
+    err_f = float(np.abs(s.field("rhoN") - o.field("rhoN")).max())
+    say(f"u rel err {err_u:.2e}, rhoN err {err_f:.2e}")
+    assert err_u < tol_u and err_f < (1e-12 if prec == "fp64" else 1e-5)
+    assert np.abs(s.field("psi") - ramp).max() <= (0.0 if prec == "fp64" else 1e-7)
+    vz = s.observables()["velocity"][2]
+    assert vz > 0 and vz == pytest.approx(o.observables()["velocity"][2], rel=5 * tol_u)

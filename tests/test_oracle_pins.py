@@ -378,6 +378,61 @@ def test_marangoni_force_is_surface_gradient_of_sigma():
     assert np.abs(F[0]).max() > 1e-6
 
 
+def test_linear_eos_closed_form():
+    """The linear law of Sec 3.2: sigma = sigma0 (1 - E0 psi / psi_inf) at every
+    psi, with no floor (at E0 = 0.95 it goes below sigma_min = 0.1 sigma0)."""
+    for E0, pinf in ((0.5, 1.0), (0.95, 2.0)):
+        o = oracle.Oracle(tiny(W.D2Q9, E0=E0, sigma0=0.01, psi_inf=pinf, eos_mode=1))
+        for x in (0.0, 0.1, 0.5, 0.99):
+            assert o.sigma(x * pinf) == pytest.approx(0.01 * (1 - E0 * x), rel=1e-15, abs=1e-18)
+    assert 0.01 * (1 - 0.95 * 0.99) < 0.001
+
+
+def _flat_strip_state(o, n):
+    L = o.lattice()
+    y = np.arange(n)
+    rN = np.tanh(2 * (8 - np.abs(y - 15.5)) / 3.0)[:, None] * np.ones((1, n))
+    o.set_field("fR", np.einsum("i,yx->iyx", L["w"], (1 + rN) / 2))
+    o.set_field("fB", np.einsum("i,yx->iyx", L["w"], (1 - rN) / 2))
+
+
+def test_linear_eos_marangoni_force_closed_form():
+    """Eq 9 with the linear law on a flat interface: the tangential force is
+    (1/2)|grad rhoN| (-sigma0 E0 / psi_inf) d psi/dx, the slope of the law
+    written out (not taken from the oracle's own sigma)."""
+    n = 32
+    sigma0, E0, pinf = 0.01, 0.5, 2.0
+    o = oracle.Oracle(tiny(W.D2Q9, n=n, E0=E0, sigma0=sigma0, psi_inf=pinf, eos_mode=1))
+    _flat_strip_state(o, n)
+    x = np.arange(n)
+    psi = (0.6 + 0.4 * np.sin(2 * np.pi * x / n))[None, :] * np.ones((n, 1))
+    o.set_field("psi", psi)
+    F = o.field("force")[:, 0]
+    G = o.field("G")[0]
+    dpx = 0.5 * (np.roll(psi, -1, 1) - np.roll(psi, 1, 1))
+    expect = 0.5 * G * (-sigma0 * E0 / pinf) * dpx
+    assert np.abs(F[0] - expect).max() < 1e-12 * np.abs(expect).max()
+    assert np.abs(F[0]).max() > 1e-5
+
+
+def test_linear_eos_uniform_psi_is_a_clean_interface():
+    """Uniform psi: no Marangoni term, and the capillary force equals that of a
+    clean interface (E0 = 0) of tension sigma0 (1 - E0 psi / psi_inf)."""
+    n = 24
+    L = oracle.Oracle(tiny(W.D2Q9, n=n)).lattice()
+    yy, xx = np.mgrid[0:n, 0:n]
+    rN = np.tanh(2 * (7.0 - np.hypot(xx - 11.5, yy - 12.0)) / 3.0)
+    forces = []
+    for over in (dict(E0=0.5, sigma0=0.01, psi_inf=1.0, eos_mode=1), dict(E0=0.0, sigma0=0.01 * (1 - 0.5 * 0.7))):
+        o = oracle.Oracle(tiny(W.D2Q9, n=n, **over))
+        o.set_field("fR", np.einsum("i,yx->iyx", L["w"], (1 + rN) / 2))
+        o.set_field("fB", np.einsum("i,yx->iyx", L["w"], (1 - rN) / 2))
+        o.set_field("psi", np.full((n, n), 0.7))
+        forces.append(o.field("force")[:, 0])
+    assert np.abs(forces[0] - forces[1]).max() <= 1e-14 * np.abs(forces[1]).max()
+    assert np.abs(forces[1]).max() > 1e-5
+
+
 # ---------------------------------------------------------------- flows with closed forms
 
 def _couette_error(uw, n=8, steps=1500):

@@ -39,6 +39,7 @@ BASE_PARAMS = dict(
     fd_eps=1e-10,                # background support of the FD weights (FP32 modes: 1e-6)
     upwind_eps=1e-12,            # |u| band in which the WENO upwind weights are 1/2 each
     buoyancy_ref=0,              # buoyancy reference density: 0 = rhoB0 (Sec 3.4), 1 = domain mean
+    eos_mode=0,                  # 0: Langmuir eq 8 with the CMC floor; 1: linear law of Sec 3.2
     precision="fp64",
 )
 
@@ -143,6 +144,35 @@ def bubble_rise(nx=128, ny=128, nz=384, radius=16.0, Eo=10.0, Mo=0.1, Bi=1.0,
     init = dict(drops=[(centre[0], centre[1], centre[2], radius)], width=3.0, psi0=0.0,
                 phi0_out=0.0 if clean else phi0, phi0_in=0.0)
     return make(params, init)
+
+
+# ----------------------------------------------------------------------------
+# Droplet migration in an imposed surfactant gradient (Sec 3.2): a red drop of
+# radius R at the centre of a (w R) x (w R) x 10R box with walls in x and y and
+# periodic z; both fluids of density 1 and viscosity 0.1, sigma0 = 0.001,
+# E0 = 0.5 with the linear tension law (eos_mode = 1), Ds = 0.1. The surfactant
+# is insoluble and held: the FD part is off and psi is the linear ramp of eq 31
+# (migration_psi), so the centre of the drop sits at psi = x_in psi_inf = 0.5.
+# ----------------------------------------------------------------------------
+def ygb_migration(R=30, width=5, precision="fp32", **over):
+    nx = ny = int(round(width * R))
+    nz = 10 * R
+    params = dict(lattice=D3Q19, nx=nx, ny=ny, nz=nz, bc=[WALL, WALL, PERIODIC],
+                  rhoR0=1.0, rhoB0=1.0, muR0=0.1, muB0=0.1, sigma0=0.001, E0=0.5, psi_inf=1.0,
+                  Ds=0.1, Db=0.1, ra=0.0, rd=0.0, fd_enable=0, eos_mode=1, precision=precision)
+    params.update(over)
+    init = dict(drops=[((nx - 1) / 2.0, (ny - 1) / 2.0, nz / 2.0, float(R))], width=3.0, psi0=0.5,
+                phi0_out=0.0, phi0_in=0.0)
+    return make(params, init)
+
+
+def migration_psi(p):
+    """Eq 31 on the nodes: psi = psi_inf z / L_z with L_z = nz (node z at height
+    z; the ramp restarts at the periodic seam, far from the drop). Shape
+    (nz, ny, nx)."""
+    z = np.arange(p["nz"], dtype=np.float64)
+    col = p["psi_inf"] * z / p["nz"]
+    return np.broadcast_to(col[:, None, None], (p["nz"], p["ny"], p["nx"])).copy()
 
 
 # ----------------------------------------------------------------------------
