@@ -325,11 +325,13 @@ def rise_validation(R, precision, max_steps, chunk, tol, cases=(0.4, 0.2, 0.1), 
                 paper=[0.552, 0.811, 0.937], cases=out)
 
 
-def ygb_validation(R, precision, max_steps, chunk, tol, widths=(5, 10)):
+def ygb_validation(R, precision, max_steps, chunk, tol, widths=(5, 10), min_steps=0):
     """Drop migration in the imposed surfactant gradient of Sec 3.2 (linear
     tension law, psi held at the ramp of eq 31, walls in x and y, L_z = 10R):
-    the migration velocity of eq 33 until it changes by less than tol over two
-    chunks of steps, divided by the YGB velocity of eq 32."""
+    the migration velocity of eq 33 divided by the YGB velocity of eq 32. The
+    value wobbles by a few tenths of a per cent as the drop crosses the lattice,
+    so the run stops when the means over the last two windows of five chunks
+    agree within tol, and the result is the mean over the last ten chunks."""
     import workloads as W
     from paper_2311_15242_amd import lbfd
 
@@ -337,29 +339,38 @@ def ygb_validation(R, precision, max_steps, chunk, tol, widths=(5, 10)):
     out = []
     for wr in widths:
         p, q = W.ygb_migration(R=R, width=wr, precision=precision)
-        u_ygb = 2.0 * p["sigma0"] * p["E0"] * R / (p["nz"] * (6.0 * p["muR0"] + 9.0 * p["muB0"]))
+        # eq 32 with the outer (blue) viscosity on the 6 and the drop's on the 9, as in
+        # Young, Goldstein and Block; the printed labels are the other way round, which
+        # gives the same value at the equal viscosities of the test
+        u_ygb = 2.0 * p["sigma0"] * p["E0"] * R / (p["nz"] * (6.0 * p["muB0"] + 9.0 * p["muR0"]))
         s = lbfd.Solver(p).init_fields(q).write_field("psi", W.migration_psi(p))
         hist = []
         steps = 0
+        converged = False
         t0 = time.time()
         while steps < max_steps:
             s.step(chunk)
             steps += chunk
-            hist.append(s.observables()["velocity"][2] / u_ygb)
+            ob = s.observables()
+            hist.append(ob["velocity"][2] / u_ygb)
+            r_eff = (3.0 * ob["nsum"] / (4.0 * np.pi)) ** (1.0 / 3.0)
             if len(hist) % 5 == 0:
-                say(f"  L_x = {wr}R: {steps} steps, U/U_YGB={hist[-1]:.4f}")
-            if len(hist) >= 3 and abs(hist[-1] - hist[-2]) <= tol * abs(hist[-1]) and \
-                    abs(hist[-2] - hist[-3]) <= tol * abs(hist[-2]):
+                say(f"  L_x = {wr}R: {steps} steps, U/U_YGB={hist[-1]:.4f}, drop radius {r_eff:.3f}")
+            converged = steps >= min_steps and len(hist) >= 10 and \
+                abs(np.mean(hist[-5:]) - np.mean(hist[-10:-5])) <= tol * abs(np.mean(hist[-5:]))
+            if converged:
                 break
         ob = s.observables()
         uz_mean = float(s.field("u")[2].mean())
-        say(f"L_x = {wr}R: U/U_YGB={hist[-1]:.4f}, mean u_z/U_YGB={uz_mean / u_ygb:.4f} after {steps} steps "
-            f"({time.time() - t0:.1f} s)")
-        out.append(dict(width=wr, grid=[p["nx"], p["ny"], p["nz"]], steps=steps, u_over_uygb=round(hist[-1], 4),
-                        mean_uz_over_uygb=round(uz_mean / u_ygb, 4), u_ygb=u_ygb,
-                        tau=round(hist[-1] * u_ygb * steps / R, 3),
-                        drift_z=round(ob["centroid"][2] - q["drops"][0][2], 3),
-                        converged=len(hist) >= 3 and abs(hist[-1] - hist[-2]) <= tol * abs(hist[-1]),
+        tail = np.asarray(hist[-10:])
+        say(f"L_x = {wr}R: U/U_YGB={tail.mean():.4f} +- {tail.std():.4f}, mean u_z/U_YGB={uz_mean / u_ygb:.4f} "
+            f"after {steps} steps ({time.time() - t0:.1f} s)")
+        out.append(dict(width=wr, grid=[p["nx"], p["ny"], p["nz"]], steps=steps, u_over_uygb=round(float(tail.mean()), 4),
+                        spread=round(float(tail.std()), 4), mean_uz_over_uygb=round(uz_mean / u_ygb, 4), u_ygb=u_ygb,
+                        tau=round(float(tail.mean()) * u_ygb * steps / R, 3),
+                        drift_z=round(ob["centroid"][2] - q["drops"][0][2], 3), converged=bool(converged),
+                        radius_end=round((3.0 * ob["nsum"] / (4.0 * np.pi)) ** (1.0 / 3.0), 3),
+                        seconds=round(time.time() - t0, 1),
                         history=[round(v, 4) for v in hist[::max(1, len(hist) // 12)]]))
         s.close()
     return dict(workload=f"drop migration in an imposed surfactant gradient, R={R}, {precision}",
@@ -604,6 +615,7 @@ def main():
     ap.add_argument("--ygb-chunk", type=int, default=2000)
     ap.add_argument("--ygb-tol", type=float, default=1e-3)
     ap.add_argument("--ygb-widths", default="5,10", help="box widths L_x = L_y in units of R")
+    ap.add_argument("--ygb-min-steps", type=int, default=0)
     ap.add_argument("--sg-size", type=int, default=256)
     ap.add_argument("--sg-snapshots", type=int, default=16)
     ap.add_argument("--sg-tiles", type=int, default=64)
@@ -644,7 +656,7 @@ def main():
     if args.validate_ygb:
         widths = tuple(float(c) for c in args.ygb_widths.split(","))
         print(json.dumps(ygb_validation(args.validate_ygb, args.ygb_precision, args.ygb_max_steps,
-                                        args.ygb_chunk, args.ygb_tol, widths)), flush=True)
+                                        args.ygb_chunk, args.ygb_tol, widths, args.ygb_min_steps)), flush=True)
         return
     if args.validate_rise:
         cases = tuple(float(c) for c in args.rise_cases.split(","))
