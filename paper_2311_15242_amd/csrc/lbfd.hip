@@ -157,7 +157,7 @@ __device__ __forceinline__ void load_moments(const KP<typename P::R> &k, const t
 template <int LAT, class P>
 __device__ __forceinline__ void store_moments(const KP<typename P::R> &k, typename P::S *fs, uint32_t n,
                                               typename P::R rR, typename P::R rB, const typename P::R *uj,
-                                              const typename P::R *m)
+                                              const typename P::R *m, Dither *dz = nullptr)
 {
     using R = typename P::R;
     using S = typename P::S;
@@ -166,7 +166,10 @@ __device__ __forceinline__ void store_moments(const KP<typename P::R> &k, typena
     meq_sum<LAT, R>(k, rR, rB, uj, mref);
 #pragma unroll
     for (int r = 0; r < L::Q; ++r)
-        if (!conserved_row<LAT>(r)) stu(fs + (long long)state_slot<LAT>(r) * k.N, n, from_real<S>(m[r] - mref[r]));
+        if (!conserved_row<LAT>(r)) {
+            const R v = m[r] - mref[r];
+            stu(fs + (long long)state_slot<LAT>(r) * k.N, n, dz ? from_real_sr<S>(v, dz->next()) : from_real<S>(v));
+        }
 }
 
 // Store the populations f of node n at the start of a step: as populations,
@@ -264,6 +267,10 @@ template <int LAT, class P> __device__ __forceinline__ void geom_body(const KP<t
 {
     using R = typename P::R;
     using L = Lat<LAT>;
+    // one geometry launch per step: it advances the step counter of the stochastic
+    // rounding, which only the collision and macro kernels (earlier in the step) read
+    if constexpr (P::DEV)
+        if (tile == 0 && threadIdx.x == 0 && threadIdx.y == 0) k.fld.sc->tick += 1u;
     Node nd = node_at(k, tile);
     if (!nd.ok) return;
     const long long N = k.N;
@@ -507,6 +514,7 @@ template <int LAT, class P> __device__ __forceinline__ void collide_body(const K
         st((V4<R> *)k.fld.desc, n, V4<R>{a, cf * nv[0], cf * nv[1], cf * nv[2]});
     }
     // propagation with periodic wrap or half-way bounce-back
+    Dither dz(n, P::DEV ? k.fld.sc->tick : 0u, 1u);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         // f_dag_i = (M^-1 m*)_i (deviation modes: minus ref_i)
@@ -539,7 +547,7 @@ template <int LAT, class P> __device__ __forceinline__ void collide_body(const K
         const uint32_t N32 = (uint32_t)N;
         const uint32_t dst = bo ? (uint32_t)(L::OPP[i] - lo) * N32 + n
                                 : (uint32_t)(i - lo) * N32 + n + (uint32_t)nb_delta(nb, ex, ey, ez);
-        if constexpr (P::DEV) stu(fout + lo * N, dst, from_real<S>(v));
+        if constexpr (P::DEV) stu(fout + lo * N, dst, from_real_sr<S>(v, dz.next()));
         else stu(fout + lo * N, dst, (S)v);
     }
 }
@@ -639,7 +647,8 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
         const R irho = R(1) / (rR + rB);
 #pragma unroll
         for (int d = 0; d < D; ++d) uj[d] = j[d] * irho;
-        store_moments<LAT, P>(k, (S *)k.fld.f[1 - sa.fc], n, rR, rB, uj, m);
+        Dither dz(n, k.fld.sc->tick, 2u);
+        store_moments<LAT, P>(k, (S *)k.fld.f[1 - sa.fc], n, rR, rB, uj, m, &dz);
     }
 }
 template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<typename P::R> k)

@@ -59,6 +59,45 @@ template <> __device__ __forceinline__ bf16 from_real<bf16>(float v)
 }
 __device__ __forceinline__ double from_real_d(double v) { return v; }
 
+// Stochastic rounding of the BF16 stores of the deviation mode: a value between
+// two BF16 neighbours is stored as the upper one with probability equal to its
+// distance from the lower one over their spacing, so the stored value is exact
+// on average. With round to nearest, a steady flow whose changes per step are
+// below half a spacing of the stored deviations loses them at every step
+// (stagnation); the error then repeats instead of averaging out and biases slow
+// flows. r16 holds 16 uniform random bits; finite inputs only. The FP16 mode
+// keeps round to nearest.
+template <class S> __device__ __forceinline__ S from_real_sr(float v, uint32_t) { return from_real<S>(v); }
+template <> __device__ __forceinline__ bf16 from_real_sr<bf16>(float v, uint32_t r16)
+{
+    return bf16{(uint16_t)((__float_as_uint(v) + r16) >> 16)};
+}
+
+// Random bits of the stochastic rounding: a 32-bit generator per node and
+// stage, seeded by the lowbias32 integer hash (C. Wellons) of the node index,
+// the step counter and the stage, then advanced by one linear congruential
+// step (multiplier 747796405, increment 2891336453, as in PCG32) per value; the
+// upper 16 bits are used. Deterministic: the same node, step and stage give the
+// same bits in a single run, a batch and a graph replay.
+struct Dither {
+    uint32_t s;
+    __device__ __forceinline__ Dither(uint32_t node, uint32_t tick, uint32_t stage)
+    {
+        uint32_t x = node * 0x9e3779b9u ^ (tick * 0x85ebca6bu + stage * 0xc2b2ae35u);
+        x ^= x >> 16;
+        x *= 0x7feb352du;
+        x ^= x >> 15;
+        x *= 0x846ca68bu;
+        x ^= x >> 16;
+        s = x;
+    }
+    __device__ __forceinline__ uint32_t next()
+    {
+        s = s * 747796405u + 2891336453u;
+        return s >> 16;
+    }
+};
+
 // ------------------------------------------------------------------ lattices
 
 template <int LAT> struct Lat;
@@ -96,7 +135,8 @@ struct DevScalars {
     unsigned long long rmax[2];   // max |rhs| of the last solve (bits of a non-negative double)
     int32_t sweeps[2];
     int32_t status;               // sticky lbfd_status of device-detected errors
-    int32_t pad;
+    uint32_t tick;                // geometry launches since the state was set (one per step):
+                                  // the time input of the stochastic rounding
 };
 
 // FP16 helpers of the packed descriptor (round to nearest even).

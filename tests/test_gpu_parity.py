@@ -160,11 +160,13 @@ def test_mixed_precision_vs_fp64_oracle(lbfd, prec, tol):
     assert abs(M0 - o.initial_total) <= 1e-6 * o.initial_total
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-3), ("bf16dev", 1e-3)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-3), ("bf16dev", 2e-3)])
 def test_bubble_column_full_size_sampled(lbfd, prec, tol):
     """The 3-D column at its full size (D3Q19, 128 x 128 x 384, density ratio
     10) in the launch configuration the benchmark times: two steps against the
-    oracle."""
+    oracle. The BF16 deviation stores round stochastically, so each is off by
+    less than one BF16 spacing (2^-7 of its value) instead of half of one: the
+    bound of round to nearest (1e-3 on u over the 6.3 M nodes) doubles."""
     say(f"[bubble128x128x384 {prec} 2 steps]")
     p, q = W.bubble_rise(precision=prec)
     s, o = run_pair(lbfd, p, q, 2)
@@ -243,14 +245,16 @@ def test_switches_and_edge_sizes_fp64(lbfd, variant):
     assert s.observables()["status"] == 0
 
 
-@pytest.mark.parametrize("prec,tol_u", [("fp32", 1e-4), ("fp16dev", 1e-3), ("bf16dev", 3e-3)])
+@pytest.mark.parametrize("prec,tol_u", [("fp32", 1e-4), ("fp16dev", 1e-3), ("bf16dev", 6e-3)])
 def test_mixed_precision_walled_box_3d(lbfd, prec, tol_u):
     """The 3-D walled box in the reduced-precision modes against the FP64 oracle
     after 30 steps: the colour function and the interface concentration within
-    1e-3 relative, the velocity within 1e-3 (FP16 deviations) or 3e-3 (BF16
+    1e-3 relative, the velocity within 1e-3 (FP16 deviations) or 6e-3 (BF16
     deviations). The velocities here are small (walls at 1e-2) and BF16 keeps 8
-    significant bits, so its velocity error in this box is about 2e-3; the
-    bubble and shear workloads meet 1e-3 in BF16 (tests above)."""
+    significant bits: with round to nearest the velocity error in this box was
+    about 2e-3 (bound 3e-3); the stochastic rounding of the BF16 stores allows
+    one spacing per value instead of half of one, so the bound doubles (about
+    3e-3 measured)."""
     say(f"[box3d {prec} 30 steps]")
     p, q = walled_box_3d(prec)
     s = lbfd.Solver(p).init_fields(q)
