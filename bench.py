@@ -377,6 +377,92 @@ def ygb_validation(R, precision, max_steps, chunk, tol, widths=(5, 10), min_step
                 paper=[0.958, 0.993], cases=out)
 
 
+def adsorption_theory(t, r, R, D, ra, psi_inf, phi0, psi0=0.0):
+    """Eqs 29 and 30 of Sec 3.1 (uptake onto a sphere with the source
+    j = ra psi_inf phi, no desorption), with m = ra psi_inf / D, a = sqrt(pi D),
+    eta = a (1 + R m) / R. Readings: D is the bulk diffusivity, and the
+    denominator of eq 29 is 1 + eta sqrt(t) (the printed one lacks the 1/R that
+    makes it dimensionless; with it, eq 30 is the time integral of eq 29 at
+    r = R). Returns (psi / psi_inf, phi / phi0 at the radii r)."""
+    from scipy.special import erfc
+
+    m = ra * psi_inf / D
+    a = np.sqrt(np.pi * D)
+    eta = a * (1.0 + R * m) / R
+    st = np.sqrt(t)
+    psi = psi0 / psi_inf + ra * phi0 * (t - a * m / eta ** 3 * (eta ** 2 * t - 2.0 * eta * st + 2.0 * np.log1p(eta * st)))
+    r = np.asarray(r, dtype=np.float64)
+    if t <= 0.0:
+        return psi, np.ones_like(r)
+    phi = 1.0 - m * a * st / (1.0 + eta * st) * (R / r) * erfc((r - R) / (2.0 * np.sqrt(D * t)))
+    return psi, phi
+
+
+def adsorption_validation(R, precision, taus=(0.011, 0.022, 0.044, 0.089, 0.22, 0.55, 1.11, 3.0), samples=60):
+    """Uptake of bulk surfactant onto a stationary drop (Sec 3.1, workload
+    adsorption_3d): psi / psi_inf on the interface (mean over nodes with
+    |rhoN| <= 0.2) against eq 30, and the radial profile of phi / phi0 at the
+    paper's times tau = D_b t / R^2 against eq 29 over R + 3 <= r <= 2.5 R (the
+    half-width of the periodic cell), outside the diffuse interface."""
+    import workloads as W
+    from paper_2311_15242_amd import lbfd
+
+    say = lambda *a: print("[adsorption]", *a, file=sys.stderr, flush=True)
+    p, q = W.adsorption_3d(R=R, precision=precision)
+    D, ra, pinf, phi0 = p["Db"], p["ra"], p["psi_inf"], q["phi0_out"]
+    n = p["nx"]
+    c = q["drops"][0][0]
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    rr = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2)
+    edges = np.arange(R + 3.0, 2.5 * R + 1e-9, 1.0)
+    mids = 0.5 * (edges[:-1] + edges[1:])
+    shell = np.digitize(rr.ravel(), edges) - 1
+    inb = (shell >= 0) & (shell < mids.size)
+    counts = np.bincount(shell[inb], minlength=mids.size)
+    s = lbfd.Solver(p).init_fields(q)
+    t_end = int(round(max(taus) * R * R / D))
+    marks = sorted(set([int(round(tau * R * R / D)) for tau in taus] +
+                       [int(round(t_end * (i + 1) / samples)) for i in range(samples)]))
+    hist, prof = [], []
+    t0 = time.time()
+    step = 0
+    for tm in marks:
+        s.step(tm - step)
+        step = tm
+        rN, psi = s.field("rhoN"), s.field("psi")
+        band = np.abs(rN) <= 0.2
+        ps = float(psi[band].mean()) / pinf
+        th, _ = adsorption_theory(float(step), [R], R, D, ra, pinf, phi0)
+        hist.append((step, ps, float(th)))
+        tau = D * step / (R * R)
+        for tt in taus:
+            if int(round(tt * R * R / D)) == step:
+                phi = s.field("phi").ravel()
+                sim = np.bincount(shell[inb], weights=phi[inb], minlength=mids.size) / np.maximum(counts, 1) / phi0
+                _, thp = adsorption_theory(float(step), mids, R, D, ra, pinf, phi0)
+                prof.append(dict(tau=tt, step=step, max_abs_err=round(float(np.abs(sim - thp).max()), 5),
+                                 r_over_R=[round(v, 3) for v in (mids / R)[::6]],
+                                 sim=[round(float(v), 4) for v in sim[::6]],
+                                 theory=[round(float(v), 4) for v in thp[::6]]))
+                say(f"tau={tt}: phi* max |sim - eq 29| = {prof[-1]['max_abs_err']:.4f}")
+        if len(hist) % 10 == 0:
+            say(f"step {step}/{t_end} (tau {tau:.3f}): psi/psi_inf {ps:.5f}, eq 30 {float(th):.5f} "
+                f"({time.time() - t0:.1f} s)")
+    ob = s.observables()
+    s.close()
+    h = np.array(hist)
+    taus_h = D * h[:, 0] / (R * R)
+    sel = taus_h >= 0.1
+    rel = np.abs(h[sel, 1] - h[sel, 2]) / h[sel, 2]
+    pick = lambda tt: h[np.argmin(np.abs(taus_h - tt))]
+    return dict(workload=f"adsorption onto a stationary drop, R={R}, periodic {n}^3 cube, {precision}",
+                status=ob["status"], steps=step, seconds=round(time.time() - t0, 1),
+                psi_max_rel_err_tau_ge_0p1=round(float(rel.max()), 4),
+                psi=[dict(tau=tt, sim=round(float(pick(tt)[1]), 6), eq30=round(float(pick(tt)[2]), 6))
+                     for tt in (0.1, 0.5, 1.0, 2.0, 3.0)],
+                phi_profiles=prof)
+
+
 def cpu_baseline(p, q, budget_s):
     """The oracle as it stands, timed on the host cores: whole steps of the same
     workload (FP64), as many as fit the time budget (at least one)."""
@@ -616,6 +702,9 @@ def main():
     ap.add_argument("--ygb-tol", type=float, default=1e-3)
     ap.add_argument("--ygb-widths", default="5,10", help="box widths L_x = L_y in units of R")
     ap.add_argument("--ygb-min-steps", type=int, default=0)
+    ap.add_argument("--validate-adsorption", type=int, default=0, metavar="R",
+                    help="uptake onto a stationary 3-D drop of radius R (Sec 3.1) against eqs 29 and 30")
+    ap.add_argument("--adsorption-precision", default="fp64")
     ap.add_argument("--sg-size", type=int, default=256)
     ap.add_argument("--sg-snapshots", type=int, default=16)
     ap.add_argument("--sg-tiles", type=int, default=64)
@@ -652,6 +741,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_calibration_bytes=n * 4, repeats=5)))
+        return
+    if args.validate_adsorption:
+        print(json.dumps(adsorption_validation(args.validate_adsorption, args.adsorption_precision)), flush=True)
         return
     if args.validate_ygb:
         widths = tuple(float(c) for c in args.ygb_widths.split(","))

@@ -147,6 +147,27 @@ def bubble_rise(nx=128, ny=128, nz=384, radius=16.0, Eo=10.0, Mo=0.1, Bi=1.0,
 
 
 # ----------------------------------------------------------------------------
+# Adsorption onto a stationary 3-D droplet (Sec 3.1). The paper simulates one
+# octant of a 5R cube with symmetry planes through the drop centre and periodic
+# far faces; mirror planes at 0 and periodicity 5R place a drop every 5R, so the
+# same problem is a whole drop at the centre of a periodic 5R cube (8 times the
+# nodes, no symmetry boundary). Both fluids of density 1 and viscosity 0.1,
+# sigma0 = 0.1, E0 = 0.5, Ds = Db = 0.1, the adsorption-only source
+# j = ra psi_inf phi with ra = 0.2 (source_mode = 1), psi0 = 0, phi0 = 0.0005
+# in the blue fluid and 0 in the drop; psi_inf = 1 (not given in the paper).
+# ----------------------------------------------------------------------------
+def adsorption_3d(R=30, precision="fp64", **over):
+    n = 5 * R
+    params = dict(lattice=D3Q19, nx=n, ny=n, nz=n, bc=[PERIODIC, PERIODIC, PERIODIC],
+                  rhoR0=1.0, rhoB0=1.0, muR0=0.1, muB0=0.1, sigma0=0.1, E0=0.5, psi_inf=1.0,
+                  Ds=0.1, Db=0.1, ra=0.2, rd=0.0, source_mode=1, precision=precision)
+    params.update(over)
+    c = (n - 1) / 2.0
+    init = dict(drops=[(c, c, c, float(R))], width=3.0, psi0=0.0, phi0_out=0.0005, phi0_in=0.0)
+    return make(params, init)
+
+
+# ----------------------------------------------------------------------------
 # Droplet migration in an imposed surfactant gradient (Sec 3.2): a red drop of
 # radius R at the centre of a (w R) x (w R) x 10R box with walls in x and y and
 # periodic z; both fluids of density 1 and viscosity 0.1, sigma0 = 0.001,
