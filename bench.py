@@ -463,6 +463,82 @@ def adsorption_validation(R, precision, taus=(0.011, 0.022, 0.044, 0.089, 0.22, 
                 phi_profiles=prof)
 
 
+def retardation_study(R, precision, tau_eo1=25.0, tau_eo10=40.0, buoyancy_ref=1):
+    """Surfactant retardation of the rising bubble (Sec 3.4, 2R/L_x = 0.4,
+    5R x 5R x 10R): Eo = 1 clean against surfactant-laden (Bi = 10), and Eo = 10
+    clean against Bi = 0.5, 1 and 10, with the other groups of the paper (Mo =
+    0.1, E0 = 0.5, Pe = 10, k = 1, x_in = 0). The paper prints no numbers for
+    these cases, only orderings, which are checked here: the surfactant slows
+    the bubble, at Eo = 1 its velocity first rises and then falls to a lower
+    steady value, at Eo = 10 the Reynolds number grows with Bi and the
+    retardation is weaker than at Eo = 1, the final psi_av hardly depends on
+    Bi, and with growing Bi psi_min rises while psi_max falls. Times in
+    tau = t / sqrt(2R/g)."""
+    import workloads as W
+    from paper_2311_15242_amd import lbfd
+
+    say = lambda *a: print("[retardation]", *a, file=sys.stderr, flush=True)
+    cases = [("Eo1 clean", 1.0, None, tau_eo1), ("Eo1 Bi10", 1.0, 10.0, tau_eo1),
+             ("Eo10 clean", 10.0, None, tau_eo10), ("Eo10 Bi0.5", 10.0, 0.5, tau_eo10),
+             ("Eo10 Bi1", 10.0, 1.0, tau_eo10), ("Eo10 Bi10", 10.0, 10.0, tau_eo10)]
+    out = {}
+    for name, Eo, Bi, tau_end in cases:
+        p, q = W.bubble_rise(nx=5 * R, ny=5 * R, nz=10 * R, radius=float(R), Eo=Eo, Mo=0.1,
+                             Bi=Bi if Bi is not None else 1.0, clean=Bi is None, precision=precision,
+                             buoyancy_ref=buoyancy_ref)
+        g = -p["gravity"][2]
+        drho = p["rhoB0"] - p["rhoR0"]
+        muB, muR = p["muB0"], p["muR0"]
+        u_th = (2.0 / 3.0) * g * drho * R * R / muB * (muB + muR) / (2.0 * muB + 3.0 * muR)
+        t_ref = np.sqrt(2.0 * R / g)
+        n_steps = int(round(tau_end * t_ref))
+        chunk = max(1, n_steps // 200)
+        s = lbfd.Solver(p).init_fields(q)
+        t0 = time.time()
+        hist = []
+        step = 0
+        while step < n_steps:
+            s.step(chunk)
+            step += chunk
+            ob = s.observables()
+            hist.append((step / t_ref, ob["velocity"][2], ob["psi_av"], ob["psi_min"], ob["psi_max"]))
+            if len(hist) % 40 == 0:
+                say(f"{name}: tau {step / t_ref:.1f}/{tau_end}, U/U_th {ob['velocity'][2] / u_th:.4f} "
+                    f"({time.time() - t0:.1f} s)")
+        if s.observables()["status"] != 0:
+            raise RuntimeError(f"{name}: status {s.observables()['status']}")
+        s.close()
+        h = np.array(hist)
+        tail = h[h[:, 0] >= 0.9 * tau_end]
+        u_end = float(tail[:, 1].mean())
+        ipk = int(np.argmax(h[:, 1]))
+        out[name] = dict(u_over_uth=round(u_end / u_th, 4), re=round(2.0 * p["rhoB0"] * u_end * R / muB, 3),
+                         peak_u_over_uth=round(float(h[ipk, 1]) / u_th, 4), peak_tau=round(float(h[ipk, 0]), 2),
+                         psi_av=round(float(tail[:, 2].mean()), 5), psi_min=round(float(tail[:, 3].mean()), 5),
+                         psi_max=round(float(tail[:, 4].mean()), 5), steps=step, seconds=round(time.time() - t0, 1),
+                         u_history=[[round(float(a), 2), round(float(b) / u_th, 4)] for a, b in h[::20, :2]])
+        say(f"{name}: U/U_th {out[name]['u_over_uth']}, Re {out[name]['re']}, peak {out[name]['peak_u_over_uth']} "
+            f"at tau {out[name]['peak_tau']}, psi_av {out[name]['psi_av']}")
+    c1, s1 = out["Eo1 clean"], out["Eo1 Bi10"]
+    c10 = out["Eo10 clean"]
+    b = [out["Eo10 Bi0.5"], out["Eo10 Bi1"], out["Eo10 Bi10"]]
+    ret1 = 1.0 - s1["re"] / c1["re"]
+    ret10 = 1.0 - b[2]["re"] / c10["re"]
+    checks = dict(
+        eo1_surfactant_slower=s1["re"] < c1["re"],
+        eo1_rises_then_falls=s1["peak_u_over_uth"] > s1["u_over_uth"] * 1.01,
+        eo10_surfactant_slower=all(x["re"] < c10["re"] for x in b),
+        eo10_re_grows_with_bi=b[0]["re"] < b[1]["re"] < b[2]["re"],
+        weaker_at_eo10=ret10 < ret1,
+        psi_av_spread_over_bi=round((max(x["psi_av"] for x in b) - min(x["psi_av"] for x in b)) /
+                                    max(x["psi_av"] for x in b), 4),
+        psi_min_grows_with_bi=b[0]["psi_min"] < b[1]["psi_min"] < b[2]["psi_min"],
+        psi_max_falls_with_bi=b[0]["psi_max"] > b[1]["psi_max"] > b[2]["psi_max"])
+    return dict(workload=f"surfactant retardation of the rising bubble, R={R}, 2R/L_x=0.4, {precision}, "
+                         f"buoyancy_ref={buoyancy_ref}",
+                retardation_eo1=round(ret1, 4), retardation_eo10_bi10=round(ret10, 4), checks=checks, cases=out)
+
+
 def cpu_baseline(p, q, budget_s):
     """The oracle as it stands, timed on the host cores: whole steps of the same
     workload (FP64), as many as fit the time budget (at least one)."""
@@ -705,6 +781,9 @@ def main():
     ap.add_argument("--validate-adsorption", type=int, default=0, metavar="R",
                     help="uptake onto a stationary 3-D drop of radius R (Sec 3.1) against eqs 29 and 30")
     ap.add_argument("--adsorption-precision", default="fp64")
+    ap.add_argument("--validate-retardation", type=int, default=0, metavar="R",
+                    help="surfactant retardation of the rising bubble at radius R (Sec 3.4 orderings)")
+    ap.add_argument("--retardation-precision", default="fp32")
     ap.add_argument("--sg-size", type=int, default=256)
     ap.add_argument("--sg-snapshots", type=int, default=16)
     ap.add_argument("--sg-tiles", type=int, default=64)
@@ -741,6 +820,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_calibration_bytes=n * 4, repeats=5)))
+        return
+    if args.validate_retardation:
+        print(json.dumps(retardation_study(args.validate_retardation, args.retardation_precision)), flush=True)
         return
     if args.validate_adsorption:
         print(json.dumps(adsorption_validation(args.validate_adsorption, args.adsorption_precision)), flush=True)
