@@ -596,12 +596,12 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
         R as, c[3] = {0, 0, 0};
         if constexpr (P::DEV) {
             // decode with the reference of the node the population left
-            const DescDev A = ld((const DescDev *)k.fld.desc, src);
+            const DescDev A = ldu((const DescDev *)k.fld.desc, src);
             R us[3] = {0, 0, 0};
             c[0] = h_lo(A.c01);
             c[1] = h_hi(A.c01);
             if constexpr (D == 3) {
-                const uint32_t Bv = ld((const uint32_t *)desc_dev_b(k), src);
+                const uint32_t Bv = ldu((const uint32_t *)desc_dev_b(k), src);
                 c[2] = h_lo(A.c2u0);
                 us[0] = h_hi(A.c2u0);
                 us[1] = h_lo(Bv);
@@ -613,7 +613,7 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
             as = A.a;
             fq += reference<LAT, R>(k, q, R(1), A.rho, as, us);
         } else {
-            const V4<R> A = ld((const V4<R> *)k.fld.desc, src);
+            const V4<R> A = ldu((const V4<R> *)k.fld.desc, src);
             as = A.x;
             c[0] = A.y;
             c[1] = A.z;

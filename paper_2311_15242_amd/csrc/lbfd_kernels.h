@@ -242,7 +242,10 @@ template <class R> __device__ __forceinline__ Node node_at(const KP<R> &k, int t
     Node n;
     const int bx = t % k.gx, r = t / k.gx;
     n.x = bx * blockDim.x + threadIdx.x;
-    n.y = (r % k.gy) * blockDim.y + threadIdx.y;
+    // node launches use 64 x 4 workgroups, so a wavefront is one row of 64 x: its y
+    // (and z) are the same in every lane, and held in scalar registers the
+    // neighbourhood arithmetic along y and z runs once per wavefront
+    n.y = __builtin_amdgcn_readfirstlane((r % k.gy) * (int)blockDim.y + (int)threadIdx.y);
     n.z = r / k.gy;
     n.ok = n.x < k.nx && n.y < k.ny;
     return n;
@@ -445,8 +448,8 @@ __device__ __forceinline__ R lat_deriv(const Nbhd &b, const R *chi, uint32_t n, 
     for (int i = 1; i < L::Q; ++i) {
         if (L::OPP[i] < i || L::E[i][a] == 0) continue;
         const int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
-        R vp = ld(chi, n + (uint32_t)nb_delta(b, ex, ey, ez));
-        R vm = ld(chi, n + (uint32_t)nb_delta(b, -ex, -ey, -ez));
+        R vp = ldu(chi, n + (uint32_t)nb_delta(b, ex, ey, ez));
+        R vm = ldu(chi, n + (uint32_t)nb_delta(b, -ex, -ey, -ez));
         if (odd_axis >= 0) {
             const int eo = L::E[i][odd_axis];
             if (nb_wall_axis(b, odd_axis, eo)) vp = -vp;
@@ -484,7 +487,7 @@ __device__ __forceinline__ uint32_t source_of(const Nbhd &b, uint32_t n, int j, 
     using L = Lat<LAT>;
     const int ex = -L::E[j][0], ey = -L::E[j][1], ez = -L::E[j][2];
     bounced = nb_wall(b, ex, ey, ez);
-    return bounced ? n : n + (uint32_t)nb_delta(b, ex, ey, ez);
+    return n + (bounced ? 0u : (uint32_t)nb_delta(b, ex, ey, ez));
 }
 
 // Moments of a second-order polynomial in e_i weighted by w_i:
