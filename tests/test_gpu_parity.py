@@ -404,3 +404,31 @@ def test_imposed_gradient_migration(lbfd, prec, tol_u):
     assert np.abs(s.field("psi") - ramp).max() <= (0.0 if prec == "fp64" else 1e-7)
     vz = s.observables()["velocity"][2]
     assert vz > 0 and vz == pytest.approx(o.observables()["velocity"][2], rel=5 * tol_u)
+
+
+def test_slow_shear_flow_low_precision_modes(lbfd):
+    """A slow shear flow between half-way walls moving at -/+1e-4 (D3Q19,
+    4 x 16 x 4, one fluid, FD off) to its steady state in each storage mode,
+    against the FP64 run of the same library and the linear Couette profile.
+    The stored non-equilibrium moments (the shear stress) are tiny and their
+    per-step changes far below a BF16 spacing, the regime where
+    round-to-nearest storage stagnates; the stochastically rounded BF16
+    deviations must follow FP64 to 1 %."""
+    H, uw = 16, 1e-4
+    base = dict(lattice=W.D3Q19, nx=4, ny=H, nz=4, bc=[W.PERIODIC, W.WALL, W.PERIODIC], sigma0=0.0, E0=0.0,
+                fd_enable=0, rhoR0=1.0, rhoB0=1.0,
+                wall_u=[[0, 0, 0], [0, 0, 0], [-uw, 0, 0], [uw, 0, 0], [0, 0, 0], [0, 0, 0]])
+    exact = uw * (2.0 * (np.arange(H) + 0.5) / H - 1.0)
+    prof = {}
+    for prec in ("fp64", "fp32", "bf16dev"):
+        say(f"[slow shear {prec}]")
+        p, q = W.make(dict(base, precision=prec), dict(drops=[], width=3.0))
+        s = lbfd.Solver(p).init_fields(q).step(6000)
+        prof[prec] = s.field("u")[0].mean(axis=(0, 2))
+        assert s.observables()["status"] == 0
+    ref = prof["fp64"]
+    assert np.abs(ref - exact).max() <= 1e-3 * uw, (ref, exact)
+    for prec in ("fp32", "bf16dev"):
+        err = float(np.abs(prof[prec] - ref).max() / uw)
+        say(f"{prec}: max |u - u_fp64| / u_w = {err:.2e}")
+        assert err < 0.01, (prec, err)
