@@ -513,15 +513,10 @@ template <int LAT, class P> __device__ __forceinline__ void collide_body(const K
     } else {
         st((V4<R> *)k.fld.desc, n, V4<R>{a, cf * nv[0], cf * nv[1], cf * nv[2]});
     }
-    // propagation with periodic wrap or half-way bounce-back
+    // propagation with periodic wrap or half-way bounce-back of f_dag_i = (M^-1 m*)_i
+    // (deviation modes: minus ref_i)
     Dither dz(n, P::DEV ? k.fld.sc->tick : 0u, 1u);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        // f_dag_i = (M^-1 m*)_i (deviation modes: minus ref_i)
-        R v = 0;
-#pragma unroll
-        for (int r = 0; r < Q; ++r)
-            if (L::MINV[i][r] != 0.0) v += R(L::MINV[i][r]) * m[r];
+    auto emit = [&](const int i, R v) {
         const int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
         // the first wall axis the population crosses reflects it, with Ladd's moving-wall
         // term -6 w_i rho (e_i . u_w) (a per-wall table); every index is a compile-time constant
@@ -549,6 +544,27 @@ template <int LAT, class P> __device__ __forceinline__ void collide_body(const K
                                 : (uint32_t)(i - lo) * N32 + n + (uint32_t)nb_delta(nb, ex, ey, ez);
         if constexpr (P::DEV) stu(fout + lo * N, dst, from_real_sr<S>(v, dz.next()));
         else stu(fout + lo * N, dst, (S)v);
+    };
+    {
+        R v = 0;
+#pragma unroll
+        for (int r = 0; r < Q; ++r)
+            if (L::MINV[0][r] != 0.0) v += R(L::MINV[0][r]) * m[r];
+        emit(0, v);
+    }
+    // opposite pairs: the even rows of M^-1 m* are shared, the odd ones change sign
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if (L::OPP[i] < i) continue;
+        R ev = 0, od = 0;
+#pragma unroll
+        for (int r = 0; r < Q; ++r) {
+            if (L::MINV[i][r] == 0.0) continue;
+            if (row_even<LAT>(r)) ev += R(L::MINV[i][r]) * m[r];
+            else od += R(L::MINV[i][r]) * m[r];
+        }
+        emit(i, ev + od);
+        emit(L::OPP[i], ev - od);
     }
 }
 template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<typename P::R> k)
@@ -587,8 +603,9 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
 #pragma unroll
         for (int r = 0; r < Q; ++r) m[r] = 0;
     }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    // one arrival: its population (deviation modes: plus the reference of the node it
+    // left) and its recoloured share of rho^R, rho^B
+    auto arrive = [&](const int q) -> R {
         bool bo;
         const uint32_t src = source_of<LAT>(nb, n, q, bo);
         const R sgn = bo ? R(-1) : R(1);   // a reflected arrival left its source along -e_q
@@ -626,12 +643,30 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
         R r = wgt * ec;
         rR += as * fq + r;
         rB += (R(1) - as) * fq - r;
-#pragma unroll
-        for (int d = 0; d < D; ++d) j[d] += fq * R(L::E[q][d]);
+        return fq;
+    };
+    {
+        const R f0 = arrive(0);
         if constexpr (P::DEV) {
 #pragma unroll
             for (int r2 = 0; r2 < Q; ++r2)
-                if (L::M[r2][q] != 0 && !conserved_row<LAT>(r2)) m[r2] += R(L::M[r2][q]) * fq;
+                if (L::M[r2][0] != 0 && !conserved_row<LAT>(r2)) m[r2] += R(L::M[r2][0]) * f0;
+        }
+    }
+    // opposite pairs: momentum and the odd moment rows take f_q - f_opp(q), the even
+    // rows f_q + f_opp(q)
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        if (L::OPP[q] < q) continue;
+        const R fa = arrive(q), fb = arrive(L::OPP[q]);
+        const R sp = fa + fb, sm = fa - fb;
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            if (L::E[q][d] != 0) j[d] += R(L::E[q][d]) * sm;
+        if constexpr (P::DEV) {
+#pragma unroll
+            for (int r2 = 0; r2 < Q; ++r2)
+                if (L::M[r2][q] != 0 && !conserved_row<LAT>(r2)) m[r2] += R(L::M[r2][q]) * (row_even<LAT>(r2) ? sp : sm);
         }
     }
     R *mac = k.fld.mac[1 - sa.lev];

@@ -117,6 +117,30 @@ template <int LAT> __host__ __device__ constexpr int state_slot(int r)
     return s;
 }
 
+// Every moment row is a polynomial of one parity in e: M[r][opp(i)] = +M[r][i]
+// for all i (even row) or -M[r][i] (odd row), and the columns of M^-1 follow
+// the same parity. Opposite populations therefore enter an even row through
+// f_i + f_opp(i) and an odd row through f_i - f_opp(i), which halves the
+// products of the transforms.
+template <int LAT> __host__ __device__ constexpr bool row_even(int r)
+{
+    using L = Lat<LAT>;
+    for (int i = 0; i < L::Q; ++i)
+        if (L::M[r][L::OPP[i]] != L::M[r][i]) return false;
+    return true;
+}
+template <int LAT> constexpr bool rows_have_parity()
+{
+    using L = Lat<LAT>;
+    for (int r = 0; r < L::Q; ++r) {
+        const double sg = row_even<LAT>(r) ? 1.0 : -1.0;
+        for (int i = 0; i < L::Q; ++i)
+            if (L::M[r][L::OPP[i]] != sg * L::M[r][i] || L::MINV[L::OPP[i]][r] != sg * L::MINV[i][r]) return false;
+    }
+    return true;
+}
+static_assert(rows_have_parity<0>() && rows_have_parity<1>(), "moment rows without a definite parity");
+
 // ------------------------------------------------------------------ parameters
 
 constexpr int QMAX = 19;
