@@ -539,6 +539,100 @@ def retardation_study(R, precision, tau_eo1=25.0, tau_eo10=40.0, buoyancy_ref=1)
                 retardation_eo1=round(ret1, 4), retardation_eo10_bi10=round(ret10, 4), checks=checks, cases=out)
 
 
+def radial_uptake(R, R_out, D, ra, rd, psi_inf, phi0, times, source_mode=0, nr=800, dt=0.5, dt_rel=0.0):
+    """Sharp-interface reference of uptake onto a circular drop (the 2-D
+    analogue of eq 30): bulk diffusion d phi/dt = D r^-1 d/dr(r d phi/dr) on
+    R < r < R_out with no flux at R_out, the flux D d phi/dr = j into the
+    interface at r = R, and d psi/dt = j, with j of eq 22 (source_mode 0) or
+    ra psi_inf phi (1). Finite volumes in r (the first cell's value stands for
+    the surface value) and Crank-Nicolson in t for phi and psi together; the
+    product phi (psi_inf - psi) of eq 22 is linearised about the mid-step psi,
+    re-estimated three times per step. The interface takes exactly what the
+    bulk loses, so R psi + sum r dr phi is conserved. Time steps of
+    max(dt, dt_rel t). Returns psi at the given times and the final profile
+    (r, phi)."""
+    from scipy.linalg import solve_banded
+
+    dr = (R_out - R) / nr
+    rc = R + (np.arange(nr) + 0.5) * dr
+    rf = R + np.arange(nr + 1) * dr
+    vol = rc * dr
+    cf = D * rf / dr                      # face conductances per unit angle
+    cf[0] = 0.0
+    cf[-1] = 0.0
+    # (L phi)_i = di_i phi_i + up_i phi_{i+1} + lo_i phi_{i-1}: face fluxes into cell i
+    lo = np.zeros(nr)
+    up = np.zeros(nr)
+    di = np.zeros(nr)
+    di[:-1] -= cf[1:-1]
+    up[:-1] += cf[1:-1]
+    di[1:] -= cf[1:-1]
+    lo[1:] += cf[1:-1]
+    phi = np.full(nr, float(phi0))
+    psi = 0.0
+    out = []
+    t = 0.0
+    for target in sorted(times):
+        while target - t > 1e-12:
+            h = min(max(dt, dt_rel * t), target - t)
+            Lphi = di * phi + np.concatenate([[0.0], lo[1:] * phi[:-1]]) + np.concatenate([up[:-1] * phi[1:], [0.0]])
+            psi_mid = psi
+            for _ in range(3):
+                # j = (a phi_mid - rd psi^n) / (1 + c) with c = h rd / 2 and phi_mid the
+                # mean of the old and new surface values (psi of eq 22 at the mid step)
+                if source_mode == 1:
+                    a, c, b = ra * psi_inf, 0.0, 0.0
+                else:
+                    a, c, b = ra * (psi_inf - psi_mid), 0.5 * h * rd, rd * psi
+                alpha, beta = a / (1.0 + c), -b / (1.0 + c)
+                A = np.zeros((3, nr))
+                A[0, 1:] = -0.5 * up[:-1]
+                A[1, :] = vol / h - 0.5 * di
+                A[2, :-1] = -0.5 * lo[1:]
+                A[1, 0] += 0.5 * R * alpha
+                rhs = vol / h * phi + 0.5 * Lphi
+                rhs[0] += -0.5 * R * alpha * phi[0] - R * beta
+                new = solve_banded((1, 1), A, rhs)
+                j = alpha * 0.5 * (phi[0] + new[0]) + beta
+                psi_new = psi + h * j
+                psi_mid = 0.5 * (psi + psi_new)
+            phi, psi = new, psi_new
+            t += h
+        out.append(psi)
+    return np.array(out), rc, phi
+
+
+def uptake_validation(precision="fp64", times=(100, 250, 500, 1000, 2000, 5000, 10000, 20000, 50000, 100000)):
+    """The adsorption workload (droplet128: D2Q9 128 x 128 periodic, R = 25,
+    Langmuir kinetics of eq 22) against the sharp-interface reference
+    radial_uptake on the disk of the box's area: the interface concentration
+    psi_av = sum G psi / sum G of the solver at the given times."""
+    import workloads as W
+    from paper_2311_15242_amd import lbfd
+
+    say = lambda *a: print("[uptake]", *a, file=sys.stderr, flush=True)
+    p, q = W.droplet_adsorption(precision=precision)
+    R = q["drops"][0][3]
+    R_out = p["nx"] / np.sqrt(np.pi)
+    s = lbfd.Solver(p).init_fields(q)
+    t0 = time.time()
+    sim = []
+    step = 0
+    for t in times:
+        s.step(t - step)
+        step = t
+        sim.append(s.observables()["psi_av"])
+        say(f"t={t}: psi_av {sim[-1]:.6f} ({time.time() - t0:.1f} s)")
+    status = s.observables()["status"]
+    s.close()
+    ref, _, _ = radial_uptake(R, R_out, p["Db"], p["ra"], p["rd"], p["psi_inf"], q["phi0_out"],
+                              [float(t) for t in times], source_mode=p["source_mode"], dt_rel=2e-3)
+    rel = [round(float(a / b - 1.0), 4) for a, b in zip(sim, ref)]
+    return dict(workload=f"uptake onto the droplet128 drop (D2Q9 128^2, R={R}), {precision}", status=status,
+                seconds=round(time.time() - t0, 1), times=list(times), psi_sim=[round(float(v), 6) for v in sim],
+                psi_sharp=[round(float(v), 6) for v in ref], rel_diff=rel)
+
+
 def cpu_baseline(p, q, budget_s):
     """The oracle as it stands, timed on the host cores: whole steps of the same
     workload (FP64), as many as fit the time budget (at least one)."""
@@ -784,6 +878,8 @@ def main():
     ap.add_argument("--validate-retardation", type=int, default=0, metavar="R",
                     help="surfactant retardation of the rising bubble at radius R (Sec 3.4 orderings)")
     ap.add_argument("--retardation-precision", default="fp32")
+    ap.add_argument("--validate-uptake", action="store_true",
+                    help="the adsorption workload against the sharp-interface radial reference")
     ap.add_argument("--sg-size", type=int, default=256)
     ap.add_argument("--sg-snapshots", type=int, default=16)
     ap.add_argument("--sg-tiles", type=int, default=64)
@@ -820,6 +916,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_calibration_bytes=n * 4, repeats=5)))
+        return
+    if args.validate_uptake:
+        print(json.dumps(uptake_validation()), flush=True)
         return
     if args.validate_retardation:
         print(json.dumps(retardation_study(args.validate_retardation, args.retardation_precision)), flush=True)
