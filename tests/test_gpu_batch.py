@@ -42,7 +42,8 @@ def walled_box_3d(prec, nx=23, ny=21, nz=19):
 def instances_3d(prec):
     return [walled_box_3d(prec),
             W.bubble_rise(nx=24, ny=20, nz=32, radius=6.0, precision=prec),
-            W.make(dict(lattice=W.D3Q19, nx=20, ny=20, nz=20, sigma0=0.01, E0=0.5, Ds=0.05, Db=0.05, precision=prec),
+            W.make(dict(lattice=W.D3Q19, nx=20, ny=20, nz=20, sigma0=0.01, E0=0.5, Ds=0.05, Db=0.05, eos_mode=1,
+                        precision=prec),
                    dict(drops=[(9.5, 9.5, 9.5, 6.0)], width=3.0, psi0=0.1, phi0_out=0.05, phi0_in=0.0))]
 
 
@@ -69,7 +70,8 @@ def test_batch_fp64_matches_oracle(lbfd, case, steps):
     """Uneven instances in one FP64 batch, each against its own oracle run: four
     2-D bubble columns of the sweep's mix at a quarter of their size (ragged
     tiles, different Eo and Bi), and three 3-D boxes (walls on every axis with
-    moving walls, a walled column, a periodic box)."""
+    moving walls, a walled column, a periodic box with the linear tension law of
+    Sec 3.2)."""
     inst = (W.batch_instances(W.load_manifest()[:4], precision="fp64", scale=0.25) if case.startswith("manifest")
             else instances_3d("fp64"))
     say(f"[batch fp64 vs oracle] {case}: " + ", ".join(f"{p['nx']}x{p['ny']}x{p['nz']}" for p, _ in inst))
@@ -89,11 +91,12 @@ def test_batch_fp64_matches_oracle(lbfd, case, steps):
 
 @pytest.mark.parametrize("case,prec,steps", [("manifest2d_8", "fp64", 20), ("manifest2d_8", "bf16dev", 40),
                                              ("mixed3d", "fp32", 12), ("mixed3d", "fp16dev", 12),
-                                             ("single_tiny", "fp64", 10)])
+                                             ("mixed3d", "bf16dev", 12), ("single_tiny", "fp64", 10)])
 def test_batch_identical_to_single(lbfd, case, prec, steps):
     """Each instance of a batch is bit-identical to the same instance stepped
     alone: full-size 2-D columns of the sweep (the first eight draws), the 3-D
-    boxes in the reduced-precision modes, and a batch of one tiny grid."""
+    boxes in the reduced-precision modes (BF16: the stochastic rounding draws
+    the same bits in a batch as alone), and a batch of one tiny grid."""
     if case == "manifest2d_8":
         inst = W.batch_instances(W.load_manifest()[:8], precision=prec)
     elif case == "mixed3d":
