@@ -35,6 +35,7 @@
 namespace lbfd {
 
 constexpr int BX = 64, BY = 4;          // one wavefront spans 64 consecutive x
+static_assert(BX == 64, "node kernels hold y in scalar registers: a wavefront must be one row");
 constexpr int NRED = 19;                 // observable partial sums per block
 constexpr int TOTAL_BLOCKS = 1024;       // most workgroups of the total-surfactant sum
 constexpr int TOTAL_NODES = 4096;        // nodes per workgroup of that sum below the cap
