@@ -937,8 +937,8 @@ def main():
                                          args.rise_chunk, args.rise_tol, cases, args.rise_buoyancy_ref)), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              f"(the solver runs on a single MI355X; multi-GPU sharding is design only).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(the solver runs on a single MI355X; sharding over several GPUs is not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import torch
