@@ -18,6 +18,13 @@
  * lexicographic SOR. Where the paper is silent or garbled the choice made is
  * marked "Reading:" in place.
  *
+ * Pins: the tests check this library against closed forms, invariants, a
+ * separately written NumPy brute force and exact dense solves. Parity partly
+ * pinned: rows 16-18 of the 3-D moment equilibrium (eq 40) beyond u = 0
+ * (pinned at u = 0 and by covariance under the lattice symmetries only).
+ * Parity unpinned: the form of the rescaling of the total surfactant (Sec 2.2
+ * cites it without giving it; the single factor used here is a reading).
+ *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math).
  */
 #include <math.h>

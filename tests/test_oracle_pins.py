@@ -92,6 +92,47 @@ def test_moment_equilibrium_reduces_to_textbook(lat, rows):
 
 
 @pytest.mark.parametrize("lat", [W.D2Q9, W.D3Q19])
+@pytest.mark.parametrize("alpha", [None, 0.2])
+def test_moment_equilibrium_is_covariant_under_the_lattice_symmetries(lat, alpha):
+    """The moment equilibria of eqs 37/40 (every row, both colours, standard and
+    shifted sound speeds) transform under each of the lattice's 8 (2-D) or 48
+    (3-D) axis permutations and reflections P as the moments themselves:
+    m_eq(rho, P u) = M Pi M^-1 m_eq(rho, u), with Pi the permutation of the
+    populations that P induces. A wrong index, sign or transposed component in
+    any row, the 3-D rows 16-18 included, breaks this."""
+    import itertools
+
+    over = {} if alpha is None else dict(alphaR=alpha, rhoR0=0.2)
+    o = oracle.Oracle(tiny(lat, **over))
+    L = o.lattice()
+    D = L["D"]
+    e = np.rint(L["e"][:, :D]).astype(int)
+    M = L["M"]
+    Minv = np.linalg.inv(M)
+    Q = e.shape[0]
+    rng = np.random.default_rng(3)
+    count = 0
+    for perm in itertools.permutations(range(D)):
+        for signs in itertools.product((1, -1), repeat=D):
+            P = np.zeros((D, D))
+            for a in range(D):
+                P[a, perm[a]] = signs[a]
+            pe = e @ P.T.astype(int)
+            Pi = np.zeros((Q, Q))
+            for i in range(Q):
+                j = [jj for jj in range(Q) if (e[jj] == pe[i]).all()]
+                assert len(j) == 1
+                Pi[j[0], i] = 1.0
+            T = M @ Pi @ Minv
+            for k in (0, 1):
+                rho = rng.uniform(0.5, 2.0)
+                u = rng.uniform(-0.05, 0.05, D)
+                assert np.abs(o.moment_eq(k, rho, P @ u) - T @ o.moment_eq(k, rho, u)).max() < 1e-13
+            count += 1
+    assert count == (8 if D == 2 else 48)
+
+
+@pytest.mark.parametrize("lat", [W.D2Q9, W.D3Q19])
 def test_rest_populations_positive_unequal_sound_speeds(lat):
     """With density ratio 10 (eq 42) both colours' rest populations are positive
     and both pure phases have the same pressure rho^k0 (cs^k)^2."""
