@@ -592,12 +592,62 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
     using L = Lat<LAT>;
     constexpr int Q = L::Q, D = L::D;
     Node nd = node_at(k, tile);
+    // Deviation modes: the descriptors of the tile and its one-node halo (every
+    // source an arrival can come from) staged in LDS, so the 19 per-node reads are
+    // LDS reads at fixed offsets instead of global gathers. Halo cells beyond a
+    // wall are never read (an arrival across a wall comes from the node itself).
+    constexpr int HX = BX + 2, HY = BY + 2, HZ = D == 3 ? 3 : 1, HN = HX * HY * HZ;
+    __shared__ DescDev sA[P::DEV ? HN : 1];
+    __shared__ uint32_t sB[(P::DEV && D == 3) ? HN : 1];
+    if constexpr (P::DEV) {
+        const int bx = tile % k.gx, rr = tile / k.gx;
+        const int ox = bx * BX - 1, oy = (rr % k.gy) * BY - 1, oz = rr / k.gy - (D == 3 ? 1 : 0);
+        const DescDev *dA = (const DescDev *)k.fld.desc;
+        const uint32_t *dB = desc_dev_b(k);
+        // every thread fetches up to HS cells, all loads issued before the LDS stores
+        constexpr int HS = (HN + BX * BY - 1) / (BX * BY);
+        const int t0 = (int)(threadIdx.x + BX * threadIdx.y);
+        DescDev va[HS];
+        uint32_t vb[HS];
+        bool have[HS];
+#pragma unroll
+        for (int it = 0; it < HS; ++it) {
+            const int h = t0 + it * BX * BY;
+            int g[3] = {ox + h % HX, oy + (h / HX) % HY, oz + h / (HX * HY)};
+            const int ext[3] = {k.nx, k.ny, k.nz};
+            bool ok = h < HN;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                if (g[a] >= 0 && g[a] < ext[a]) continue;
+                if (k.bc[a]) { ok = false; continue; }
+                if (g[a] < 0) g[a] += ext[a];
+                while (g[a] >= ext[a]) g[a] -= ext[a];
+            }
+            have[it] = ok;
+            if (ok) {
+                const uint32_t gi = (uint32_t)g[0] + (uint32_t)k.nx * ((uint32_t)g[1] + (uint32_t)k.ny * (uint32_t)(D == 3 ? g[2] : 0));
+                va[it] = ldu(dA, gi);
+                if constexpr (D == 3) vb[it] = ldu(dB, gi);
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < HS; ++it) {
+            const int h = t0 + it * BX * BY;
+            if (have[it]) {
+                sA[h] = va[it];
+                if constexpr (D == 3) sB[h] = vb[it];
+            }
+        }
+        __syncthreads();
+    }
     if (!nd.ok) return;
     const int x = nd.x, y = nd.y, z = nd.z;
     const long long N = k.N;
     const uint32_t n = node_index(k, nd);
     const S *fin = (const S *)k.fld.f[1 - sa.fc];
     const Nbhd nb = make_nbhd(k, x, y, z);
+    // halo cell of this node
+    const int hself = (int)(threadIdx.x + 1) + HX * ((int)(threadIdx.y + 1) + HY * (D == 3 ? 1 : 0));
     R rR = 0, rB = 0, j[3] = {0, 0, 0};
     R m[P::DEV ? Q : 1];
     if constexpr (P::DEV) {
@@ -608,18 +658,20 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
     // left) and its recoloured share of rho^R, rho^B
     auto arrive = [&](const int q) -> R {
         bool bo;
-        const uint32_t src = source_of<LAT>(nb, n, q, bo);
-        const R sgn = bo ? R(-1) : R(1);   // a reflected arrival left its source along -e_q
         R fq = to_real(ldu(fin + q * N, n));
         R as, c[3] = {0, 0, 0};
         if constexpr (P::DEV) {
-            // decode with the reference of the node the population left
-            const DescDev A = ldu((const DescDev *)k.fld.desc, src);
+            // decode with the reference of the node the population left (x - e_q, or
+            // the node itself across a wall)
+            const int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
+            bo = nb_wall(nb, -ex, -ey, -ez);
+            const int hs = bo ? hself : hself - ex - HX * (ey + HY * ez);
+            const DescDev A = sA[hs];
             R us[3] = {0, 0, 0};
             c[0] = h_lo(A.c01);
             c[1] = h_hi(A.c01);
             if constexpr (D == 3) {
-                const uint32_t Bv = ldu((const uint32_t *)desc_dev_b(k), src);
+                const uint32_t Bv = sB[hs];
                 c[2] = h_lo(A.c2u0);
                 us[0] = h_hi(A.c2u0);
                 us[1] = h_lo(Bv);
@@ -631,12 +683,14 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
             as = A.a;
             fq += reference<LAT, R>(k, q, R(1), A.rho, as, us);
         } else {
+            const uint32_t src = source_of<LAT>(nb, n, q, bo);
             const V4<R> A = ldu((const V4<R> *)k.fld.desc, src);
             as = A.x;
             c[0] = A.y;
             c[1] = A.z;
             c[2] = A.w;
         }
+        const R sgn = bo ? R(-1) : R(1);   // a reflected arrival left its source along -e_q
         R ec = R(L::E[q][0]) * c[0] + R(L::E[q][1]) * c[1];
         if constexpr (D == 3) ec += R(L::E[q][2]) * c[2];
         ec *= sgn;
