@@ -260,6 +260,100 @@ __global__ __launch_bounds__(256) void k_import(KP<typename P::R> k, const doubl
     k.fld.Bp[n] = Bp ? (R)Bp[n] : R(0);
 }
 
+// ============================================================== LDS halos
+
+// A 64 x 4 node tile (one plane) and its one-node halo: 66 x 6 (x 3 planes in 3-D).
+template <int D> struct Halo1 {
+    static constexpr int HX = BX + 2, HY = BY + 2, HZ = D == 3 ? 3 : 1, HN = HX * HY * HZ;
+    static constexpr int HS = (HN + BX * BY - 1) / (BX * BY);   // cells per thread
+    // halo cell of the thread's own node
+    __device__ static int self() { return (int)(threadIdx.x + 1) + HX * ((int)(threadIdx.y + 1) + HY * (D == 3 ? 1 : 0)); }
+    // offset of the neighbour at lattice offset (ex, ey, ez)
+    __host__ __device__ static constexpr int off(int ex, int ey, int ez) { return ex + HX * (ey + HY * ez); }
+};
+
+// Halo coordinate along one axis: wrapped on a periodic axis, the mirror node
+// beyond a wall (what the lattice stencils read there); cells that no node of
+// the tile reads are clamped into the grid.
+__device__ __forceinline__ int halo_coord(int g, int n, int wall)
+{
+    if (g >= 0 && g < n) return g;
+    if (wall) {
+        g = g < 0 ? -1 - g : 2 * n - 1 - g;
+        return g < 0 ? 0 : (g >= n ? n - 1 : g);
+    }
+    if (g < 0) g += n;
+    while (g >= n) g -= n;
+    return g;
+}
+
+// Stage NF node arrays of a tile and its one-node halo in LDS, a row of HX cells
+// per wavefront at a time: each lane holds one x column (lanes 0 and 1 a second
+// one), whose wrap is worked out once; the rows' y and z are uniform. Every
+// wavefront issues all of its loads before its LDS stores. The caller
+// synchronises the workgroup before reading.
+template <int LAT, class T, int NF, class R>
+__device__ __forceinline__ void stage_halo1(const KP<R> &k, int tile, const T *const *src, T (*sh)[Halo1<Lat<LAT>::D>::HN])
+{
+    constexpr int D = Lat<LAT>::D;
+    using H = Halo1<D>;
+    constexpr int NR = H::HY * H::HZ, RPW = (NR + BY - 1) / BY;   // rows, rows per wavefront
+    const int bx = tile % k.gx, rr = tile / k.gx;
+    const int ox = bx * BX - 1, oy = (rr % k.gy) * BY - 1, oz = rr / k.gy - (D == 3 ? 1 : 0);
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const int lane = (int)threadIdx.x;
+    const bool two = lane < H::HX - BX;
+    const uint32_t gx0 = (uint32_t)halo_coord(ox + lane, k.nx, k.bc[0]);
+    const uint32_t gx1 = two ? (uint32_t)halo_coord(ox + BX + lane, k.nx, k.bc[0]) : 0u;
+    T v0[RPW][NF], v1[RPW][NF];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        const int row = w + BY * i;
+        if (row >= NR) continue;
+        const int gy = halo_coord(oy + row % H::HY, k.ny, k.bc[1]);
+        const int gz = D == 3 ? halo_coord(oz + row / H::HY, k.nz, k.bc[2]) : 0;
+        const uint32_t base = (uint32_t)k.nx * ((uint32_t)gy + (uint32_t)k.ny * (uint32_t)gz);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            v0[i][f] = ldu(src[f], base + gx0);
+            if (two) v1[i][f] = ldu(src[f], base + gx1);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        const int row = w + BY * i;
+        if (row >= NR) continue;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            sh[f][row * H::HX + lane] = v0[i][f];
+            if (two) sh[f][row * H::HX + BX + lane] = v1[i][f];
+        }
+    }
+}
+
+// lat_deriv on a staged field: the same stencil, pairs and mirror signs.
+template <int LAT, class R>
+__device__ __forceinline__ R lat_deriv_lds(const Nbhd &b, const R *sh, int hself, R scl, int a, int odd_axis)
+{
+    using L = Lat<LAT>;
+    using H = Halo1<L::D>;
+    R acc = 0;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        if (L::OPP[i] < i || L::E[i][a] == 0) continue;
+        const int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
+        R vp = sh[hself + H::off(ex, ey, ez)];
+        R vm = sh[hself - H::off(ex, ey, ez)];
+        if (odd_axis >= 0) {
+            const int eo = L::E[i][odd_axis];
+            if (nb_wall_axis(b, odd_axis, eo)) vp = -vp;
+            if (nb_wall_axis(b, odd_axis, -eo)) vm = -vm;
+        }
+        acc += R(L::W[i] * L::E[i][a]) * (vp - vm);
+    }
+    return R(3) * acc * scl;
+}
+
 // ============================================================== geometry
 
 // |grad rhoN| and the regularised normal n = -grad rhoN / sqrt(|grad rhoN|^2 + eps^2)
@@ -312,13 +406,25 @@ template <int LAT, class P> __device__ __forceinline__ void force_body(const KP<
     using L = Lat<LAT>;
     constexpr int D = L::D;
     Node nd = node_at(k, tile);
+    const long long N = k.N;
+    const R *psiA = k.fld.psi[sa.pc];
+    // the normal and psi of the tile and its halo staged in LDS (FP32 arithmetic)
+    constexpr bool LDS = sizeof(R) == 4;
+    using H = Halo1<D>;
+    __shared__ R sh[LDS ? D + 1 : 1][LDS ? H::HN : 1];
+    if constexpr (LDS) {
+        const R *srcs[D + 1];
+#pragma unroll
+        for (int a = 0; a < D; ++a) srcs[a] = k.fld.nrm + a * N;
+        srcs[D] = psiA;
+        stage_halo1<LAT, R, D + 1>(k, tile, srcs, sh);
+        __syncthreads();
+    }
     if (!nd.ok) return;
     const int x = nd.x, y = nd.y, z = nd.z;
-    const long long N = k.N;
     const uint32_t n = node_index(k, nd);
     const R *mac = k.fld.mac[sa.lev];
     const R s = (R)k.fld.sc->scale;
-    const R *psiA = k.fld.psi[sa.pc];
     const Nbhd nb = make_nbhd(k, x, y, z);
     // grad rhoN = -n sqrt(|grad rhoN|^2 + eps_n^2), from the geometry kernel's n and |grad rhoN|
     const R G = ld(k.fld.G[sa.lev], n);
@@ -326,12 +432,20 @@ template <int LAT, class P> __device__ __forceinline__ void force_body(const KP<
     R g[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, nv[3] = {0, 0, 0}, kappa = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        kappa -= lat_deriv<LAT, R>(nb, k.fld.nrm + a * N, n, R(1), a, a);
-        gp[a] = lat_deriv<LAT, R>(nb, psiA, n, s, a, -1);
-        nv[a] = ld(k.fld.nrm + a * N, n);
+        if constexpr (LDS) {
+            kappa -= lat_deriv_lds<LAT, R>(nb, sh[a], H::self(), R(1), a, a);
+            gp[a] = lat_deriv_lds<LAT, R>(nb, sh[D], H::self(), s, a, -1);
+            nv[a] = sh[a][H::self()];
+        } else {
+            kappa -= lat_deriv<LAT, R>(nb, k.fld.nrm + a * N, n, R(1), a, a);
+            gp[a] = lat_deriv<LAT, R>(nb, psiA, n, s, a, -1);
+            nv[a] = ld(k.fld.nrm + a * N, n);
+        }
         g[a] = -nv[a] * den;
     }
-    const R psi = s * ld(psiA, n);
+    R psi;
+    if constexpr (LDS) psi = s * sh[D][H::self()];
+    else psi = s * ld(psiA, n);
     R Fs[3] = {0, 0, 0};
     if (k.E0 == R(0)) {
 #pragma unroll
