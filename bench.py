@@ -633,6 +633,73 @@ def uptake_validation(precision="fp64", times=(100, 250, 500, 1000, 2000, 5000, 
                 psi_sharp=[round(float(v), 6) for v in ref], rel_diff=rel)
 
 
+def shear_study(precision="fp64", R=50, sigma0=5e-4):
+    """The surfactant-covered drop in simple shear of Sec 3.3 (D2Q9, [-6R, 6R] x
+    [-2R, 2R], walls moving at -/+u_w, Re = 1, Ca = 0.5, lambda = 1, Pe_s = 10,
+    E0 = 0.3, x_in = 0.5, h = 0.5, Bi = 1, k = 1, sigma0 = 5e-4, so u_w follows
+    from Ca and Re): soluble cases with Pe_b = 0.1, 1 and 10 and an insoluble
+    one (no exchange). The paper compares shapes with another code's figures,
+    which are not available here; the orderings its text states are checked:
+    each soluble drop is more deformed than the insoluble one at tau = 4 and 8
+    (tau = shear rate x t), deformation falls as Pe_b grows, psi is highest at
+    the poles and lowest at the equator, and the insoluble case has the least
+    uniform psi."""
+    import workloads as W
+    from paper_2311_15242_amd import lbfd
+
+    say = lambda *a: print("[shear]", *a, file=sys.stderr, flush=True)
+    # sigma0 = mu U / Ca with mu = U R / Re (rho = 1) gives U^2 = sigma0 Re Ca / R
+    Re, Ca = 1.0, 0.5
+    U = np.sqrt(sigma0 * Re * Ca / R)
+    u_w = 2.0 * U
+    cases = [("Pe_b 0.1", dict(Pe_b=0.1)), ("Pe_b 1", dict(Pe_b=1.0)), ("Pe_b 10", dict(Pe_b=10.0)),
+             ("insoluble", dict(Pe_b=1.0, ra=0.0, rd=0.0))]
+    out = {}
+    for name, over in cases:
+        extra = {kk: v for kk, v in over.items() if kk in ("ra", "rd")}
+        p, q = W.shear_droplet(nx=12 * R, ny=4 * R, radius=float(R), u_w=u_w, Ca=Ca, Re=Re, Pe_s=10.0,
+                               Pe_b=over["Pe_b"], Bi=1.0, E0=0.3, x_in=0.5, h=0.5, k=1.0, precision=precision,
+                               **extra)
+        shear = 2.0 * u_w / p["ny"]
+        s = lbfd.Solver(p).init_fields(q)
+        t0 = time.time()
+        res = {}
+        step = 0
+        for tau in (4.0, 8.0):
+            n_t = int(round(tau / shear))
+            s.step(n_t - step)
+            step = n_t
+            ob = s.observables()
+            rec = dict(deformation=round(ob["deformation"], 4))
+            if tau == 4.0:
+                # psi at the interface by angle from the major axis of the drop
+                rN, psi = s.field("rhoN")[0], s.field("psi")[0]        # the one plane of the 2-D grid
+                ys, xs = np.nonzero(np.abs(rN) <= 0.2)
+                cx, cy = ob["centroid"][0], ob["centroid"][1]
+                sxx, syy, sxy = ob["second"][0], ob["second"][1], ob["second"][3]
+                ang = 0.5 * np.arctan2(2.0 * sxy, sxx - syy)           # major axis
+                dx, dy = xs - cx, ys - cy
+                c = np.abs(dx * np.cos(ang) + dy * np.sin(ang)) / np.maximum(np.hypot(dx, dy), 1e-12)
+                pv = psi[ys, xs] / q["psi0"]
+                rec.update(psi_poles=round(float(pv[c > 0.95].mean()), 4), psi_equator=round(float(pv[c < 0.3].mean()), 4),
+                           psi_spread=round(float(ob["psi_max"] - ob["psi_min"]) / q["psi0"], 4),
+                           incline_deg=round(float(np.degrees(ang)), 2))
+            res[f"tau{int(tau)}"] = rec
+            say(f"{name}: tau {tau}: {rec} ({time.time() - t0:.1f} s)")
+        res["status"] = s.observables()["status"]
+        s.close()
+        out[name] = res
+    sol = ["Pe_b 0.1", "Pe_b 1", "Pe_b 10"]
+    D = lambda nm, t: out[nm][t]["deformation"]
+    checks = dict(
+        soluble_more_deformed=all(D(nm, t) > D("insoluble", t) for nm in sol for t in ("tau4", "tau8")),
+        deformation_falls_with_pe_b=all(D(sol[0], t) > D(sol[1], t) > D(sol[2], t) for t in ("tau4", "tau8")),
+        psi_highest_at_poles=all(out[nm]["tau4"]["psi_poles"] > out[nm]["tau4"]["psi_equator"] for nm in out),
+        insoluble_least_uniform=all(out["insoluble"]["tau4"]["psi_spread"] > out[nm]["tau4"]["psi_spread"] for nm in sol))
+    return dict(workload=f"surfactant-covered drop in simple shear, R={R}, {12 * R}x{4 * R}, Ca=0.5, {precision}",
+                u_w=round(float(u_w), 6), checks=checks, cases=out)
+
+
 def cpu_baseline(p, q, budget_s):
     """The oracle as it stands, timed on the host cores: whole steps of the same
     workload (FP64), as many as fit the time budget (at least one)."""
@@ -880,6 +947,8 @@ def main():
     ap.add_argument("--retardation-precision", default="fp32")
     ap.add_argument("--validate-uptake", action="store_true",
                     help="the adsorption workload against the sharp-interface radial reference")
+    ap.add_argument("--validate-shear", action="store_true",
+                    help="orderings of the surfactant-covered drop in simple shear (Sec 3.3)")
     ap.add_argument("--sg-size", type=int, default=256)
     ap.add_argument("--sg-snapshots", type=int, default=16)
     ap.add_argument("--sg-tiles", type=int, default=64)
@@ -916,6 +985,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_calibration_bytes=n * 4, repeats=5)))
+        return
+    if args.validate_shear:
+        print(json.dumps(shear_study()), flush=True)
         return
     if args.validate_uptake:
         print(json.dumps(uptake_validation()), flush=True)

@@ -50,3 +50,12 @@ def test_retardation_small(gpu):
     for name, c in r["cases"].items():
         assert np.isfinite(c["re"]) and c["re"] > 0, name
     assert r["cases"]["Eo10 Bi1"]["psi_av"] > 0 and r["cases"]["Eo1 clean"]["psi_av"] == 0
+
+
+def test_shear_small(gpu):
+    r = bench.shear_study(R=10)
+    print(r["checks"], {k: v["tau8"] for k, v in r["cases"].items()})
+    assert set(r["cases"]) == {"Pe_b 0.1", "Pe_b 1", "Pe_b 10", "insoluble"}
+    for name, c in r["cases"].items():
+        assert c["status"] == 0, name
+        assert 0.0 < c["tau4"]["deformation"] < 1.0 and 0.0 < c["tau8"]["deformation"] < 1.0, name
