@@ -17,6 +17,7 @@
 //   force    curvature (eq 7), equation of state (eq 8), interfacial force
 //            (eq 9), buoyancy (Sec 3.4) and velocity (eq 10) of step n+1
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <algorithm>
 #include <cmath>
@@ -710,18 +711,22 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
     // source an arrival can come from) staged in LDS, so the 19 per-node reads are
     // LDS reads at fixed offsets instead of global gathers. Halo cells beyond a
     // wall are never read (an arrival across a wall comes from the node itself).
+    // The FP32 mode stages its (a, c) descriptors the same way; FP64 (32-byte
+    // descriptors) keeps the global gathers.
     constexpr int HX = BX + 2, HY = BY + 2, HZ = D == 3 ? 3 : 1, HN = HX * HY * HZ;
-    __shared__ DescDev sA[P::DEV ? HN : 1];
-    __shared__ uint32_t sB[(P::DEV && D == 3) ? HN : 1];
-    if constexpr (P::DEV) {
+    constexpr bool STG = P::DEV || sizeof(R) == 4, TWO = P::DEV && D == 3;
+    using TA = std::conditional_t<P::DEV, DescDev, V4<R>>;
+    __shared__ TA sA[STG ? HN : 1];
+    __shared__ uint32_t sB[TWO ? HN : 1];
+    if constexpr (STG) {
         const int bx = tile % k.gx, rr = tile / k.gx;
         const int ox = bx * BX - 1, oy = (rr % k.gy) * BY - 1, oz = rr / k.gy - (D == 3 ? 1 : 0);
-        const DescDev *dA = (const DescDev *)k.fld.desc;
+        const TA *dA = (const TA *)k.fld.desc;
         const uint32_t *dB = desc_dev_b(k);
         // every thread fetches up to HS cells, all loads issued before the LDS stores
         constexpr int HS = (HN + BX * BY - 1) / (BX * BY);
         const int t0 = (int)(threadIdx.x + BX * threadIdx.y);
-        DescDev va[HS];
+        TA va[HS];
         uint32_t vb[HS];
         bool have[HS];
 #pragma unroll
@@ -741,7 +746,7 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
             if (ok) {
                 const uint32_t gi = (uint32_t)g[0] + (uint32_t)k.nx * ((uint32_t)g[1] + (uint32_t)k.ny * (uint32_t)(D == 3 ? g[2] : 0));
                 va[it] = ldu(dA, gi);
-                if constexpr (D == 3) vb[it] = ldu(dB, gi);
+                if constexpr (TWO) vb[it] = ldu(dB, gi);
             }
         }
 #pragma unroll
@@ -749,7 +754,7 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
             const int h = t0 + it * BX * BY;
             if (have[it]) {
                 sA[h] = va[it];
-                if constexpr (D == 3) sB[h] = vb[it];
+                if constexpr (TWO) sB[h] = vb[it];
             }
         }
         __syncthreads();
@@ -797,8 +802,14 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
             as = A.a;
             fq += reference<LAT, R>(k, q, R(1), A.rho, as, us);
         } else {
-            const uint32_t src = source_of<LAT>(nb, n, q, bo);
-            const V4<R> A = ldu((const V4<R> *)k.fld.desc, src);
+            V4<R> A;
+            if constexpr (STG) {
+                const int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
+                bo = nb_wall(nb, -ex, -ey, -ez);
+                A = sA[bo ? hself : hself - ex - HX * (ey + HY * ez)];
+            } else {
+                A = ldu((const V4<R> *)k.fld.desc, source_of<LAT>(nb, n, q, bo));
+            }
             as = A.x;
             c[0] = A.y;
             c[1] = A.z;
