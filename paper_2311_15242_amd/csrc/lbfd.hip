@@ -707,18 +707,18 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
     using L = Lat<LAT>;
     constexpr int Q = L::Q, D = L::D;
     Node nd = node_at(k, tile);
-    // Deviation modes: the descriptors of the tile and its one-node halo (every
-    // source an arrival can come from) staged in LDS, so the 19 per-node reads are
-    // LDS reads at fixed offsets instead of global gathers. Halo cells beyond a
-    // wall are never read (an arrival across a wall comes from the node itself).
-    // The FP32 mode stages its (a, c) descriptors the same way; FP64 (32-byte
-    // descriptors) keeps the global gathers.
+    // The descriptors of the tile and its one-node halo (every source an arrival
+    // can come from) staged in LDS, so the 19 per-node reads are LDS reads at
+    // fixed offsets instead of global gathers: the packed descriptors of the
+    // deviation modes, the (a, c) vectors of FP32 and FP64 (16 and 32 bytes).
+    // Halo cells beyond a wall are never read (an arrival across a wall comes
+    // from the node itself).
     constexpr int HX = BX + 2, HY = BY + 2, HZ = D == 3 ? 3 : 1, HN = HX * HY * HZ;
-    constexpr bool STG = P::DEV || sizeof(R) == 4, TWO = P::DEV && D == 3;
+    constexpr bool TWO = P::DEV && D == 3;
     using TA = std::conditional_t<P::DEV, DescDev, V4<R>>;
-    __shared__ TA sA[STG ? HN : 1];
+    __shared__ TA sA[HN];
     __shared__ uint32_t sB[TWO ? HN : 1];
-    if constexpr (STG) {
+    {
         const int bx = tile % k.gx, rr = tile / k.gx;
         const int ox = bx * BX - 1, oy = (rr % k.gy) * BY - 1, oz = rr / k.gy - (D == 3 ? 1 : 0);
         const TA *dA = (const TA *)k.fld.desc;
@@ -802,14 +802,9 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
             as = A.a;
             fq += reference<LAT, R>(k, q, R(1), A.rho, as, us);
         } else {
-            V4<R> A;
-            if constexpr (STG) {
-                const int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
-                bo = nb_wall(nb, -ex, -ey, -ez);
-                A = sA[bo ? hself : hself - ex - HX * (ey + HY * ez)];
-            } else {
-                A = ldu((const V4<R> *)k.fld.desc, source_of<LAT>(nb, n, q, bo));
-            }
+            const int ex = L::E[q][0], ey = L::E[q][1], ez = L::E[q][2];
+            bo = nb_wall(nb, -ex, -ey, -ez);
+            const V4<R> A = sA[bo ? hself : hself - ex - HX * (ey + HY * ez)];
             as = A.x;
             c[0] = A.y;
             c[1] = A.z;

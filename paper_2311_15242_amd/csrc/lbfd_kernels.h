@@ -502,18 +502,6 @@ __device__ __forceinline__ R reference(const KP<R> &k, int i, R sgn, R rho, R a,
     return rho * (rest + R(L::W[i]) * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu));
 }
 
-// Source node of the population arriving at node n in direction j: x - e_j, or
-// n itself when that crosses a wall (half-way bounce-back returns a population
-// that left through a wall to its node reversed).
-template <int LAT>
-__device__ __forceinline__ uint32_t source_of(const Nbhd &b, uint32_t n, int j, bool &bounced)
-{
-    using L = Lat<LAT>;
-    const int ex = -L::E[j][0], ey = -L::E[j][1], ez = -L::E[j][2];
-    bounced = nb_wall(b, ex, ey, ez);
-    return n + (bounced ? 0u : (uint32_t)nb_delta(b, ex, ey, ez));
-}
-
 // Moments of a second-order polynomial in e_i weighted by w_i:
 // sum_i M_ri w_i [c0 + sum_a c1_a e_ia + sum_p c2_p (e_i e_i)_p], pairs p = xx yy zz xy xz yz
 // (an off-diagonal coefficient multiplies e_ia e_ib once). Zero table entries fold away.
