@@ -2086,13 +2086,17 @@ template <int LAT, class P> struct Impl {
         KP<R> &k = kp(h);
         LAUNCH(KC_FD, (k_fd<LAT, P>), h->grid, h->block, k);
         for (int s = 0; s < h->sweeps_launch; ++s) {
+            // sweeps past the third usually find both systems converged and return at
+            // once: a narrower persistent grid makes that cheaper (the updates of a
+            // colour half-sweep do not depend on their order, so the result is the same)
+            const dim3 gs(s < 3 ? h->sor_blocks : std::min(h->sor_blocks, 256));
             if (h->seam_levels == 0) {
-                LAUNCH(KC_SOR, (k_sor<LAT, P, false>), dim3(h->sor_blocks), dim3(256), k, 0, s);
-                LAUNCH(KC_SOR, (k_sor<LAT, P, false>), dim3(h->sor_blocks), dim3(256), k, 1, s);
+                LAUNCH(KC_SOR, (k_sor<LAT, P, false>), gs, dim3(256), k, 0, s);
+                LAUNCH(KC_SOR, (k_sor<LAT, P, false>), gs, dim3(256), k, 1, s);
                 continue;
             }
-            LAUNCH(KC_SOR, (k_sor<LAT, P, true>), dim3(h->sor_blocks), dim3(256), k, 0, s);
-            LAUNCH(KC_SOR, (k_sor<LAT, P, true>), dim3(h->sor_blocks), dim3(256), k, 1, s);
+            LAUNCH(KC_SOR, (k_sor<LAT, P, true>), gs, dim3(256), k, 0, s);
+            LAUNCH(KC_SOR, (k_sor<LAT, P, true>), gs, dim3(256), k, 1, s);
             for (int lv = 1; lv <= h->seam_levels; ++lv) {
                 LAUNCH(KC_SOR, (k_sor_seam<LAT, P>), dim3(h->seam_tiles), dim3(256), k, lv, 0, s);
                 LAUNCH(KC_SOR, (k_sor_seam<LAT, P>), dim3(h->seam_tiles), dim3(256), k, lv, 1, s);
