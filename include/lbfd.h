@@ -23,7 +23,9 @@
  *   - Device memory: the caller allocates one device workspace of the size
  *     lbfd_workspace_bytes reports and keeps it alive until lbfd_destroy;
  *     the handle only borrows it. The handle allocates nothing on the device
- *     except transient buffers inside lbfd_read_field / lbfd_set_state.
+ *     except transient buffers inside lbfd_read_field / lbfd_set_state /
+ *     lbfd_write_field; lbfd_read_field_noalloc stages through a fixed
+ *     library-owned array instead and allocates nothing.
  *   - Streams: every device operation is enqueued on the stream given to
  *     lbfd_create (a hipStream_t passed as void*; NULL is the null stream).
  *     lbfd_step is asynchronous; lbfd_observables, lbfd_read_field and
@@ -51,7 +53,8 @@ typedef enum {
     LBFD_ENONFINITE = -4,   /* a non-finite total surfactant or mass was detected */
     LBFD_ESOR = -5,         /* SOR reached sor_max_sweeps above tolerance */
     LBFD_EWORKSPACE = -6,   /* workspace missing or smaller than required */
-    LBFD_EUNSUPPORTED = -7  /* valid but not supported combination */
+    LBFD_EUNSUPPORTED = -7, /* valid but not supported combination */
+    LBFD_ESCRATCH = -8      /* request larger than the fixed scratch buffer (lbfd_read_field_noalloc) */
 } lbfd_status;
 
 typedef enum { LBFD_D2Q9 = 0, LBFD_D3Q19 = 1 } lbfd_lattice;
@@ -185,6 +188,21 @@ int lbfd_observables(lbfd_handle *h, lbfd_obs *out);
 /* Copy one field of the current state to host memory as FP64; `count`
  * must equal components * nodes. Synchronises the stream. */
 int lbfd_read_field(lbfd_handle *h, int32_t field, double *host, size_t count);
+
+/* lbfd_read_field without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). The field is converted to FP64 in a fixed device staging
+ * array owned by the library (one per device, LBFD_SCRATCH_DOUBLES doubles =
+ * 64 MiB, held until the process ends) and copied to `host`; arguments and
+ * result are those of lbfd_read_field. The call allocates nothing: no hipMalloc,
+ * hipFree or allocating library routine. All calls on one device share that
+ * array and it keeps the last call's contents, so calls that overlap on one
+ * device (from several host threads or handles) race; serialise them.
+ * Synchronises the handle's stream. Errors: EINVAL (unknown field, count not
+ * components * nodes, null pointer), ESCRATCH (count > LBFD_SCRATCH_DOUBLES;
+ * use lbfd_read_field), EHIP. */
+#define LBFD_SCRATCH_DOUBLES ((size_t)8 << 20)
+int lbfd_read_field_noalloc(lbfd_handle *h, int32_t field, double *host, size_t count);
 
 /* Per-kernel timing with HIP events on the handle's stream: enable (non-zero)
  * or disable (0); enabling clears the accumulators. enable = 1 times every

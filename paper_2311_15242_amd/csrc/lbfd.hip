@@ -25,6 +25,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1689,6 +1690,7 @@ struct lbfd_handle {
     StepGraphs graphs;
     bool fd_off = false;  // LB steps only (psi, phi held): surrogate mode between its updates
     bool kp_dirty = false;  // the parameter block changed after creation (a batch re-uploads its table)
+    int dev = 0;          // device current at lbfd_create (the workspace's device)
 };
 
 // A batch: independent instances (ordinary handles on slices of one workspace)
@@ -1951,6 +1953,19 @@ struct Timer {
         Timer _t(h, KC);                                                              \
         hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, h->stream, __VA_ARGS__);           \
     } while (0)
+
+// Number of FP64 values lbfd_read_field returns for a field (components x
+// nodes), or 0 for an unknown field identifier.
+static size_t field_count(const lbfd_handle *h, int field)
+{
+    switch (field) {
+    case LBFD_FIELD_F: return (size_t)h->Q * (size_t)h->N;
+    case LBFD_FIELD_U: case LBFD_FIELD_FORCE: return (size_t)h->D * (size_t)h->N;
+    case LBFD_FIELD_RHOR: case LBFD_FIELD_RHOB: case LBFD_FIELD_RHON: case LBFD_FIELD_PSI: case LBFD_FIELD_PHI:
+    case LBFD_FIELD_G: case LBFD_FIELD_SPREV: case LBFD_FIELD_BPREV: return (size_t)h->N;
+    default: return 0;
+    }
+}
 
 template <int LAT, class P> struct Impl {
     using R = typename P::R;
@@ -2470,24 +2485,25 @@ template <int LAT, class P> struct Impl {
         return e == hipSuccess ? LBFD_OK : LBFD_EHIP;
     }
 
-    static int read_field(lbfd_handle *h, int field, double *host, size_t count)
+    // FP64 export of one field through the device staging buffer d (count
+    // doubles, at least the field's size), then to host memory; synchronous.
+    static int export_via(lbfd_handle *h, int field, double *host, size_t count, double *d)
     {
-        int comps = field == LBFD_FIELD_F ? h->Q : (field == LBFD_FIELD_U || field == LBFD_FIELD_FORCE) ? h->D : 1;
-        switch (field) {
-        case LBFD_FIELD_F: case LBFD_FIELD_RHOR: case LBFD_FIELD_RHOB: case LBFD_FIELD_RHON: case LBFD_FIELD_U:
-        case LBFD_FIELD_PSI: case LBFD_FIELD_PHI: case LBFD_FIELD_FORCE: case LBFD_FIELD_G:
-        case LBFD_FIELD_SPREV: case LBFD_FIELD_BPREV: break;
-        default: return LBFD_EINVAL;
-        }
-        if (count != (size_t)comps * (size_t)h->N || !host) return LBFD_EINVAL;
-        double *d = nullptr;
-        if (hipMalloc(&d, count * sizeof(double)) != hipSuccess) return LBFD_EHIP;
         sync_levels(h);
         LAUNCH(KC_OTHER, (k_export<LAT, P>), h->grid, h->block, kp(h), field, d);
-        hipMemcpyAsync(host, d, count * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-        hipError_t e = hipStreamSynchronize(h->stream);
+        if (hipMemcpyAsync(host, d, count * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+            return LBFD_EHIP;
+        return hipStreamSynchronize(h->stream) == hipSuccess ? LBFD_OK : LBFD_EHIP;
+    }
+
+    static int read_field(lbfd_handle *h, int field, double *host, size_t count)
+    {
+        if (field_count(h, field) != count || count == 0 || !host) return LBFD_EINVAL;
+        double *d = nullptr;
+        if (hipMalloc(&d, count * sizeof(double)) != hipSuccess) return LBFD_EHIP;
+        int st = export_via(h, field, host, count, d);
         hipFree(d);
-        return e == hipSuccess ? LBFD_OK : LBFD_EHIP;
+        return st;
     }
 };
 
@@ -2510,6 +2526,7 @@ struct Dispatch {
     int (*sg_candidate)(lbfd_handle *, const float *, float, float);
     int (*sg_accept)(lbfd_handle *);
     int (*read_scalars)(lbfd_handle *, DevScalars *);
+    int (*export_via)(lbfd_handle *, int, double *, size_t, double *);
 };
 
 template <int LAT, class P> Dispatch make_dispatch()
@@ -2518,7 +2535,7 @@ template <int LAT, class P> Dispatch make_dispatch()
     return Dispatch{&I::init,        &I::set_state,   &I::step,        &I::observables, &I::read_field,
                     &I::write_field, &I::batch_step,  &I::batch_table, sizeof(KP<typename P::R>),
                     &I::fd_substeps, &I::sg_features, &I::sg_snapshot, &I::sg_tiles,      &I::sg_candidate,
-                    &I::sg_accept,   &I::read_scalars};
+                    &I::sg_accept,   &I::read_scalars, &I::export_via};
 }
 
 Dispatch dispatch_for(int lat, int prec)
@@ -2537,6 +2554,41 @@ Dispatch dispatch_for(int lat, int prec)
     case LBFD_FP16DEV: return make_dispatch<1, PrecF16>();
     default: return make_dispatch<1, PrecB16>();
     }
+}
+
+// ---- fixed staging buffer of lbfd_read_field_noalloc ------------------------
+// Callers that cannot allocate device memory (code under graph capture, tight
+// serving loops) read fields through this file-scope array instead of a
+// per-call allocation. Every device the library runs on holds one copy, at its
+// own address, until the process ends. Host code never passes the array's name
+// to a kernel or a copy (on the host it is only a stand-in symbol): it uses the
+// device address hipGetSymbolAddress returns for the current device, looked up
+// once per device and kept in scratch_ptr.
+constexpr size_t SCRATCH_DOUBLES = (size_t)8 << 20;  // 64 MiB: one scalar field of up to 8 Mi nodes
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double *scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of `scratch` on device dev (made current for the lookup, then
+// the caller's current device is restored).
+int scratch_address(int dev, double **out)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return LBFD_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return LBFD_EHIP;
+        if (cur != dev && hipSetDevice(dev) != hipSuccess) return LBFD_EHIP;
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) hipSetDevice(cur);
+        if (e != hipSuccess || !ptr) return LBFD_EHIP;
+        scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = scratch_ptr[dev];
+    return LBFD_OK;
 }
 
 int sticky_status(lbfd_handle *h)
@@ -2601,6 +2653,7 @@ int lbfd_create(const lbfd_params *p, void *d_workspace, size_t bytes, void *str
     }
     h->prof = false;
     h->prof_mask = 0xffffffffu;
+    if (hipGetDevice(&h->dev) != hipSuccess) h->dev = 0;
     fill_kp(h->kd, p, h->ws, Lo);
     fill_kp(h->kf, p, h->ws, Lo);
     h->obs_out = (double *)(h->ws + Lo.obs);
@@ -2646,6 +2699,20 @@ int lbfd_read_field(lbfd_handle *h, int32_t field, double *host, size_t count)
 {
     if (!h) return LBFD_EINVAL;
     int st = dispatch_for(h->p.lattice, h->p.precision).read_field(h, field, host, count);
+    if (st != LBFD_OK) return st;
+    return sticky_status(h);
+}
+
+int lbfd_read_field_noalloc(lbfd_handle *h, int32_t field, double *host, size_t count)
+{
+    if (!h || !host) return LBFD_EINVAL;
+    const size_t need = field_count(h, field);
+    if (need == 0 || count != need) return LBFD_EINVAL;
+    if (count > SCRATCH_DOUBLES) return LBFD_ESCRATCH;
+    double *d = nullptr;
+    int st = scratch_address(h->dev, &d);
+    if (st != LBFD_OK) return st;
+    st = dispatch_for(h->p.lattice, h->p.precision).export_via(h, field, host, count, d);
     if (st != LBFD_OK) return st;
     return sticky_status(h);
 }
@@ -3273,6 +3340,7 @@ const char *lbfd_strerror(int s)
     case LBFD_ESOR: return "SOR did not reach its tolerance within sor_max_sweeps";
     case LBFD_EWORKSPACE: return "device workspace missing, misaligned or too small";
     case LBFD_EUNSUPPORTED: return "unsupported combination";
+    case LBFD_ESCRATCH: return "request larger than the library's fixed scratch buffer";
     default: return "unknown status";
     }
 }

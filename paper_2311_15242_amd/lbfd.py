@@ -14,13 +14,15 @@ import numpy as np
 from . import build as _build
 
 LBFD_OK, LBFD_EINVAL, LBFD_ENOMEM, LBFD_EHIP, LBFD_ENONFINITE, LBFD_ESOR, LBFD_EWORKSPACE = 0, -1, -2, -3, -4, -5, -6
+LBFD_EUNSUPPORTED, LBFD_ESCRATCH = -7, -8
+SCRATCH_DOUBLES = 8 << 20   # LBFD_SCRATCH_DOUBLES: capacity of lbfd_read_field_noalloc
 PRECISION = {"fp64": 0, "fp32": 1, "fp16dev": 2, "bf16dev": 3}
 FIELDS = dict(f=0, rhoR=3, rhoB=4, rhoN=5, u=6, psi=7, phi=8, force=9, G=10, Sprev=11, Bprev=12)
 EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_init_fields", "lbfd_set_state", "lbfd_step",
             "lbfd_observables", "lbfd_read_field", "lbfd_profile", "lbfd_profile_read", "lbfd_destroy",
             "lbfd_strerror", "lbfd_batch_workspace_bytes", "lbfd_batch_create", "lbfd_batch_instance",
             "lbfd_batch_step", "lbfd_batch_destroy", "lbfd_set_graphs", "lbfd_batch_set_graphs",
-            "lbfd_fd_substeps", "lbfd_set_fd", "lbfd_write_field",
+            "lbfd_fd_substeps", "lbfd_set_fd", "lbfd_write_field", "lbfd_read_field_noalloc",
             "lbfd_sg_n_params", "lbfd_sg_workspace_bytes", "lbfd_sg_create", "lbfd_sg_set_params",
             "lbfd_sg_get_params", "lbfd_sg_forward", "lbfd_sg_gradient", "lbfd_sg_train_step", "lbfd_sg_features",
             "lbfd_sg_snapshot", "lbfd_sg_tiles", "lbfd_sg_advance", "lbfd_sg_destroy", "lbfd_sg_set_drift_tol"]
@@ -107,6 +109,7 @@ def load(build_if_missing: bool = False):
     L.lbfd_step.argtypes = [vp, C.c_int64]
     L.lbfd_observables.argtypes = [vp, P(Obs)]
     L.lbfd_read_field.argtypes = [vp, C.c_int32, dp, C.c_size_t]
+    L.lbfd_read_field_noalloc.argtypes = [vp, C.c_int32, dp, C.c_size_t]
     L.lbfd_profile.argtypes = [vp, C.c_int32]
     L.lbfd_profile_read.argtypes = [vp, C.c_int32, P(C.c_char_p), dp, P(C.c_int64), P(C.c_int32)]
     L.lbfd_destroy.argtypes = [vp]
@@ -262,6 +265,15 @@ class _Instance:
         out = np.zeros(c * self.N, dtype=np.float64)
         _check(load().lbfd_read_field(self.h, FIELDS[name], out.ctypes.data_as(C.POINTER(C.c_double)),
                                       out.size), f"lbfd_read_field({name})")
+        return out.reshape((c,) + self.shape) if c > 1 else out.reshape(self.shape)
+
+    def field_noalloc(self, name: str) -> np.ndarray:
+        """field() through lbfd_read_field_noalloc: staged in the library's fixed
+        device array (no device allocation); LBFD_ESCRATCH above its capacity."""
+        c = self.Q if name == "f" else self.D if name in ("u", "force") else 1
+        out = np.zeros(c * self.N, dtype=np.float64)
+        _check(load().lbfd_read_field_noalloc(self.h, FIELDS[name], out.ctypes.data_as(C.POINTER(C.c_double)),
+                                              out.size), f"lbfd_read_field_noalloc({name})")
         return out.reshape((c,) + self.shape) if c > 1 else out.reshape(self.shape)
 
     KERNEL_CLASSES = ("collide", "macro", "geom", "fd", "sor", "total", "force", "other")
