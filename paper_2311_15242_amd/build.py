@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbfd.so")
 SOURCES = [os.path.join(CSRC, "lbfd.hip")]
 HEADERS = [os.path.join(CSRC, "lbfd_kernels.h"), os.path.join(CSRC, "lbfd_lattice_tables.h"),
-           os.path.join(ROOT, "include", "lbfd.h")]
+           os.path.join(CSRC, "sg_conv.h"), os.path.join(ROOT, "include", "lbfd.h"),
+           os.path.join(ROOT, "include", "lbfd_surrogate.h")]
 
 
 def hipcc() -> str:
