@@ -94,6 +94,8 @@ def lib():
         L.orc_lattice_q.argtypes = [C.c_void_p]
         L.orc_threads.restype = C.c_int
         L.orc_threads.argtypes = []
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_initial_total.restype = C.c_double
         L.orc_initial_total.argtypes = [C.c_void_p]
         L.orc_get_field.argtypes = [C.c_void_p, C.c_int, dp]
@@ -121,6 +123,11 @@ def _ptr(a):
 def threads() -> int:
     """OpenMP threads the oracle's node loops use."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's node loops (timing runs)."""
+    lib().orc_set_threads(int(n))
 
 
 def params_struct(p: dict) -> _Params:

@@ -942,6 +942,13 @@ int orc_step(orc_state *s, int64_t nsteps)
 int64_t orc_nodes(const orc_state *s) { return s ? s->N : 0; }
 
 /* Threads the OpenMP loops use (for reporting the CPU baseline). */
+/* Set the OpenMP threads of the node loops (timing only: results do not
+   depend on it beyond the summation order of the observables). */
+void orc_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}
+
 int orc_threads(void)
 {
     int n = 1;

@@ -445,11 +445,32 @@ template <int LAT, class P> __device__ __forceinline__ void force_body(const KP<
         }
         g[a] = -nv[a] * den;
     }
-    R psi;
-    if constexpr (LDS) psi = s * sh[D][H::self()];
-    else psi = s * ld(psiA, n);
+    R psi_st;  // stored (unscaled) psi
+    if constexpr (LDS) psi_st = sh[D][H::self()];
+    else psi_st = ld(psiA, n);
+    const R psi = s * psi_st;
     R Fs[3] = {0, 0, 0};
-    if (k.E0 == R(0)) {
+    // Near saturation the FP32 modes evaluate eq 8 and the Marangoni prefactor of
+    // eq 9 in FP64: there 1 - psi/psi_inf is small (1.2e-4 at the CMC of E0 = 0.1)
+    // and FP32 rounding of psi s and psi/psi_inf would cost up to 1e-3 of it.
+    // Above psi = 0.9 psi_inf, psi = s psi_st, 1 - psi/psi_inf (by log1p), the CMC
+    // test and psi_inf - psi are FP64; below it FP32 keeps ~1e-6 relative.
+    const bool sat64 = sizeof(R) == 4 && !k.eos_linear && k.E0 != R(0) && psi > R(0.9) * k.psi_inf;
+    if (sat64) {
+        const double pd = k.fld.sc->scale * (double)psi_st;
+        if (pd < k.cmc_d) {
+            const R sigma = (R)(k.sigma0_d * (1.0 + k.E0_d * log1p(-pd / k.psi_inf_d)));
+            const R mar = (R)(0.5 * (double)G * k.sigma0_d * k.E0_d / (k.psi_inf_d - pd));
+            R ndg = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) ndg += nv[a] * gp[a];
+#pragma unroll
+            for (int a = 0; a < D; ++a) Fs[a] = R(-0.5) * sigma * kappa * g[a] - mar * (gp[a] - ndg * nv[a]);
+        } else {
+#pragma unroll
+            for (int a = 0; a < D; ++a) Fs[a] = R(-0.5) * k.sigma_min * kappa * g[a];
+        }
+    } else if (k.E0 == R(0)) {
 #pragma unroll
         for (int a = 0; a < D; ++a) Fs[a] = R(-0.5) * k.sigma0 * kappa * g[a];
     } else if (k.eos_linear) {
@@ -1875,6 +1896,8 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
     k.sigma0 = (R)p->sigma0; k.E0 = (R)p->E0; k.psi_inf = (R)p->psi_inf;
     k.sigma_min = (R)(p->sigma_min_ratio * p->sigma0);
     k.cmc = (R)(p->E0 > 0 ? p->psi_inf * (1.0 - std::exp(-(1.0 - p->sigma_min_ratio) / p->E0)) : p->psi_inf);
+    k.sigma0_d = p->sigma0; k.E0_d = p->E0; k.psi_inf_d = p->psi_inf;
+    k.cmc_d = p->E0 > 0 ? p->psi_inf * (1.0 - std::exp(-(1.0 - p->sigma_min_ratio) / p->E0)) : p->psi_inf;
     k.eos_linear = p->eos_mode == 1;
     k.Ds = (R)p->Ds; k.Db = (R)p->Db; k.ra = (R)p->ra; k.rd = (R)p->rd;
     k.source_mode = p->source_mode;

@@ -42,14 +42,22 @@ struct PrecF16 { using R = float; using S = _Float16; static constexpr bool DEV 
 struct bf16 { uint16_t bits; };
 struct PrecB16 { using R = float; using S = bf16; static constexpr bool DEV = true; };
 
+// The FP16 mode stores its deviations and non-equilibrium moments scaled by
+// 2^12: FP16 keeps 11 significant bits only above 2^-14 (6.1e-5), and
+// deviations of slow or starting flows (1e-8 to 1e-5) would otherwise fall among
+// the subnormals; scaled, they stay normal down to 1.5e-8 while the largest
+// storable value is 16 (deviations and moments stay below 1). Powers of two
+// scale exactly.
+constexpr float F16_SCALE = 4096.0f, F16_ISCALE = 1.0f / 4096.0f;
+
 __device__ __forceinline__ float to_real(bf16 v) { return __uint_as_float((uint32_t)v.bits << 16); }
-__device__ __forceinline__ float to_real(_Float16 v) { return (float)v; }
+__device__ __forceinline__ float to_real(_Float16 v) { return (float)v * F16_ISCALE; }
 __device__ __forceinline__ float to_real(float v) { return v; }
 __device__ __forceinline__ double to_real(double v) { return v; }
 
 template <class S> __device__ __forceinline__ S from_real(float v);
 template <> __device__ __forceinline__ float from_real<float>(float v) { return v; }
-template <> __device__ __forceinline__ _Float16 from_real<_Float16>(float v) { return (_Float16)v; }
+template <> __device__ __forceinline__ _Float16 from_real<_Float16>(float v) { return (_Float16)(v * F16_SCALE); }
 template <> __device__ __forceinline__ bf16 from_real<bf16>(float v)
 {
     // round to nearest even; finite inputs only (populations are finite)
@@ -221,6 +229,7 @@ template <class R> struct KP {
     R beta;
     int recolour_literal;
     R sigma0, E0, psi_inf, sigma_min, cmc;
+    double sigma0_d, E0_d, psi_inf_d, cmc_d;  // FP64 copies: the equation of state near saturation
     int eos_linear;     // sigma = sigma0 (1 - E0 psi / psi_inf) without a floor (Sec 3.2)
     R Ds, Db, ra, rd;
     int source_mode;

@@ -100,6 +100,10 @@ def load(build_if_missing: bool = False):
         if not build_if_missing:
             raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
         _build.build()
+    # torch provides the workspace and the stream, so its HIP runtime must be the
+    # one the library binds to: loaded first, the library's libamdhip64 dependency
+    # resolves to it instead of a second runtime copy that knows neither
+    import torch  # noqa: F401
     L = C.CDLL(path)
     P, vp, dp = C.POINTER, C.c_void_p, C.POINTER(C.c_double)
     L.lbfd_workspace_bytes.argtypes = [P(Params), P(C.c_size_t)]
