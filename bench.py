@@ -46,8 +46,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "traffic_bubble128x128x384_bf16dev.json")
+VALU_FILE = os.path.join(PROFILES, "valu_bubble128x128x384_bf16dev.json")
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # wave64 VALU lane instructions per second
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2311_15242_amd", "csrc", f)
-                  for f in ("lbfd.hip", "lbfd_kernels.h", "lbfd_lattice_tables.h")]
+                  for f in ("lbfd.hip", "lbfd_kernels.h", "lbfd_lattice_tables.h", "sg_conv.h")]
+TIMED_REGIONS = 5        # the headline is the median of this many timed regions of K steps
+
+# Minimum state a two-colour method must move per lattice update (every population
+# read and written once, plus the scalar fields of the step; on-chip recomputation
+# excluded), by lattice and storage: the "useful bandwidth" denominator.
+USEFUL_BYTES = {(0, "fp64"): 424, (0, "fp32"): 212, (0, "fp16dev"): 148, (0, "bf16dev"): 148,
+                (1, "fp64"): 768, (1, "fp32"): 384, (1, "fp16dev"): 240, (1, "bf16dev"): 240}
 
 
 def kernel_source_hash() -> str:
@@ -104,7 +113,11 @@ def build_solver(p, q):
     return lbfd.Solver(p).init_fields(q)
 
 
-def timed_run(p, q, steps, warmup, profile, only=None):
+def timed_run(p, q, steps, warmup, profile, only=None, regions=1):
+    """Warm-up, then `regions` timed regions of `steps` steps each on the same
+    solver (HIP events on its stream, synchronised on both sides). Returns the
+    median region's milliseconds, the profile of all regions, the observables
+    and every region's milliseconds."""
     import torch
 
     s = build_solver(p, q)
@@ -117,18 +130,20 @@ def timed_run(p, q, steps, warmup, profile, only=None):
         s.profile(True, only=only)
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    a.record()
-    s.step(steps)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b)
+    runs = []
+    for _ in range(regions):
+        torch.cuda.synchronize()
+        a.record()
+        s.step(steps)
+        b.record()
+        torch.cuda.synchronize()
+        runs.append(a.elapsed_time(b))
     prof = s.profile_read() if profile else {}
     ob = s.observables()
     if ob["status"] != 0:
         raise RuntimeError(f"solver status {ob['status']} in the timed region")
     s.close()
-    return ms, prof, ob
+    return float(np.median(runs)), prof, ob, runs
 
 
 def conv_flops(d, h, w, B=1):
@@ -700,37 +715,108 @@ def shear_study(precision="fp64", R=50, sigma0=5e-4):
                 u_w=round(float(u_w), 6), checks=checks, cases=out)
 
 
-def cpu_baseline(p, q, budget_s):
-    """The oracle as it stands, timed on the host cores: whole steps of the same
-    workload (FP64), as many as fit the time budget (at least one)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(p, q, budget_s, warmup=0, min_steps=1):
+    """Whole FP64 oracle steps of a workload after `warmup` untimed steps, as many
+    as fit the time budget (at least min_steps): (MLUPS, steps, seconds)."""
     import oracle
 
     o = oracle.Oracle(dict(p, precision="fp64")).init(q)
-    N = o.N
+    if warmup:
+        o.step(warmup)
     t0 = time.perf_counter()
-    o.step(1)
-    t1 = time.perf_counter()
-    steps = 1
-    per = t1 - t0
-    extra = int(max(0, budget_s - per) // per)
-    if extra:
-        o.step(extra)
-        steps += extra
-    t2 = time.perf_counter()
-    mlups = N * steps / (t2 - t0) / 1e6
-    return dict(value=round(mlups, 4), unit="MLUPS", cores=oracle.threads(), kind="oracle",
-                sample=f"{steps} FP64 step(s) of the same {p['nx']}x{p['ny']}x{p['nz']} workload "
-                       f"after initialisation, {t2 - t0:.1f} s")
+    o.step(min_steps)
+    per = (time.perf_counter() - t0) / min_steps
+    steps = min_steps + int(max(0.0, budget_s - per * min_steps) // per)
+    if steps > min_steps:
+        o.step(steps - min_steps)
+    dt = time.perf_counter() - t0
+    return o.N * steps / dt / 1e6, steps, dt
 
 
-def traffic_for(kernel, launches_per_step):
-    if not os.path.exists(TRAFFIC_FILE):
+def cpu_baseline(p, q, budget_s):
+    """The oracle as it stands, timed on the host cores: whole FP64 steps of the
+    same workload, as many as fit the time budget, on every core the OpenMP
+    runtime offers, then one step on a single thread."""
+    import oracle
+
+    cores = oracle.threads()
+    mlups, steps, dt = _oracle_rate(p, q, budget_s)
+    oracle.set_threads(1)
+    m1, s1, d1 = _oracle_rate(p, q, 0.0)
+    oracle.set_threads(cores)
+    return dict(value=round(mlups, 4), unit="MLUPS", cores=cores, kind="oracle", cpu_model=cpu_model(),
+                one_thread_mlups=round(m1, 4),
+                sample=f"{steps} FP64 step(s) of the same {p['nx']}x{p['ny']}x{p['nz']} workload after "
+                       f"initialisation on {cores} threads, {dt:.1f} s; {s1} step on 1 thread, {d1:.1f} s")
+
+
+def cpu_windows():
+    """The oracle over fixed windows on every host core (droplet128 2000 steps,
+    shear512x256 1000 steps, bubble128x128x384 50 steps after 10) and over
+    shortened windows on one thread (200, 50 and 1 after 1)."""
+    import oracle
+
+    import workloads as W
+
+    cores = oracle.threads()
+    rows = [f"CPU: {cpu_model()}, {cores} OpenMP threads (all cores) and 1 thread; FP64 oracle, whole steps"]
+    rows.append(f"{'workload':22s} {'threads':>8s} {'warm-up':>8s} {'steps':>6s} {'seconds':>9s} {'MLUPS':>9s}")
+    plan = [("droplet128", 2000, 0, 200, 0), ("shear512x256", 1000, 0, 50, 0), ("bubble128x128x384", 50, 10, 1, 1)]
+    for name, n_all, w_all, n_one, w_one in plan:
+        p, q = W.config(name, "fp64")
+        for thr, n, w in ((cores, n_all, w_all), (1, n_one, w_one)):
+            oracle.set_threads(thr)
+            o = oracle.Oracle(p).init(q)
+            if w:
+                o.step(w)
+            t0 = time.perf_counter()
+            o.step(n)
+            dt = time.perf_counter() - t0
+            rows.append(f"{name:22s} {thr:8d} {w:8d} {n:6d} {dt:9.2f} {o.N * n / dt / 1e6:9.4f}")
+            print(rows[-1], file=sys.stderr, flush=True)
+            del o
+    oracle.set_threads(cores)
+    return "\n".join(rows)
+
+
+KERNEL_CLASS_OF = {"k_collide<": "collide", "k_macro<": "macro", "k_geom<": "geom", "k_fd<": "fd",
+                   "k_sor<": "sor", "k_total_part<": "total", "k_force<": "force"}
+
+
+def kernel_class(name):
+    for pat, cls in KERNEL_CLASS_OF.items():
+        if pat in name:
+            return cls
+    return None
+
+
+def _evidence(path):
+    """A profile record under profiles/ if it was taken on the current kernel sources."""
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel") != kernel or t.get("source_hash") != kernel_source_hash():
+    return t if t.get("source_hash") == kernel_source_hash() else None
+
+
+def traffic_for(kernel, launches_per_step=1.0):
+    """Measured HBM bytes per launch of a kernel class (scaled FETCH_SIZE +
+    WRITE_SIZE, from the profile record), or None."""
+    t = _evidence(TRAFFIC_FILE)
+    if not t:
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_launch", {}).get(kernel)
 
 
 def _pmc_rows(path):
@@ -786,17 +872,19 @@ def trace_summary(stats_csv):
     return "\n".join(lines)
 
 
-def write_traffic(kernel, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out_path):
-    """HBM bytes per launch of one kernel class (scaled FETCH_SIZE + WRITE_SIZE),
-    stored with the hash of the kernel sources they were measured on."""
+def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out_path):
+    """HBM bytes per launch of every kernel class of the step (scaled FETCH_SIZE +
+    WRITE_SIZE; SOR: the mean over its launches, early returns included), stored
+    with the hash of the kernel sources they were measured on."""
     import collections
 
     def mean_kib(path):
         acc = collections.defaultdict(list)
         for name, v, _ in _pmc_rows(path):
-            acc[name].append(v)
-        sel = [sum(v) / len(v) for k, v in acc.items() if f"k_{kernel}<" in k]
-        return sel[0] if sel else None
+            c = kernel_class(name)
+            if c and not name.split("lbfd::")[-1].startswith("kb_"):
+                acc[c].append(v)
+        return {c: sum(v) / len(v) for c, v in acc.items()}
 
     def copy_kib(path):
         vals = [v for name, v, _ in _pmc_rows(path) if "copy" in name.lower()]
@@ -806,12 +894,150 @@ def write_traffic(kernel, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, 
     sf = nbytes / (copy_kib(copy_fetch_csv) * 1024)
     sw = nbytes / (copy_kib(copy_write_csv) * 1024)
     fk, wk = mean_kib(fetch_csv), mean_kib(write_csv)
-    rec = dict(kernel=kernel, source_hash=kernel_source_hash(), fetch_kib=fk, write_kib=wk,
-               fetch_scale=round(sf, 4), write_scale=round(sw, 4),
-               bytes_per_launch=round((fk * sf + wk * sw) * 1024))
+    rec = dict(source_hash=kernel_source_hash(), fetch_scale=round(sf, 4), write_scale=round(sw, 4),
+               fetch_kib={c: round(v, 1) for c, v in fk.items()}, write_kib={c: round(v, 1) for c, v in wk.items()},
+               bytes_per_launch={c: round((fk[c] * sf + wk.get(c, 0.0) * sw) * 1024) for c in fk})
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
     return rec
+
+
+def write_valu(pmc_csv, out_path):
+    """VALU instructions per wavefront and wavefronts per launch of every kernel
+    class, from a rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES run, stored with the
+    hash of the kernel sources."""
+    import collections
+    import csv
+
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    with open(pmc_csv) as fh:
+        for r in csv.DictReader(fh):
+            c = kernel_class(r["Kernel_Name"])
+            if c and not r["Kernel_Name"].split("lbfd::")[-1].startswith("kb_"):
+                acc[c][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    rec = dict(source_hash=kernel_source_hash(), classes={})
+    for c, d in acc.items():
+        v, w = d.get("SQ_INSTS_VALU"), d.get("SQ_WAVES")
+        if v and w and sum(w) > 0:
+            rec["classes"][c] = dict(valu_per_wave=round(sum(v) / sum(w), 1), waves_per_launch=round(sum(w) / len(w)))
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
+def sor_half_sweeps(p, ob):
+    """SOR half-sweeps that did work in a step: K sweeps and, with omega = 1 and
+    no seam classes, the red half of sweep K + 1 that found the residual within
+    tolerance (otherwise the whole of sweep K + 1 tested it)."""
+    if not p["fd_enable"]:
+        return 0
+    K = max(ob["sor_sweeps"])
+    exact = p["sor_omega"] == 1.0 and not any(
+        p["bc"][a] == 0 and n % 2 == 1 for a, n in enumerate((p["nx"], p["ny"], p["nz"])) if a < 2 or p["lattice"] == 1)
+    return 2 * K + 1 if exact else 2 * K + 2
+
+
+def _valu_roof(cls, per_launch_s):
+    """Issue-rate view of a kernel class from the VALU counter record: lane
+    instructions per second against 256 CUs x 64 lanes x 2.4 GHz (one wave64
+    VALU instruction per CU per clock; the FP32 FMA rate without packed FP32)."""
+    rec = _evidence(VALU_FILE)
+    if not rec or cls not in rec["classes"]:
+        return None
+    c = rec["classes"][cls]
+    lane_ops = c["valu_per_wave"] * c["waves_per_launch"] * 64
+    achieved = lane_ops / per_launch_s / 1e12
+    return dict(achieved=round(achieved, 2), peak=VALU_PEAK_TOPS, unit="T lane-instr/s",
+                frac=round(achieved / VALU_PEAK_TOPS, 4), valu_per_wave=c["valu_per_wave"])
+
+
+def class_rooflines(p, prof, steps, sor_half):
+    """Per kernel class: algorithmic bytes per step over its time per step against
+    HBM peak, the measured traffic, and (from the VALU counter record) the issue
+    rate; `bound` is the roof the kernel is nearer to."""
+    N = p["nx"] * p["ny"] * p["nz"]
+    out = {}
+    for cls, (ms, launches) in prof.items():
+        if cls == "other" or launches == 0 or ms <= 0:
+            continue
+        per_step_s = ms / steps / 1e3
+        if cls == "sor":
+            nbytes = sor_half * algorithmic_bytes("sor", p) * N
+        else:
+            nbytes = algorithmic_bytes(cls, p) * N * launches / steps
+        ach = nbytes / per_step_s / 1e9
+        r = dict(achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
+                 ms_per_step=round(ms / steps, 4), algorithmic_bytes_per_step=nbytes)
+        t = traffic_for(cls)
+        r["traffic_per_launch"] = t
+        v = _valu_roof(cls, ms / launches / 1e3)
+        if v:
+            r["valu"] = v
+        r["bound"] = "alu" if v and v["frac"] > r["frac"] else "hbm"
+        if cls == "sor":
+            r["half_sweeps_with_work"] = sor_half
+            r["launches_per_step"] = round(launches / steps, 2)
+        out[cls] = r
+    return out
+
+
+def headline_roofline(p, kname, per_launch_ms, launches_per_step, share, ms_step):
+    """The longest single-pass kernel, timed alone: against HBM with its
+    algorithmic bytes and, where the VALU counters show the issue rate is the
+    nearer roof, against that (bound "alu")."""
+    N = p["nx"] * p["ny"] * p["nz"]
+    abytes = algorithmic_bytes(kname, p) * N
+    hbm = abytes / (per_launch_ms / 1e3) / 1e9
+    v = _valu_roof(kname, per_launch_ms / 1e3)
+    common = dict(kernel=kname, traffic=traffic_for(kname, launches_per_step), algorithmic_bytes_per_launch=abytes,
+                  mean_launch_us=round(per_launch_ms * 1e3, 2), share_of_step=round(share, 3),
+                  timed_region_ms_per_step=round(ms_step, 4),
+                  hbm=dict(achieved=round(hbm, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(hbm / HBM_PEAK_GBS, 4)))
+    if v and v["frac"] > hbm / HBM_PEAK_GBS:
+        return dict(bound="alu", achieved=v["achieved"], peak=v["peak"], unit=v["unit"], frac=v["frac"],
+                    valu_per_wave=v["valu_per_wave"], **common)
+    return dict(bound="hbm", achieved=round(hbm, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(hbm / HBM_PEAK_GBS, 4), **common)
+
+
+def accuracy_report(workload, precision, steps):
+    """The benchmarked mode and the other deviation mode against the plain FP32
+    GPU solver and the FP64 GPU solver (which matches the FP64 oracle to 1e-10)
+    on the same workload after the same number of steps: max-norm errors
+    relative to the reference field's largest magnitude, and RMS errors."""
+    import workloads as W
+    from paper_2311_15242_amd import lbfd
+
+    def fields(prec):
+        pp, qq = W.config(workload, prec)
+        s = lbfd.Solver(pp).init_fields(qq).step(steps)
+        ob = s.observables()
+        f = dict(u=s.field("u"), Gpsi=s.field("G") * s.field("psi"), rhoN=s.field("rhoN"))
+        s.close()
+        return f, ob
+
+    ref, _ = fields("fp64")
+    base, _ = fields("fp32")
+
+    def errs(a, b):
+        out = {}
+        for k in ("u", "Gpsi", "rhoN"):
+            d = np.abs(a[k] - b[k])
+            if d.ndim == 4:
+                d = d.max(0)
+            m = float(np.abs(b[k]).max())
+            out[k] = float(d.max() / m)
+            out[k + "_rms"] = float(np.sqrt((d * d).mean()) / m)
+        return {k: float(f"{v:.3e}") for k, v in out.items()}
+
+    rep = dict(steps=steps, norm="max |a - b| / max |b| per field (u: over components); _rms: RMS / max |b|",
+               target=1e-3, fp32=dict(vs_fp64=errs(base, ref)))
+    for prec in dict.fromkeys([precision, "fp16dev", "bf16dev"]):
+        if prec in ("fp32", "fp64"):
+            continue
+        f, _ = fields(prec)
+        rep[prec] = dict(vs_fp32=errs(f, base), vs_fp64=errs(f, ref))
+    return rep
 
 
 def sweep_budget(p, q, warmup, margin=2):
@@ -883,6 +1109,8 @@ def batch_bench(steps, warmup, sor_sweeps, precision="bf16dev"):
     torch.cuda.synchronize()
     ms_b = ev0.elapsed_time(ev1)
     check(b.members, "in the batched timed region")
+    # the state each instance reached, for the comparison with its sequential run
+    snap = [(m.field("u"), m.field("psi")) for m in b.members]
     b.close()
     del b
 
@@ -897,6 +1125,9 @@ def batch_bench(steps, warmup, sor_sweeps, precision="bf16dev"):
     torch.cuda.synchronize()
     ms_s = ev0.elapsed_time(ev1)
     check(solvers, "in the sequential timed region")
+    diff = 0.0
+    for (u, ps), s in zip(snap, solvers):
+        diff = max(diff, float(np.abs(s.field("u") - u).max()), float(np.abs(s.field("psi") - ps).max()))
     for s in solvers:
         s.close()
     mb = nodes * steps / (ms_b / 1e3) / 1e6
@@ -905,7 +1136,8 @@ def batch_bench(steps, warmup, sor_sweeps, precision="bf16dev"):
                          "Eo and Bi swept)", storage=precision, instances=len(inst), nodes=nodes, steps=steps,
                 batched_mlups=round(mb, 2), sequential_mlups=round(ms, 2), speedup=round(mb / ms, 3),
                 batched_ms_per_step=round(ms_b / steps, 4), sequential_ms_per_step=round(ms_s / steps, 4),
-                sor_sweeps_launched=budget)
+                sor_sweeps_launched=budget, max_abs_diff_vs_sequential=diff,
+                accuracy="u and psi of every instance after warm-up + timed steps: batched - sequential")
 
 
 def main():
@@ -962,9 +1194,17 @@ def main():
                          "copy calibration run) and exit")
     ap.add_argument("--trace-summary", metavar="KERNEL_STATS_CSV",
                     help="print the per-kernel table of a rocprofv3 --kernel-trace --stats run and exit")
-    ap.add_argument("--write-traffic", nargs=6,
-                    metavar=("KERNEL", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "OUT_JSON"),
-                    help="store the measured HBM bytes per launch of one kernel class and exit")
+    ap.add_argument("--write-traffic", nargs=5,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "OUT_JSON"),
+                    help="store the measured HBM bytes per launch of every kernel class and exit")
+    ap.add_argument("--write-valu", nargs=2, metavar=("PMC_CSV", "OUT_JSON"),
+                    help="store VALU instructions per wave of every kernel class (SQ_INSTS_VALU, SQ_WAVES) and exit")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the deviation modes' errors against the FP32 and FP64 GPU solvers")
+    ap.add_argument("--accuracy-steps", type=int, default=500)
+    ap.add_argument("--cpu-windows", action="store_true",
+                    help="time the oracle over the fixed windows (C1 2000, C2 1000, C3 10 + 50 steps) on all host "
+                         "cores and a shortened window on one thread, print a table and exit")
     args = ap.parse_args()
     if args.pmc_summary:
         print(pmc_summary(*args.pmc_summary))
@@ -974,6 +1214,12 @@ def main():
         return
     if args.write_traffic:
         print(json.dumps(write_traffic(*args.write_traffic)))
+        return
+    if args.write_valu:
+        print(json.dumps(write_valu(*args.write_valu)))
+        return
+    if args.cpu_windows:
+        print(cpu_windows(), flush=True)
         return
     if args.copy_calibration:
         import torch
@@ -1026,36 +1272,36 @@ def main():
     p["sor_max_sweeps"] = sweep_budget(p, q, args.warmup) if args.sor_sweeps == "auto" else int(args.sor_sweeps)
     N = p["nx"] * p["ny"] * p["nz"]
 
-    # 1) plain timed region: the headline value
-    ms_plain, _, ob = timed_run(p, q, args.steps, args.warmup, profile=False)
+    # 1) the headline: the median of TIMED_REGIONS timed regions of K steps each
+    ms_plain, _, ob, runs = timed_run(p, q, args.steps, args.warmup, profile=False, regions=TIMED_REGIONS)
     value = N * args.steps / (ms_plain / 1e3) / 1e6
     # 2) every kernel class timed (breakdown; the events add some overhead)
-    ms_prof, prof, _ = timed_run(p, q, args.steps, args.warmup, profile=True)
-    # 3) the dominant single-pass kernel timed alone, for the roofline
+    ms_prof, prof, _, _ = timed_run(p, q, args.steps, args.warmup, profile=True)
+    # 3) the longest single-pass kernel timed alone, for the headline roofline
     kname = max((k for k in prof if k not in ("sor", "total", "other")), key=lambda k: prof[k][0])
-    ms_k, prof_k, _ = timed_run(p, q, args.steps, args.warmup, profile=True, only=[kname])
+    ms_k, prof_k, _, _ = timed_run(p, q, args.steps, args.warmup, profile=True, only=[kname])
     kms, klaunch = prof_k[kname]
     per_launch_ms = kms / max(klaunch, 1)
-    abytes = algorithmic_bytes(kname, p) * N
-    achieved = abytes / (per_launch_ms / 1e3) / 1e9
     launches_per_step = klaunch / args.steps
-    roof = dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_for(kname, launches_per_step),
-                algorithmic_bytes_per_launch=abytes, mean_launch_us=round(per_launch_ms * 1e3, 2),
-                share_of_step=round(kms / ms_k, 3), timed_region_ms_per_step=round(ms_k / args.steps, 4))
+    sor_half = sor_half_sweeps(p, ob)
+    rooflines = class_rooflines(p, prof, args.steps, sor_half)
+    roof = headline_roofline(p, kname, per_launch_ms, launches_per_step, kms / ms_k, ms_k / args.steps)
     breakdown = {k: dict(ms_per_step=round(v[0] / args.steps, 4), launches_per_step=round(v[1] / args.steps, 2),
-                         gbs=round(algorithmic_bytes(k, p) * N * v[1] / (v[0] / 1e3) / 1e9, 1) if v[0] > 0 else 0.0)
+                         gbs=rooflines[k]["achieved"] if k in rooflines else 0.0)
                  for k, v in prof.items() if v[1] > 0}
 
     # whole-step bandwidth: the algorithmic bytes of every kernel of one step (SOR
-    # half-sweeps counted for the sweeps that ran) x lattice updates per second
-    sweeps_run = max(ob["sor_sweeps"]) + 1 if p["fd_enable"] else 0
+    # half-sweeps counted for those that ran) x lattice updates per second
     step_bytes = sum(algorithmic_bytes(k, p) for k in ("collide", "macro", "geom", "force")) + \
-        (algorithmic_bytes("fd", p) + algorithmic_bytes("total", p) + 2 * sweeps_run * algorithmic_bytes("sor", p)
+        (algorithmic_bytes("fd", p) + algorithmic_bytes("total", p) + sor_half * algorithmic_bytes("sor", p)
          if p["fd_enable"] else 0.0)
     step_gbs = step_bytes * value * 1e6 / 1e9
-    step_bw = dict(bytes_per_lup=round(step_bytes, 1), sor_half_sweeps_counted=2 * sweeps_run,
+    step_bw = dict(bytes_per_lup=round(step_bytes, 1), sor_half_sweeps_counted=sor_half,
                    achieved=round(step_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(step_gbs / HBM_PEAK_GBS, 4))
+    # useful bandwidth: the minimum state of a two-colour method per update x updates per second
+    ub = USEFUL_BYTES[(p["lattice"], p["precision"])]
+    useful = dict(bytes_per_lup=ub, achieved=round(ub * value / 1e3, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                  frac=round(ub * value / 1e3 / HBM_PEAK_GBS, 4))
     out = dict(metric="MLUPS (LBM+FD step)", value=round(value, 2), unit="MLUPS", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_plain / args.steps, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32" if p["precision"] != "fp64" else "f64",
@@ -1064,8 +1310,12 @@ def main():
                            grid=[p["nx"], p["ny"], p["nz"]], storage=p["precision"],
                            sor_sweeps_launched=p["sor_max_sweeps"], sor_sweeps_used=ob["sor_sweeps"],
                            parallelism="single GPU"),
-               roofline=roof, step_bandwidth=step_bw, kernels=breakdown,
-               ms_per_step_profiled=round(ms_prof / args.steps, 4))
+               timed_regions=dict(count=TIMED_REGIONS, statistic="median",
+                                  mlups=[round(N * args.steps / (r / 1e3) / 1e6, 1) for r in runs]),
+               roofline=roof, rooflines=rooflines, step_bandwidth=step_bw, useful_bandwidth=useful,
+               kernels=breakdown, ms_per_step_profiled=round(ms_prof / args.steps, 4))
+    if not args.no_accuracy:
+        out["accuracy"] = accuracy_report(args.workload, p["precision"], args.accuracy_steps)
 
     if not args.no_secondary:
         sec = {}
@@ -1074,7 +1324,7 @@ def main():
             pp, qq = W.config(name, prec)
             pp["sor_max_sweeps"] = sweep_budget(pp, qq, 20) if args.sor_sweeps == "auto" else int(args.sor_sweeps)
             nn = pp["nx"] * pp["ny"] * pp["nz"]
-            ms2, _, ob2 = timed_run(pp, qq, 200, 20, profile=False)
+            ms2, _, ob2, _ = timed_run(pp, qq, 200, 20, profile=False)
             sec[f"{name}_{prec}"] = dict(mlups=round(nn * 200 / (ms2 / 1e3) / 1e6, 2),
                                          ms_per_step=round(ms2 / 200, 4), sor_sweeps_used=ob2["sor_sweeps"],
                                          sor_sweeps_launched=pp["sor_max_sweeps"])
