@@ -380,10 +380,17 @@ template <int LAT, class P> __device__ __forceinline__ void geom_body(const KP<t
         g[a] = lat_deriv<LAT, R>(nb, rN, n, R(1), a, -1);
         G2 += g[a] * g[a];
     }
-    st(k.fld.G[level], n, sqrt(G2));
+    const R G = sqrt(G2);
+    st(k.fld.G[level], n, G);
     R den = sqrt(G2 + k.eps_n * k.eps_n);
 #pragma unroll
     for (int a = 0; a < L::D; ++a) st(k.fld.nrm + a * N, n, den > R(0) ? -g[a] / den : R(0));
+    // node weights of the implicit systems at this level, W = G + eps (psi) and
+    // X + eps = 1 - rhoN + eps (phi), in the solve's colour-split arrays: the level
+    // a geometry launch computes is always the one the next solve needs
+    const uint32_t j = split_idx(k, nd.x, nd.y, nd.z);
+    st(k.fld.cwP, j, G + k.fd_eps);
+    st(k.fld.cwF, j, (R(1) - ld(rN, n)) + k.fd_eps);
 }
 template <int LAT, class P> __global__ __launch_bounds__(256) void k_geom(KP<typename P::R> k, int level)
 {
@@ -975,8 +982,6 @@ template <int LAT, class P> __device__ __forceinline__ void fd_body(const KP<typ
         }
     const R rhP = Gn * psi + R(0.5) * k.Ds * (swcP - swP * psi) + eS;
     const R rhF = Xn * phi + R(0.5) * k.Db * (swcF - swF * phi) + eB;
-    st(k.fld.rhsP, n, rhP);
-    st(k.fld.rhsF, n, rhF);
     st(k.fld.Sp, n, Sn);
     st(k.fld.Bp, n, Bn);
     // initial guess of the implicit solve: linear extrapolation from the two
@@ -987,8 +992,13 @@ template <int LAT, class P> __device__ __forceinline__ void fd_body(const KP<typ
         psig = R(2) * psi - sp * ld(k.fld.psi[1 - sa.pc], n);
         phig = R(2) * phi - sp * ld(k.fld.phi[1 - sa.pc], n);
     }
-    st(k.fld.psi[1 - sa.pc], n, psig);
-    st(k.fld.phi[1 - sa.pc], n, phig);
+    // the solve's right-hand sides and initial guesses in its colour-split arrays
+    // (the geometry kernel of the new level wrote the node weights there)
+    const uint32_t j = split_idx(k, x, y, z);
+    st(k.fld.rhsP, j, rhP);
+    st(k.fld.rhsF, j, rhF);
+    st(k.fld.csP, j, psig);
+    st(k.fld.csF, j, phig);
 }
 template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typename P::R> k)
 {
@@ -1047,85 +1057,104 @@ template <int D, class R> __device__ __forceinline__ bool on_seam(const KP<R> &k
            (D == 3 && (k.seam & 4) && z == k.nz - 1);
 }
 
-// Operands of the implicit systems at this step, resolved once per workgroup.
+// Operands of the implicit systems at this step (colour-split arrays).
 template <class R> struct SorOps {
-    const R *G1, *rN1;   // W = G^{n+1} + eps (psi) and X^{n+1} + eps from rhoN^{n+1} (phi)
+    const R *wP, *wF;    // node weights W = G^{n+1} + eps (psi) and X^{n+1} + eps (phi)
     R *psi, *phi;        // iterates (initial guess on entry)
     const R *rhsP, *rhsF;
-    R eps, hdP, hdF, om;
+    R hdP, hdF, om;
 };
-template <class R> __device__ __forceinline__ SorOps<R> sor_ops(const KP<R> &k, const StepArgs &sa)
+template <class R> __device__ __forceinline__ SorOps<R> sor_ops(const KP<R> &k, const StepArgs &)
 {
     SorOps<R> a;
-    a.G1 = k.fld.G[1 - sa.lev];
-    a.rN1 = k.fld.mac[1 - sa.lev] + 2 * k.N;
-    a.psi = k.fld.psi[1 - sa.pc];
-    a.phi = k.fld.phi[1 - sa.pc];
+    a.wP = k.fld.cwP;
+    a.wF = k.fld.cwF;
+    a.psi = k.fld.csP;
+    a.phi = k.fld.csF;
     a.rhsP = k.fld.rhsP;
     a.rhsF = k.fld.rhsF;
-    a.eps = k.fd_eps;
     a.hdP = R(0.5) * k.Ds;
     a.hdF = R(0.5) * k.Db;
     a.om = k.omega;
     return a;
 }
 
+// Operands of one SOR row, loaded before any update is stored: the two systems'
+// loads are then in flight together instead of the second system's waiting
+// behind the first one's store (the arrays could alias as far as the compiler
+// knows).
+template <class R, int NF> struct SorRow {
+    R Wn, Wf[NF], cf[NF], rhs, c0;
+};
+template <class R, int NF>
+__device__ __forceinline__ void sor_load(SorRow<R, NF> &o, const R *W, const R *chi, const R *rhsA, uint32_t n,
+                                         const uint32_t *q, const bool *on)
+{
+    o.Wn = ld(W, n);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        o.Wf[f] = on[f] ? ld(W, q[f]) : R(0);
+        o.cf[f] = on[f] ? ld(chi, q[f]) : R(0);
+    }
+    o.rhs = ld(rhsA, n);
+    o.c0 = ld(chi, n);
+}
+
+// The update: diag = W_n + sum_f w_f, off = sum_f w_f chi_f over the faces present
+// (a wall face carries no flux), w_f = (Dc/2) (W_n + W_f)/2; the pre-update
+// residual |rhs - (diag chi - off)| and |rhs| feed the maxima.
+template <class R, int NF>
+__device__ __forceinline__ R sor_update(const SorRow<R, NF> &o, const bool *on, R hd, R om, R &rmax, R &bmax)
+{
+    R diag = o.Wn, off = 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        if (!on[f]) continue;
+        const R wf = hd * (R(0.5) * (o.Wn + o.Wf[f]));
+        diag += wf;
+        off += wf * o.cf[f];
+    }
+    rmax = fmax(rmax, fabs(o.rhs - (diag * o.c0 - off)));
+    bmax = fmax(bmax, fabs(o.rhs));
+    return (R(1) - om) * o.c0 + om * (o.rhs + off) / diag;
+}
+
 // One SOR update of node (x, y, z) in both implicit systems (a converged system is
-// left alone), recording its pre-update residual and |rhs|.
+// left alone), recording its pre-update residual and |rhs|. Face neighbours in the
+// interior lie in the other colour plane at the same row offset; across a periodic
+// wrap the neighbour's own parity decides its plane (an odd extent keeps it).
 template <int LAT, class P>
 __device__ __forceinline__ void sor_node(const KP<typename P::R> &k, const SorOps<typename P::R> &a, int x, int y,
                                          int z, const bool *conv, typename P::R *rloc, typename P::R *bloc)
 {
     using R = typename P::R;
-    using L = Lat<LAT>;
-    constexpr int D = L::D;
+    constexpr int D = Lat<LAT>::D, NF = 2 * D;
     const int nx = k.nx, ny = k.ny, nz = k.nz;
-    const int sy = nx, sz = nx * ny;
-    const R *G1 = a.G1, *rN1 = a.rN1;
-    R *psi = a.psi, *phi = a.phi;
-    const R *rhsP = a.rhsP, *rhsF = a.rhsF;
-    const R eps = a.eps, hdP = a.hdP, hdF = a.hdF, om = a.om;
-    const uint32_t n = (uint32_t)(x + sy * y + sz * z);
-    // face neighbours: periodic wrap, or the node itself across a wall (no flux)
+    const uint32_t n = split_idx(k, x, y, z);
+    const uint32_t hx = k.hx, sz = k.hx * (uint32_t)ny;
+    // the same x >> 1 in the other colour plane
+    const uint32_t o = ((x + y + z) & 1) ? n - k.hn : n + k.hn;
     uint32_t q[6];
-    q[0] = x > 0 ? n - 1 : (k.bc[0] ? n : n + (nx - 1));
-    q[1] = x < nx - 1 ? n + 1 : (k.bc[0] ? n : n - (nx - 1));
-    q[2] = y > 0 ? n - sy : (k.bc[1] ? n : n + sy * (ny - 1));
-    q[3] = y < ny - 1 ? n + sy : (k.bc[1] ? n : n - sy * (ny - 1));
+    bool on[6];
+    on[0] = x > 0 || !k.bc[0];
+    q[0] = x > 0 ? o - (uint32_t)(x >> 1) + (uint32_t)((x - 1) >> 1) : split_idx(k, nx - 1, y, z);
+    on[1] = x < nx - 1 || !k.bc[0];
+    q[1] = x < nx - 1 ? o - (uint32_t)(x >> 1) + (uint32_t)((x + 1) >> 1) : split_idx(k, 0, y, z);
+    on[2] = y > 0 || !k.bc[1];
+    q[2] = y > 0 ? o - hx : split_idx(k, x, ny - 1, z);
+    on[3] = y < ny - 1 || !k.bc[1];
+    q[3] = y < ny - 1 ? o + hx : split_idx(k, x, 0, z);
     if constexpr (D == 3) {
-        q[4] = z > 0 ? n - sz : (k.bc[2] ? n : n + sz * (nz - 1));
-        q[5] = z < nz - 1 ? n + sz : (k.bc[2] ? n : n - sz * (nz - 1));
+        on[4] = z > 0 || !k.bc[2];
+        q[4] = z > 0 ? o - sz : split_idx(k, x, y, nz - 1);
+        on[5] = z < nz - 1 || !k.bc[2];
+        q[5] = z < nz - 1 ? o + sz : split_idx(k, x, y, 0);
     }
-    if (!conv[0]) {
-        const R Wn = ld(G1, n) + eps;
-        R diag = Wn, off = 0;
-#pragma unroll
-        for (int f = 0; f < 2 * D; ++f) {
-            if (q[f] == n) continue;
-            const R wf = hdP * (R(0.5) * (Wn + (ld(G1, q[f]) + eps)));
-            diag += wf;
-            off += wf * ld((const R *)psi, q[f]);
-        }
-        const R rhs = ld(rhsP, n), c0 = ld((const R *)psi, n);
-        rloc[0] = fmax(rloc[0], fabs(rhs - (diag * c0 - off)));
-        bloc[0] = fmax(bloc[0], fabs(rhs));
-        st(psi, n, (R(1) - om) * c0 + om * (rhs + off) / diag);
-    }
-    if (!conv[1]) {
-        const R Wn = (R(1) - ld(rN1, n)) + eps;
-        R diag = Wn, off = 0;
-#pragma unroll
-        for (int f = 0; f < 2 * D; ++f) {
-            if (q[f] == n) continue;
-            const R wf = hdF * (R(0.5) * (Wn + ((R(1) - ld(rN1, q[f])) + eps)));
-            diag += wf;
-            off += wf * ld((const R *)phi, q[f]);
-        }
-        const R rhs = ld(rhsF, n), c0 = ld((const R *)phi, n);
-        rloc[1] = fmax(rloc[1], fabs(rhs - (diag * c0 - off)));
-        bloc[1] = fmax(bloc[1], fabs(rhs));
-        st(phi, n, (R(1) - om) * c0 + om * (rhs + off) / diag);
-    }
+    SorRow<R, NF> rp, rf;
+    if (!conv[0]) sor_load(rp, a.wP, (const R *)a.psi, a.rhsP, n, q, on);
+    if (!conv[1]) sor_load(rf, a.wF, (const R *)a.phi, a.rhsF, n, q, on);
+    if (!conv[0]) st(a.psi, n, sor_update(rp, on, a.hdP, a.om, rloc[0], bloc[0]));
+    if (!conv[1]) st(a.phi, n, sor_update(rf, on, a.hdF, a.om, rloc[1], bloc[1]));
 }
 
 // One tile of a colour half-sweep: 256 consecutive entries of the colour's index
@@ -1443,7 +1472,7 @@ template <int NV> __device__ __forceinline__ void block_sum_store(double (&v)[NV
 // at `level`, psi/phi from buffer `buf` times `mult`.
 template <int LAT, class P>
 __device__ __forceinline__ void total_part_body(const KP<typename P::R> &k, int level, int buf, double mult, int blk,
-                                                int nblk)
+                                                int nblk, int from_split)
 {
     using R = typename P::R;
     const long long N = k.N;
@@ -1452,24 +1481,38 @@ __device__ __forceinline__ void total_part_body(const KP<typename P::R> &k, int 
         const uint32_t i = (uint32_t)n;
         double G = (double)(ld(k.fld.G[level], i) + k.fd_eps);
         double X = (double)((R(1) - ld(k.fld.mac[level] + 2 * N, i)) + k.fd_eps);
-        double ps = mult * (double)ld(k.fld.psi[buf], i), ph = mult * (double)ld(k.fld.phi[buf], i);
-        v[0] += G * ps + X * ph;
+        R vp, vf;
+        if (from_split) {
+            // after the solve: its colour-split iterates become the new level in node order
+            const uint32_t yz = udiv(i, (uint32_t)k.nx, k.inv_nx);
+            const uint32_t z = udiv(yz, (uint32_t)k.ny, k.inv_ny);
+            const uint32_t j = split_idx(k, (int)(i - yz * (uint32_t)k.nx), (int)(yz - z * (uint32_t)k.ny), (int)z);
+            vp = ld((const R *)k.fld.csP, j);
+            vf = ld((const R *)k.fld.csF, j);
+            st(k.fld.psi[buf], i, vp);
+            st(k.fld.phi[buf], i, vf);
+        } else {
+            vp = ld(k.fld.psi[buf], i);
+            vf = ld(k.fld.phi[buf], i);
+        }
+        v[0] += G * (mult * (double)vp) + X * (mult * (double)vf);
     }
     block_sum_store<1>(v, k.fld.part + blk);
 }
 template <int LAT, class P>
-__global__ __launch_bounds__(256) void k_total_part(KP<typename P::R> k, int level, int buf, double mult)
+__global__ __launch_bounds__(256) void k_total_part(KP<typename P::R> k, int level, int buf, double mult,
+                                                   int from_split)
 {
-    total_part_body<LAT, P>(k, level, buf, mult, (int)blockIdx.x, (int)gridDim.x);
+    total_part_body<LAT, P>(k, level, buf, mult, (int)blockIdx.x, (int)gridDim.x, from_split);
 }
 // batch: instance i owns workgroups prefix[i] .. prefix[i+1]-1
 template <int LAT, class P>
 __global__ __launch_bounds__(256) void kb_total_part(const KP<typename P::R> *tab, const int *prefix, int ninst,
-                                                    int level, int buf, double mult)
+                                                    int level, int buf, double mult, int from_split)
 {
     int inst, local;
     batch_tile(prefix, ninst, inst, local);
-    total_part_body<LAT, P>(tab[inst], level, buf, mult, local, prefix[inst + 1] - prefix[inst]);
+    total_part_body<LAT, P>(tab[inst], level, buf, mult, local, prefix[inst + 1] - prefix[inst], from_split);
 }
 template <class R> __device__ __forceinline__ void total_final_body(const KP<R> &k, long long nblocks, int mode)
 {
@@ -1739,7 +1782,8 @@ size_t pop_bytes(int prec) { return prec == LBFD_FP64 ? 8 : prec == LBFD_FP32 ? 
 size_t real_bytes(int prec) { return prec == LBFD_FP64 ? 8 : 4; }
 
 struct Layout {
-    size_t f[2], mac[2], desc, G[2], nrm, u, F, qf, sorres, psi[2], phi[2], Sp, Bp, rhsP, rhsF, part, sc, obs, total;
+    size_t f[2], mac[2], desc, G[2], nrm, u, F, qf, sorres, psi[2], phi[2], Sp, Bp, rhsP, rhsF, csP, csF, cwP, cwF,
+        part, sc, obs, total;
 };
 
 Layout layout(const lbfd_params *p)
@@ -1765,8 +1809,14 @@ Layout layout(const lbfd_params *p)
     for (int b = 0; b < 2; ++b) L.phi[b] = take(sr * N);
     L.Sp = take(sr * N);
     L.Bp = take(sr * N);
-    L.rhsP = take(sr * N);
-    L.rhsF = take(sr * N);
+    // arrays of the implicit solve, two colour planes of ((nx + 1) / 2) ny nz entries each
+    const long long NS = 2LL * ((p->nx + 1) / 2) * p->ny * p->nz;
+    L.rhsP = take(sr * NS);
+    L.rhsF = take(sr * NS);
+    L.csP = take(sr * NS);
+    L.csF = take(sr * NS);
+    L.cwP = take(sr * NS);
+    L.cwF = take(sr * NS);
     const size_t npart = (size_t)NRED * (size_t)nblocks;
     L.part = take(sizeof(double) * (npart > (size_t)TOTAL_BLOCKS ? npart : (size_t)TOTAL_BLOCKS));
     L.sc = take(sizeof(DevScalars));
@@ -1908,6 +1958,9 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
     k.seam = seam_axes(p);
     k.inv_hx = 1.0 / (double)((p->nx + 1) / 2);
     k.inv_ny = 1.0 / (double)p->ny;
+    k.inv_nx = 1.0 / (double)p->nx;
+    k.hx = (uint32_t)((p->nx + 1) / 2);
+    k.hn = k.hx * (uint32_t)p->ny * (uint32_t)p->nz;
     k.sor_exact = (p->sor_omega == 1.0 && k.seam == 0) ? 1 : 0;
     k.weno_eps = (R)p->weno_eps;
     k.eps_n = (R)p->eps_n;
@@ -1933,6 +1986,10 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
     F.Bp = (R *)(ws + Lo.Bp);
     F.rhsP = (R *)(ws + Lo.rhsP);
     F.rhsF = (R *)(ws + Lo.rhsF);
+    F.csP = (R *)(ws + Lo.csP);
+    F.csF = (R *)(ws + Lo.csF);
+    F.cwP = (R *)(ws + Lo.cwP);
+    F.cwF = (R *)(ws + Lo.cwF);
     F.part = (double *)(ws + Lo.part);
     F.sc = (DevScalars *)(ws + Lo.sc);
 }
@@ -2010,10 +2067,12 @@ template <int LAT, class P> struct Impl {
         k.nsweeps = h->sweeps_launch;
     }
 
-    static void totals(lbfd_handle *h, int level, int buf, double mult, int mode)
+    // Total of level `level` with psi, phi of buffer `buf` (from_split: take them from
+    // the solve's colour-split iterates and store them into `buf` on the way).
+    static void totals(lbfd_handle *h, int level, int buf, double mult, int mode, int from_split = 0)
     {
         KP<R> &k = kp(h);
-        LAUNCH(KC_TOTAL, (k_total_part<LAT, P>), dim3(h->tblocks), dim3(256), k, level, buf, mult);
+        LAUNCH(KC_TOTAL, (k_total_part<LAT, P>), dim3(h->tblocks), dim3(256), k, level, buf, mult, from_split);
         LAUNCH(KC_TOTAL, (k_total_final<R>), dim3(1), dim3(256), k, (long long)h->tblocks, mode);
     }
 
@@ -2141,7 +2200,7 @@ template <int LAT, class P> struct Impl {
             }
         }
         LAUNCH(KC_OTHER, (k_sor_done<R>), dim3(1), dim3(64), k, h->sweeps_launch);
-        totals(h, 1 - k.lev, 1 - k.pc, 1.0, 1);
+        totals(h, 1 - k.lev, 1 - k.pc, 1.0, 1, 1);
         h->pc = 1 - h->pc;
         h->fd_hist += 1;
         sync_levels(h);
@@ -2282,7 +2341,7 @@ template <int LAT, class P> struct Impl {
                 }
                 LAUNCH(KC_OTHER, (kb_sor_done<R>), dim3(n), dim3(64), tab, h->sweeps_launch);
                 LAUNCH(KC_TOTAL, (kb_total_part<LAT, P>), b->grid_total, dim3(256), tab, b->prefix_total, n,
-                       1 - sa.lev, 1 - sa.pc, 1.0);
+                       1 - sa.lev, 1 - sa.pc, 1.0, 1);
                 LAUNCH(KC_TOTAL, (kb_total_final<R>), dim3(n), dim3(256), tab, b->prefix_total, 1);
             }
             for (lbfd_handle *x : b->inst) {

@@ -204,7 +204,10 @@ template <class R> struct Fields {
     R *qf;
     R *psi[2];
     R *phi[2];
-    R *Sp, *Bp, *rhsP, *rhsF;
+    R *Sp, *Bp;
+    // The implicit solve works on colour-split arrays (split_idx): right-hand
+    // sides, iterates and node weights W = G + eps, X + eps of both systems
+    R *rhsP, *rhsF, *csP, *csF, *cwP, *cwF;
     double *part;   // reduction partials
     unsigned long long *sorres;  // residual and |rhs| maxima per field, sweep and slot (bits of doubles)
     DevScalars *sc;
@@ -239,6 +242,8 @@ template <class R> struct KP {
     R tol;
     int seam;           // periodic axes of odd extent (bit a): seam classes of the SOR ordering
     double inv_hx, inv_ny;  // 1 / ((nx + 1) / 2) and 1 / ny for the SOR index arithmetic
+    double inv_nx;          // 1 / nx
+    uint32_t hx, hn;        // (nx + 1) / 2 and hx ny nz: row length and size of a colour plane
     int sor_exact;      // omega = 1 without seam classes: the red residual is the whole residual
     R weno_eps, eps_n;
     R fd_eps;           // background support of the FD weights
@@ -465,6 +470,15 @@ __device__ __forceinline__ bool nb_wall(const Nbhd &b, int ex, int ey, int ez)
 __device__ __forceinline__ bool nb_wall_axis(const Nbhd &b, int a, int ea)
 {
     return ea != 0 && ((b.mir >> (a * 4 + slot_of(ea))) & 1u);
+}
+
+// Colour-split index of node (x, y, z) in the arrays of the implicit solve: each
+// parity class (x + y + z) & 1 in a plane of its own, at (x >> 1) + hx (y + ny z).
+// A colour half-sweep then reads and writes whole lines of its own plane and
+// reads its face neighbours from whole lines of the other one.
+template <class R> __device__ __forceinline__ uint32_t split_idx(const KP<R> &k, int x, int y, int z)
+{
+    return (uint32_t)((x + y + z) & 1) * k.hn + (uint32_t)(x >> 1) + k.hx * (uint32_t)(y + k.ny * z);
 }
 
 // Isotropic lattice derivative (the stencil with which eq 9 evaluates every
