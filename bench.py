@@ -107,25 +107,26 @@ def algorithmic_bytes(kernel: str, p: dict) -> float:
     return float(table.get(kernel, 0.0))
 
 
-def build_solver(p, q):
+def build_solver(p, q, tuning="auto"):
     from paper_2311_15242_amd import lbfd
 
-    return lbfd.Solver(p).init_fields(q)
+    return lbfd.Solver(p, tuning=tuning).init_fields(q)
 
 
-def timed_run(p, q, steps, warmup, profile, only=None, regions=1):
+def timed_run(p, q, steps, warmup, profile, only=None, regions=1, tuning="auto"):
     """Warm-up, then `regions` timed regions of `steps` steps each on the same
     solver (HIP events on its stream, synchronised on both sides). Returns the
     median region's milliseconds, the profile of all regions, the observables
     and every region's milliseconds."""
     import torch
 
-    s = build_solver(p, q)
+    s = build_solver(p, q, tuning)
     s.step(warmup)
     torch.cuda.synchronize()
     ob = s.observables()
     if ob["status"] != 0:
         raise RuntimeError(f"solver status {ob['status']} after warm-up")
+    timed_run.shape = s.get_tuning()
     if profile:
         s.profile(True, only=only)
     a = torch.cuda.Event(enable_timing=True)
@@ -1000,6 +1001,31 @@ def headline_roofline(p, kname, per_launch_ms, launches_per_step, share, ms_step
                 frac=round(hbm / HBM_PEAK_GBS, 4), **common)
 
 
+def autotune(out_path, workload, precision, warmup):
+    """Tune the launch shapes of the headline workload (with its measured SOR
+    launch budget) and of the 64-instance batch; write the table."""
+    import workloads as W
+    from paper_2311_15242_amd import autotune as T
+
+    p, q = W.config(workload, precision)
+    p["sor_max_sweeps"] = sweep_budget(p, q, max(warmup, 5))
+    res = [T.tune_solver(p, q)]
+    print(f"[autotune] {res[-1]['key']}: {res[-1]['tuning']} {res[-1]['ms_per_step']} ms "
+          f"(default {res[-1]['default_ms_per_step']} ms)", file=sys.stderr, flush=True)
+    inst = W.batch_instances(W.load_manifest(), precision="bf16dev")
+    plist = [dict(pp) for pp, _ in inst]
+    for pp in plist:
+        pp["sor_max_sweeps"] = 6
+    res.append(T.tune_batch(plist, [qq for _, qq in inst]))
+    print(f"[autotune] {res[-1]['key']}: {res[-1]['tuning']} {res[-1]['ms_per_step']} ms "
+          f"(default {res[-1]['default_ms_per_step']} ms)", file=sys.stderr, flush=True)
+    import torch
+
+    T.write(res, out_path, device=torch.cuda.get_device_name(0))
+    return dict(written=out_path, entries=[dict(key=r["key"], tuning=r["tuning"], ms_per_step=r["ms_per_step"],
+                                                default_ms_per_step=r["default_ms_per_step"]) for r in res])
+
+
 def accuracy_report(workload, precision, steps):
     """The benchmarked mode and the other deviation mode against the plain FP32
     GPU solver and the FP64 GPU solver (which matches the FP64 oracle to 1e-10)
@@ -1073,8 +1099,8 @@ def batch_bench(steps, warmup, sor_sweeps, precision="bf16dev"):
     inst = W.batch_instances(W.load_manifest(), precision=precision)
     nodes = sum(p["nx"] * p["ny"] * p["nz"] for p, _ in inst)
 
-    def new_batch():
-        b = lbfd.Batch([p for p, _ in inst])
+    def new_batch(tuning="auto"):
+        b = lbfd.Batch([p for p, _ in inst], tuning=tuning)
         for m, (_, q) in zip(b.members, inst):
             m.init_fields(q)
         return b
@@ -1111,6 +1137,19 @@ def batch_bench(steps, warmup, sor_sweeps, precision="bf16dev"):
     check(b.members, "in the batched timed region")
     # the state each instance reached, for the comparison with its sequential run
     snap = [(m.field("u"), m.field("psi")) for m in b.members]
+    bkey = b.key
+    b.close()
+    del b
+    # the same batch in the library's default launch shape
+    b = new_batch(tuning=None)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    ev0.record()
+    b.step(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_bf = ev0.elapsed_time(ev1)
+    check(b.members, "in the fixed-shape batched timed region")
     b.close()
     del b
 
@@ -1137,6 +1176,9 @@ def batch_bench(steps, warmup, sor_sweeps, precision="bf16dev"):
                 batched_mlups=round(mb, 2), sequential_mlups=round(ms, 2), speedup=round(mb / ms, 3),
                 batched_ms_per_step=round(ms_b / steps, 4), sequential_ms_per_step=round(ms_s / steps, 4),
                 sor_sweeps_launched=budget, max_abs_diff_vs_sequential=diff,
+                tuning=dict(key=bkey, shape=lbfd.tuned_shape(bkey) or lbfd.DEFAULT_TUNING,
+                            fixed_mlups=round(nodes * steps / (ms_bf / 1e3) / 1e6, 2),
+                            tuned_over_fixed=round(ms_bf / ms_b, 4)),
                 accuracy="u and psi of every instance after warm-up + timed steps: batched - sequential")
 
 
@@ -1202,6 +1244,9 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the deviation modes' errors against the FP32 and FP64 GPU solvers")
     ap.add_argument("--accuracy-steps", type=int, default=500)
+    ap.add_argument("--autotune", metavar="OUT_JSON",
+                    help="tune the launch shapes of the headline workload and of the 64-instance batch, write "
+                         "the table to OUT_JSON and exit")
     ap.add_argument("--cpu-windows", action="store_true",
                     help="time the oracle over the fixed windows (C1 2000, C2 1000, C3 10 + 50 steps) on all host "
                          "cores and a shortened window on one thread, print a table and exit")
@@ -1220,6 +1265,9 @@ def main():
         return
     if args.cpu_windows:
         print(cpu_windows(), flush=True)
+        return
+    if args.autotune:
+        print(json.dumps(autotune(args.autotune, args.workload, args.precision, args.warmup)), flush=True)
         return
     if args.copy_calibration:
         import torch
@@ -1272,9 +1320,16 @@ def main():
     p["sor_max_sweeps"] = sweep_budget(p, q, args.warmup) if args.sor_sweeps == "auto" else int(args.sor_sweeps)
     N = p["nx"] * p["ny"] * p["nz"]
 
-    # 1) the headline: the median of TIMED_REGIONS timed regions of K steps each
+    # 1) the headline: the median of TIMED_REGIONS timed regions of K steps each, in
+    #    the tuned launch shape (the autotuner's table; the defaults where it has none)
     ms_plain, _, ob, runs = timed_run(p, q, args.steps, args.warmup, profile=False, regions=TIMED_REGIONS)
     value = N * args.steps / (ms_plain / 1e3) / 1e6
+    shape = timed_run.shape
+    ms_fixed, _, _, _ = timed_run(p, q, args.steps, args.warmup, profile=False, regions=TIMED_REGIONS, tuning=None)
+    from paper_2311_15242_amd import lbfd as _L
+    tuning = dict(key=_L.tuning_key(p), shape=shape, tuned_table_entry=_L.tuned_shape(_L.tuning_key(p)) is not None,
+                  fixed_shape=_L.DEFAULT_TUNING, fixed_mlups=round(N * args.steps / (ms_fixed / 1e3) / 1e6, 2),
+                  tuned_over_fixed=round(ms_fixed / ms_plain, 4))
     # 2) every kernel class timed (breakdown; the events add some overhead)
     ms_prof, prof, _, _ = timed_run(p, q, args.steps, args.warmup, profile=True)
     # 3) the longest single-pass kernel timed alone, for the headline roofline
@@ -1312,7 +1367,7 @@ def main():
                            parallelism="single GPU"),
                timed_regions=dict(count=TIMED_REGIONS, statistic="median",
                                   mlups=[round(N * args.steps / (r / 1e3) / 1e6, 1) for r in runs]),
-               roofline=roof, rooflines=rooflines, step_bandwidth=step_bw, useful_bandwidth=useful,
+               tuning=tuning, roofline=roof, rooflines=rooflines, step_bandwidth=step_bw, useful_bandwidth=useful,
                kernels=breakdown, ms_per_step_profiled=round(ms_prof / args.steps, 4))
     if not args.no_accuracy:
         out["accuracy"] = accuracy_report(args.workload, p["precision"], args.accuracy_steps)

@@ -246,6 +246,24 @@ int lbfd_set_fd(lbfd_handle *h, int32_t enable);
  * identical either way. Errors: EINVAL (null handle). */
 int lbfd_set_graphs(lbfd_handle *h, int32_t enable);
 
+/* Launch shape of the solver's kernels: a tuning choice that never changes the
+ * results (every node's arithmetic and the red-black order of the solve are the
+ * same; the FP64 reductions keep their own fixed shape). */
+typedef struct {
+    int32_t rows;           /* workgroups of the step's node kernels: 64 x rows nodes, rows = 1, 2 or 4
+                               (default 4) */
+    int32_t sor_wg_per_cu;  /* persistent grid of the SOR half-sweeps: workgroups of 256 per compute unit,
+                               1..32 (default 8), capped at one per 256 nodes of a colour */
+    int32_t sor_narrow;     /* workgroups of the sweeps past the third (they usually only find the systems
+                               converged): 8..65536, a multiple of 8 (default 256) */
+} lbfd_tuning;
+
+/* Set or read a handle's launch shape (lbfd_set_tuning synchronises the stream
+ * and drops captured graphs). Errors: EINVAL (null pointer, value out of range),
+ * EHIP. */
+int lbfd_set_tuning(lbfd_handle *h, const lbfd_tuning *t);
+int lbfd_get_tuning(const lbfd_handle *h, lbfd_tuning *t);
+
 /* Release the handle (not the caller's workspace or stream). */
 void lbfd_destroy(lbfd_handle *h);
 
@@ -281,6 +299,11 @@ lbfd_handle *lbfd_batch_instance(lbfd_batch *b, int32_t i);
 /* Advance every instance n >= 0 steps. All instances must be at the same step
  * (initialised, or set to the same step, together), else EINVAL. Asynchronous. */
 int lbfd_batch_step(lbfd_batch *b, int64_t n);
+
+/* Launch shape of every instance of a batch (the batch launches one workgroup
+ * per SOR tile of each instance, so only `rows` changes its launches). Errors:
+ * EINVAL, EHIP. */
+int lbfd_batch_set_tuning(lbfd_batch *b, const lbfd_tuning *t);
 
 /* Graph replay of lbfd_batch_step, as lbfd_set_graphs for one handle. */
 int lbfd_batch_set_graphs(lbfd_batch *b, int32_t enable);

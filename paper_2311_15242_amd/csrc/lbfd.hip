@@ -264,10 +264,11 @@ __global__ __launch_bounds__(256) void k_import(KP<typename P::R> k, const doubl
 
 // ============================================================== LDS halos
 
-// A 64 x 4 node tile (one plane) and its one-node halo: 66 x 6 (x 3 planes in 3-D).
-template <int D> struct Halo1 {
-    static constexpr int HX = BX + 2, HY = BY + 2, HZ = D == 3 ? 3 : 1, HN = HX * HY * HZ;
-    static constexpr int HS = (HN + BX * BY - 1) / (BX * BY);   // cells per thread
+// A 64 x TY node tile (one plane) and its one-node halo: 66 x (TY + 2) (x 3 planes
+// in 3-D).
+template <int D, int TY> struct Halo1 {
+    static constexpr int HX = BX + 2, HY = TY + 2, HZ = D == 3 ? 3 : 1, HN = HX * HY * HZ;
+    static constexpr int HS = (HN + BX * TY - 1) / (BX * TY);   // cells per thread
     // halo cell of the thread's own node
     __device__ static int self() { return (int)(threadIdx.x + 1) + HX * ((int)(threadIdx.y + 1) + HY * (D == 3 ? 1 : 0)); }
     // offset of the neighbour at lattice offset (ex, ey, ez)
@@ -294,14 +295,15 @@ __device__ __forceinline__ int halo_coord(int g, int n, int wall)
 // one), whose wrap is worked out once; the rows' y and z are uniform. Every
 // wavefront issues all of its loads before its LDS stores. The caller
 // synchronises the workgroup before reading.
-template <int LAT, class T, int NF, class R>
-__device__ __forceinline__ void stage_halo1(const KP<R> &k, int tile, const T *const *src, T (*sh)[Halo1<Lat<LAT>::D>::HN])
+template <int LAT, class T, int NF, int TY, class R>
+__device__ __forceinline__ void stage_halo1(const KP<R> &k, int tile, const T *const *src,
+                                            T (*sh)[Halo1<Lat<LAT>::D, TY>::HN])
 {
     constexpr int D = Lat<LAT>::D;
-    using H = Halo1<D>;
-    constexpr int NR = H::HY * H::HZ, RPW = (NR + BY - 1) / BY;   // rows, rows per wavefront
-    const int bx = tile % k.gx, rr = tile / k.gx;
-    const int ox = bx * BX - 1, oy = (rr % k.gy) * BY - 1, oz = rr / k.gy - (D == 3 ? 1 : 0);
+    using H = Halo1<D, TY>;
+    constexpr int NR = H::HY * H::HZ, RPW = (NR + TY - 1) / TY;   // rows, rows per wavefront
+    const int bx = tile % k.gx, rr = tile / k.gx, gy = gy_of(k, TY);
+    const int ox = bx * BX - 1, oy = (rr % gy) * TY - 1, oz = rr / gy - (D == 3 ? 1 : 0);
     const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     const int lane = (int)threadIdx.x;
     const bool two = lane < H::HX - BX;
@@ -310,7 +312,7 @@ __device__ __forceinline__ void stage_halo1(const KP<R> &k, int tile, const T *c
     T v0[RPW][NF], v1[RPW][NF];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
-        const int row = w + BY * i;
+        const int row = w + TY * i;
         if (row >= NR) continue;
         const int gy = halo_coord(oy + row % H::HY, k.ny, k.bc[1]);
         const int gz = D == 3 ? halo_coord(oz + row / H::HY, k.nz, k.bc[2]) : 0;
@@ -323,7 +325,7 @@ __device__ __forceinline__ void stage_halo1(const KP<R> &k, int tile, const T *c
     }
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
-        const int row = w + BY * i;
+        const int row = w + TY * i;
         if (row >= NR) continue;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -334,11 +336,11 @@ __device__ __forceinline__ void stage_halo1(const KP<R> &k, int tile, const T *c
 }
 
 // lat_deriv on a staged field: the same stencil, pairs and mirror signs.
-template <int LAT, class R>
+template <int LAT, int TY, class R>
 __device__ __forceinline__ R lat_deriv_lds(const Nbhd &b, const R *sh, int hself, R scl, int a, int odd_axis)
 {
     using L = Lat<LAT>;
-    using H = Halo1<L::D>;
+    using H = Halo1<L::D, TY>;
     R acc = 0;
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
@@ -409,7 +411,8 @@ __global__ __launch_bounds__(256) void kb_geom(const KP<typename P::R> *tab, con
 // Curvature (eq 7), modified Langmuir EOS (eq 8), interfacial force with the
 // Marangoni term (eq 9), buoyancy (Sec 3.4), total force and velocity (eq 10)
 // at the current time level.
-template <int LAT, class P> __device__ __forceinline__ void force_body(const KP<typename P::R> &k, int tile, const StepArgs &sa)
+template <int LAT, class P, int TY>
+__device__ __forceinline__ void force_body(const KP<typename P::R> &k, int tile, const StepArgs &sa)
 {
     using R = typename P::R;
     using L = Lat<LAT>;
@@ -419,14 +422,14 @@ template <int LAT, class P> __device__ __forceinline__ void force_body(const KP<
     const R *psiA = k.fld.psi[sa.pc];
     // the normal and psi of the tile and its halo staged in LDS (FP32 arithmetic)
     constexpr bool LDS = sizeof(R) == 4;
-    using H = Halo1<D>;
+    using H = Halo1<D, TY>;
     __shared__ R sh[LDS ? D + 1 : 1][LDS ? H::HN : 1];
     if constexpr (LDS) {
         const R *srcs[D + 1];
 #pragma unroll
         for (int a = 0; a < D; ++a) srcs[a] = k.fld.nrm + a * N;
         srcs[D] = psiA;
-        stage_halo1<LAT, R, D + 1>(k, tile, srcs, sh);
+        stage_halo1<LAT, R, D + 1, TY>(k, tile, srcs, sh);
         __syncthreads();
     }
     if (!nd.ok) return;
@@ -442,8 +445,8 @@ template <int LAT, class P> __device__ __forceinline__ void force_body(const KP<
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         if constexpr (LDS) {
-            kappa -= lat_deriv_lds<LAT, R>(nb, sh[a], H::self(), R(1), a, a);
-            gp[a] = lat_deriv_lds<LAT, R>(nb, sh[D], H::self(), s, a, -1);
+            kappa -= lat_deriv_lds<LAT, TY, R>(nb, sh[a], H::self(), R(1), a, a);
+            gp[a] = lat_deriv_lds<LAT, TY, R>(nb, sh[D], H::self(), s, a, -1);
             nv[a] = sh[a][H::self()];
         } else {
             kappa -= lat_deriv<LAT, R>(nb, k.fld.nrm + a * N, n, R(1), a, a);
@@ -512,16 +515,16 @@ template <int LAT, class P> __device__ __forceinline__ void force_body(const KP<
         if (k.qon) st(k.fld.qf + a * N, n, (k.qcoef[0] * rR + k.qcoef[1] * rB) * ua);
     }
 }
-template <int LAT, class P> __global__ __launch_bounds__(256) void k_force(KP<typename P::R> k)
+template <int LAT, class P, int TY> __global__ __launch_bounds__(256) void k_force(KP<typename P::R> k)
 {
-    force_body<LAT, P>(k, xcd_tile((int)blockIdx.x, (int)gridDim.x), step_args(k));
+    force_body<LAT, P, TY>(k, xcd_tile((int)blockIdx.x, (int)gridDim.x), step_args(k));
 }
-template <int LAT, class P>
+template <int LAT, class P, int TY>
 __global__ __launch_bounds__(256) void kb_force(const KP<typename P::R> *tab, const int *prefix, int ninst, StepArgs sa)
 {
     int inst, local;
     batch_tile(prefix, ninst, inst, local);
-    force_body<LAT, P>(tab[inst], local, sa);
+    force_body<LAT, P, TY>(tab[inst], local, sa);
 }
 
 // ============================================================== collision
@@ -729,7 +732,8 @@ __global__ __launch_bounds__(256) void kb_collide(const KP<typename P::R> *tab, 
 // rho^R, rho^B of the streamed populations, rebuilt from the recolouring
 // descriptors of the nodes they left (eq 11 summed over arrivals), the colour
 // function (eq 6) and the momentum sum f e, into mac of the next level.
-template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<typename P::R> &k, int tile, const StepArgs &sa)
+template <int LAT, class P, int TY>
+__device__ __forceinline__ void macro_body(const KP<typename P::R> &k, int tile, const StepArgs &sa)
 {
     using R = typename P::R;
     using S = typename P::S;
@@ -742,25 +746,25 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
     // deviation modes, the (a, c) vectors of FP32 and FP64 (16 and 32 bytes).
     // Halo cells beyond a wall are never read (an arrival across a wall comes
     // from the node itself).
-    constexpr int HX = BX + 2, HY = BY + 2, HZ = D == 3 ? 3 : 1, HN = HX * HY * HZ;
+    constexpr int HX = BX + 2, HY = TY + 2, HZ = D == 3 ? 3 : 1, HN = HX * HY * HZ;
     constexpr bool TWO = P::DEV && D == 3;
     using TA = std::conditional_t<P::DEV, DescDev, V4<R>>;
     __shared__ TA sA[HN];
     __shared__ uint32_t sB[TWO ? HN : 1];
     {
-        const int bx = tile % k.gx, rr = tile / k.gx;
-        const int ox = bx * BX - 1, oy = (rr % k.gy) * BY - 1, oz = rr / k.gy - (D == 3 ? 1 : 0);
+        const int bx = tile % k.gx, rr = tile / k.gx, gy = gy_of(k, TY);
+        const int ox = bx * BX - 1, oy = (rr % gy) * TY - 1, oz = rr / gy - (D == 3 ? 1 : 0);
         const TA *dA = (const TA *)k.fld.desc;
         const uint32_t *dB = desc_dev_b(k);
         // every thread fetches up to HS cells, all loads issued before the LDS stores
-        constexpr int HS = (HN + BX * BY - 1) / (BX * BY);
+        constexpr int HS = (HN + BX * TY - 1) / (BX * TY);
         const int t0 = (int)(threadIdx.x + BX * threadIdx.y);
         TA va[HS];
         uint32_t vb[HS];
         bool have[HS];
 #pragma unroll
         for (int it = 0; it < HS; ++it) {
-            const int h = t0 + it * BX * BY;
+            const int h = t0 + it * BX * TY;
             int g[3] = {ox + h % HX, oy + (h / HX) % HY, oz + h / (HX * HY)};
             const int ext[3] = {k.nx, k.ny, k.nz};
             bool ok = h < HN;
@@ -780,7 +784,7 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
         }
 #pragma unroll
         for (int it = 0; it < HS; ++it) {
-            const int h = t0 + it * BX * BY;
+            const int h = t0 + it * BX * TY;
             if (have[it]) {
                 sA[h] = va[it];
                 if constexpr (TWO) sB[h] = vb[it];
@@ -890,16 +894,16 @@ template <int LAT, class P> __device__ __forceinline__ void macro_body(const KP<
         store_moments<LAT, P>(k, (S *)k.fld.f[1 - sa.fc], n, rR, rB, uj, m, &dz);
     }
 }
-template <int LAT, class P> __global__ __launch_bounds__(256) void k_macro(KP<typename P::R> k)
+template <int LAT, class P, int TY> __global__ __launch_bounds__(256) void k_macro(KP<typename P::R> k)
 {
-    macro_body<LAT, P>(k, xcd_tile((int)blockIdx.x, (int)gridDim.x), step_args(k));
+    macro_body<LAT, P, TY>(k, xcd_tile((int)blockIdx.x, (int)gridDim.x), step_args(k));
 }
-template <int LAT, class P>
+template <int LAT, class P, int TY>
 __global__ __launch_bounds__(256) void kb_macro(const KP<typename P::R> *tab, const int *prefix, int ninst, StepArgs sa)
 {
     int inst, local;
     batch_tile(prefix, ninst, inst, local);
-    macro_body<LAT, P>(tab[inst], local, sa);
+    macro_body<LAT, P, TY>(tab[inst], local, sa);
 }
 
 // ============================================================== finite differences
@@ -1718,6 +1722,12 @@ struct StepGraphs {
     bool on = true;                  // replay when a call advances four or more steps
     hipStream_t cap = nullptr;       // private capture stream (the caller's may be the null stream)
     std::vector<StepGraph> cache;
+    // forget the captured graphs (they hold the launch shapes of their capture)
+    void drop()
+    {
+        for (auto &g : cache) hipGraphExecDestroy(g.exec);
+        cache.clear();
+    }
     void release()
     {
         for (auto &g : cache) hipGraphExecDestroy(g.exec);
@@ -1755,6 +1765,12 @@ struct lbfd_handle {
     bool fd_off = false;  // LB steps only (psi, phi held): surrogate mode between its updates
     bool kp_dirty = false;  // the parameter block changed after creation (a batch re-uploads its table)
     int dev = 0;          // device current at lbfd_create (the workspace's device)
+    // launch shape (a tuning choice; results do not depend on it): rows of 64 x per
+    // workgroup of the step's node kernels, the SOR's persistent grid
+    int rows = BY;
+    int sor_wg_per_cu = 8, sor_narrow = 256, cus = 256;
+    dim3 grid4, block4;   // the observables' reduction keeps 64 x 4 workgroups
+    long long nblocks4 = 0;
 };
 
 // A batch: independent instances (ordinary handles on slices of one workspace)
@@ -1770,6 +1786,7 @@ struct lbfd_batch {
     int *prefix_seam;   // device: first seam workgroup of each instance (n + 1 entries)
     dim3 grid_node, grid_sor, grid_total, grid_seam;
     int seam_levels;    // most seam levels of any instance
+    int rows = BY;      // rows of 64 x per workgroup of the node kernels (every instance)
     StepGraphs graphs;
 };
 
@@ -1918,7 +1935,8 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
     k.ihmu[1] = (R)(0.5 / p->muB0);
     k.irho0[0] = (R)(1.0 / p->rhoR0);
     k.irho0[1] = (R)(1.0 / p->rhoB0);
-    k.gx = (p->nx + BX - 1) / BX; k.gy = (p->ny + BY - 1) / BY;
+    k.gx = (p->nx + BX - 1) / BX;
+    k.gy[0] = p->ny; k.gy[1] = (p->ny + 1) / 2; k.gy[2] = (p->ny + 3) / 4;
     k.N = (long long)p->nx * p->ny * p->nz;
     for (int a = 0; a < 3; ++a) k.bc[a] = p->bc[a];
     for (int w = 0; w < 6; ++w)
@@ -2034,6 +2052,17 @@ struct Timer {
         hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, h->stream, __VA_ARGS__);           \
     } while (0)
 
+// LAUNCH of a node kernel templated on the rows of its workgroups (the
+// handle's tile shape).
+#define LAUNCH_TY(ROWS, KC, KERNEL, GRID, BLOCK, ...)                                             \
+    do {                                                                                       \
+        switch (ROWS) {                                                                        \
+        case 1: LAUNCH(KC, (KERNEL<LAT, P, 1>), GRID, BLOCK, __VA_ARGS__); break;               \
+        case 2: LAUNCH(KC, (KERNEL<LAT, P, 2>), GRID, BLOCK, __VA_ARGS__); break;               \
+        default: LAUNCH(KC, (KERNEL<LAT, P, 4>), GRID, BLOCK, __VA_ARGS__); break;              \
+        }                                                                                      \
+    } while (0)
+
 // Number of FP64 values lbfd_read_field returns for a field (components x
 // nodes), or 0 for an unknown field identifier.
 static size_t field_count(const lbfd_handle *h, int field)
@@ -2082,7 +2111,7 @@ template <int LAT, class P> struct Impl {
         KP<R> &k = kp(h);
         sync_levels(h);
         LAUNCH(KC_GEOM, (k_geom<LAT, P>), h->grid, h->block, k, k.lev);
-        LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
+        LAUNCH_TY(h->rows, KC_FORCE, k_force, h->grid, h->block, k);
     }
 
     static int init(lbfd_handle *h, const InitDev &in)
@@ -2105,7 +2134,7 @@ template <int LAT, class P> struct Impl {
             if (st != LBFD_OK && st != LBFD_ENONFINITE && st != LBFD_ESOR) return st;
             set_rho_ref(h, (o.mass_R + o.mass_B) / (double)h->N);
         }
-        LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
+        LAUNCH_TY(h->rows, KC_FORCE, k_force, h->grid, h->block, k);
         return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
     }
 
@@ -2186,7 +2215,7 @@ template <int LAT, class P> struct Impl {
             // sweeps past the third usually find both systems converged and return at
             // once: a narrower persistent grid makes that cheaper (the updates of a
             // colour half-sweep do not depend on their order, so the result is the same)
-            const dim3 gs(s < 3 ? h->sor_blocks : std::min(h->sor_blocks, 256));
+            const dim3 gs(s < 3 ? h->sor_blocks : std::min(h->sor_blocks, h->sor_narrow));
             if (h->seam_levels == 0) {
                 LAUNCH(KC_SOR, (k_sor<LAT, P, false>), gs, dim3(256), k, 0, s);
                 LAUNCH(KC_SOR, (k_sor<LAT, P, false>), gs, dim3(256), k, 1, s);
@@ -2225,7 +2254,7 @@ template <int LAT, class P> struct Impl {
                            h->stream) != hipSuccess)
             return LBFD_EHIP;
         for (long long t = 0; t < ksub; ++t) fd_block(h);
-        LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
+        LAUNCH_TY(h->rows, KC_FORCE, k_force, h->grid, h->block, k);
         return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
     }
 
@@ -2274,7 +2303,7 @@ template <int LAT, class P> struct Impl {
         h->pc = 1 - h->pc;
         h->fd_hist = 0;
         sync_levels(h);
-        LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
+        LAUNCH_TY(h->rows, KC_FORCE, k_force, h->grid, h->block, k);
         return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
     }
 
@@ -2292,13 +2321,13 @@ template <int LAT, class P> struct Impl {
         for (long long t = 0; t < nsteps; ++t) {
             sync_levels(h);
             LAUNCH(KC_COLLIDE, (k_collide<LAT, P>), h->grid, h->block, k);
-            LAUNCH(KC_MACRO, (k_macro<LAT, P>), h->grid, h->block, k);
+            LAUNCH_TY(h->rows, KC_MACRO, k_macro, h->grid, h->block, k);
             LAUNCH(KC_GEOM, (k_geom<LAT, P>), h->grid, h->block, k, 1 - k.lev);
             if (h->p.fd_enable && !h->fd_off) fd_block(h);
             h->fc = 1 - h->fc;
             h->step += 1;
             sync_levels(h);
-            LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
+            LAUNCH_TY(h->rows, KC_FORCE, k_force, h->grid, h->block, k);
         }
         return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
     }
@@ -2310,7 +2339,7 @@ template <int LAT, class P> struct Impl {
         lbfd_handle *h = b->inst[0];   // time levels are common; profiling goes to instance 0
         const KP<R> *tab = (const KP<R> *)b->tab;
         const int n = b->n;
-        const dim3 blk(BX, BY, 1);
+        const dim3 blk(BX, b->rows, 1);
         for (long long t = 0; t < nsteps; ++t) {
             StepArgs sa;
             sa.lev = (int)(h->step & 1);
@@ -2319,7 +2348,7 @@ template <int LAT, class P> struct Impl {
             sa.extrap = h->fd_hist >= 1 ? 1 : 0;
             sa.step = h->step;
             LAUNCH(KC_COLLIDE, (kb_collide<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sa);
-            LAUNCH(KC_MACRO, (kb_macro<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sa);
+            LAUNCH_TY(b->rows, KC_MACRO, kb_macro, b->grid_node, blk, tab, b->prefix_node, n, sa);
             LAUNCH(KC_GEOM, (kb_geom<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sa, 1 - sa.lev);
             const bool fd = h->p.fd_enable != 0;
             if (fd) {
@@ -2359,7 +2388,7 @@ template <int LAT, class P> struct Impl {
             sb.pc = h->pc;
             sb.extrap = h->fd_hist >= 1 ? 1 : 0;
             sb.step = h->step;
-            LAUNCH(KC_FORCE, (kb_force<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sb);
+            LAUNCH_TY(b->rows, KC_FORCE, kb_force, b->grid_node, blk, tab, b->prefix_node, n, sb);
         }
         return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
     }
@@ -2484,8 +2513,8 @@ template <int LAT, class P> struct Impl {
         KP<R> &k = kp(h);
         sync_levels(h);
         double r0[NRED], r1[NRED];
-        LAUNCH(KC_OTHER, (k_obs_part<LAT, P>), h->grid, h->block, k, 0, 0.0, 0.0, 0.0);
-        LAUNCH(KC_OTHER, k_obs_final, dim3(1), dim3(256), k.fld.part, h->nblocks, h->obs_out);
+        LAUNCH(KC_OTHER, (k_obs_part<LAT, P>), h->grid4, h->block4, k, 0, 0.0, 0.0, 0.0);
+        LAUNCH(KC_OTHER, k_obs_final, dim3(1), dim3(256), k.fld.part, h->nblocks4, h->obs_out);
         hipMemcpyAsync(r0, h->obs_out, sizeof(r0), hipMemcpyDeviceToHost, h->stream);
         DevScalars sc;
         hipMemcpyAsync(&sc, k.fld.sc, sizeof(sc), hipMemcpyDeviceToHost, h->stream);
@@ -2504,9 +2533,9 @@ template <int LAT, class P> struct Impl {
         o->p_out = r0[16] > 0 ? r0[15] / r0[16] : 0.0;
         o->psi_min = r0[17];
         o->psi_max = r0[18];
-        LAUNCH(KC_OTHER, (k_obs_part<LAT, P>), h->grid, h->block, k, 1, o->centroid[0], o->centroid[1],
+        LAUNCH(KC_OTHER, (k_obs_part<LAT, P>), h->grid4, h->block4, k, 1, o->centroid[0], o->centroid[1],
                o->centroid[2]);
-        LAUNCH(KC_OTHER, k_obs_final, dim3(1), dim3(256), k.fld.part, h->nblocks, h->obs_out);
+        LAUNCH(KC_OTHER, k_obs_final, dim3(1), dim3(256), k.fld.part, h->nblocks4, h->obs_out);
         hipMemcpyAsync(r1, h->obs_out, sizeof(r1), hipMemcpyDeviceToHost, h->stream);
         if (hipStreamSynchronize(h->stream) != hipSuccess) return LBFD_EHIP;
         for (int i = 0; i < 6; ++i) o->second[i] = r0[7] > 0 ? r1[i] / r0[7] : 0.0;
@@ -2561,7 +2590,7 @@ template <int LAT, class P> struct Impl {
         KP<R> &k = kp(h);
         hipMemcpyAsync(d, host, count * sizeof(double), hipMemcpyHostToDevice, h->stream);
         LAUNCH(KC_OTHER, (k_import_fd<R>), dim3((unsigned)((h->N + 255) / 256)), dim3(256), k, field, d);
-        if (field == LBFD_FIELD_PSI) LAUNCH(KC_FORCE, (k_force<LAT, P>), h->grid, h->block, k);
+        if (field == LBFD_FIELD_PSI) LAUNCH_TY(h->rows, KC_FORCE, k_force, h->grid, h->block, k);
         hipError_t e = hipStreamSynchronize(h->stream);
         hipFree(d);
         return e == hipSuccess ? LBFD_OK : LBFD_EHIP;
@@ -2588,6 +2617,24 @@ template <int LAT, class P> struct Impl {
         return st;
     }
 };
+
+// Launch shape of a handle: rows of 64 x per workgroup of the step's node kernels,
+// and the SOR's persistent grid (workgroups of 256 per compute unit, capped at one
+// per tile of a colour; a multiple of 8 keeps the XCD-aware tile order) and the
+// grid of sweeps past the third. The results do not depend on it.
+void apply_shape(lbfd_handle *h, int rows, int wg_per_cu, int narrow)
+{
+    const lbfd_params *p = &h->p;
+    h->rows = rows;
+    h->block = dim3(BX, rows, 1);
+    h->nblocks = (long long)((p->nx + BX - 1) / BX) * ((p->ny + rows - 1) / rows) * p->nz;
+    h->grid = dim3((unsigned)h->nblocks);
+    const long long need = sor_tiles_of(p->nx, p->ny, p->nz);
+    const long long cap = (long long)wg_per_cu * h->cus;
+    h->sor_wg_per_cu = wg_per_cu;
+    h->sor_blocks = (int)(need < cap ? need : cap);
+    h->sor_narrow = narrow;
+}
 
 struct Dispatch {
     int (*init)(lbfd_handle *, const InitDev &);
@@ -2715,24 +2762,21 @@ int lbfd_create(const lbfd_params *p, void *d_workspace, size_t bytes, void *str
     h->ws_bytes = bytes;
     h->fc = h->pc = 0;
     h->step = 0;
-    h->block = dim3(BX, BY, 1);
-    h->nblocks = (long long)((p->nx + BX - 1) / BX) * ((p->ny + BY - 1) / BY) * p->nz;
-    h->grid = dim3((unsigned)h->nblocks);
+    h->block4 = dim3(BX, BY, 1);
+    h->nblocks4 = (long long)((p->nx + BX - 1) / BX) * ((p->ny + BY - 1) / BY) * p->nz;
+    h->grid4 = dim3((unsigned)h->nblocks4);
     h->tblocks = total_blocks(h->N);
     seam_shape(p, &h->seam_tiles, &h->seam_levels);
     h->sweeps_launch = p->sor_max_sweeps;
     {
-        // tiles of one colour (256 nodes), capped at 8 workgroups of 256 per compute unit
-        long long need = sor_tiles_of(p->nx, p->ny, p->nz);
-        int dev = 0, cus = 256;
+        int dev = 0;
         if (hipGetDevice(&dev) == hipSuccess) {
             hipDeviceProp_t prop;
             if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-                cus = prop.multiProcessorCount;
+                h->cus = prop.multiProcessorCount;
         }
-        long long cap = 8LL * cus;  // a multiple of 8 (XCD-aware tile order)
-        h->sor_blocks = (int)(need < cap ? need : cap);
     }
+    apply_shape(h, BY, 8, 256);
     h->prof = false;
     h->prof_mask = 0xffffffffu;
     if (hipGetDevice(&h->dev) != hipSuccess) h->dev = 0;
@@ -2810,6 +2854,50 @@ int lbfd_set_graphs(lbfd_handle *h, int32_t enable)
 {
     if (!h) return LBFD_EINVAL;
     h->graphs.on = enable != 0;
+    return LBFD_OK;
+}
+
+static int tuning_valid(const lbfd_tuning *t)
+{
+    return t && (t->rows == 1 || t->rows == 2 || t->rows == 4) && t->sor_wg_per_cu >= 1 && t->sor_wg_per_cu <= 32 &&
+           t->sor_narrow >= 8 && t->sor_narrow <= 65536 && t->sor_narrow % 8 == 0;
+}
+
+int lbfd_set_tuning(lbfd_handle *h, const lbfd_tuning *t)
+{
+    if (!h || !tuning_valid(t)) return LBFD_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return LBFD_EHIP;
+    h->graphs.drop();
+    apply_shape(h, t->rows, t->sor_wg_per_cu, t->sor_narrow);
+    return LBFD_OK;
+}
+
+int lbfd_get_tuning(const lbfd_handle *h, lbfd_tuning *t)
+{
+    if (!h || !t) return LBFD_EINVAL;
+    t->rows = h->rows;
+    t->sor_wg_per_cu = h->sor_wg_per_cu;
+    t->sor_narrow = h->sor_narrow;
+    return LBFD_OK;
+}
+
+int lbfd_batch_set_tuning(lbfd_batch *b, const lbfd_tuning *t)
+{
+    if (!b || !tuning_valid(t)) return LBFD_EINVAL;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return LBFD_EHIP;
+    b->graphs.drop();
+    std::vector<int> pn(b->n + 1);
+    pn[0] = 0;
+    for (int i = 0; i < b->n; ++i) {
+        lbfd_handle *h = b->inst[i];
+        h->graphs.drop();
+        apply_shape(h, t->rows, t->sor_wg_per_cu, t->sor_narrow);
+        pn[i + 1] = pn[i] + (int)h->nblocks;
+    }
+    if (hipMemcpy(b->prefix_node, pn.data(), sizeof(int) * (b->n + 1), hipMemcpyHostToDevice) != hipSuccess)
+        return LBFD_EHIP;
+    b->grid_node = dim3((unsigned)pn[b->n]);
+    b->rows = t->rows;
     return LBFD_OK;
 }
 

@@ -215,7 +215,8 @@ template <class R> struct Fields {
 
 template <class R> struct KP {
     int nx, ny, nz;
-    int gx, gy;         // tiles along x and y of the node launches
+    int gx;             // tiles along x of the node launches (64 x each)
+    int gy[3];          // tiles along y for workgroups of 1, 2 and 4 rows of 64 x
     long long N;
     int bc[3];
     R wall_u[6][3];
@@ -275,16 +276,24 @@ __device__ __forceinline__ int xcd_tile(int i, int n)
 
 // Node of this thread in tile t of the gx * gy * nz tiles of blockDim.x by
 // blockDim.y nodes (x fastest).
+// Tiles along y of a node launch whose workgroups have `rows` rows of 64 x
+// (1, 2 or 4: the tile shape is a tuning choice; results do not depend on it).
+template <class R> __device__ __forceinline__ int gy_of(const KP<R> &k, int rows)
+{
+    return rows == 4 ? k.gy[2] : rows == 2 ? k.gy[1] : k.gy[0];
+}
+
 template <class R> __device__ __forceinline__ Node node_at(const KP<R> &k, int t)
 {
     Node n;
     const int bx = t % k.gx, r = t / k.gx;
+    const int gy = gy_of(k, (int)blockDim.y);
     n.x = bx * blockDim.x + threadIdx.x;
-    // node launches use 64 x 4 workgroups, so a wavefront is one row of 64 x: its y
-    // (and z) are the same in every lane, and held in scalar registers the
-    // neighbourhood arithmetic along y and z runs once per wavefront
-    n.y = __builtin_amdgcn_readfirstlane((r % k.gy) * (int)blockDim.y + (int)threadIdx.y);
-    n.z = r / k.gy;
+    // node launches use workgroups of 64 x by 1, 2 or 4 rows, so a wavefront is one
+    // row of 64 x: its y (and z) are the same in every lane, and held in scalar
+    // registers the neighbourhood arithmetic along y and z runs once per wavefront
+    n.y = __builtin_amdgcn_readfirstlane((r % gy) * (int)blockDim.y + (int)threadIdx.y);
+    n.z = r / gy;
     n.ok = n.x < k.nx && n.y < k.ny;
     return n;
 }

@@ -7,6 +7,8 @@ library is missing this module raises; there is no other code path.
 from __future__ import annotations
 
 import ctypes as C
+import json
+import math
 import os
 
 import numpy as np
@@ -23,6 +25,7 @@ EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_init_fields", "lbfd_set
             "lbfd_strerror", "lbfd_batch_workspace_bytes", "lbfd_batch_create", "lbfd_batch_instance",
             "lbfd_batch_step", "lbfd_batch_destroy", "lbfd_set_graphs", "lbfd_batch_set_graphs",
             "lbfd_fd_substeps", "lbfd_set_fd", "lbfd_write_field", "lbfd_read_field_noalloc",
+            "lbfd_set_tuning", "lbfd_get_tuning", "lbfd_batch_set_tuning",
             "lbfd_sg_n_params", "lbfd_sg_workspace_bytes", "lbfd_sg_create", "lbfd_sg_set_params",
             "lbfd_sg_get_params", "lbfd_sg_forward", "lbfd_sg_gradient", "lbfd_sg_train_step", "lbfd_sg_features",
             "lbfd_sg_snapshot", "lbfd_sg_tiles", "lbfd_sg_advance", "lbfd_sg_destroy", "lbfd_sg_set_drift_tol"]
@@ -74,6 +77,42 @@ class Obs(C.Structure):
 _lib = None
 
 
+class Tuning(C.Structure):
+    _fields_ = [("rows", C.c_int32), ("sor_wg_per_cu", C.c_int32), ("sor_narrow", C.c_int32)]
+
+
+# Launch shape of the library's defaults (64 x 4 node tiles, 8 SOR workgroups per
+# compute unit, 256 for sweeps past the third) and the table of tuned shapes the
+# autotuner writes (tuning.json next to this module), keyed by tuning_key.
+DEFAULT_TUNING = dict(rows=4, sor_wg_per_cu=8, sor_narrow=256)
+TUNING_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def tuning_key(params: dict, instances: int = 0, nodes: int | None = None) -> str:
+    """Table key of a workload: lattice, storage, size class round(log2 nodes), and
+    for a batch its instance count (nodes: the batch's total)."""
+    lat = "D3Q19" if params["lattice"] == 1 else "D2Q9"
+    n = nodes if nodes is not None else params["nx"] * params["ny"] * params["nz"]
+    key = f"{lat}/{params.get('precision', 'fp64')}/n2^{int(round(math.log2(max(n, 1))))}"
+    return f"batch{instances}/{key}" if instances else key
+
+
+def tuned_shape(key: str, path: str = TUNING_FILE):
+    """The tuned launch shape of a key, or None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        table = json.load(fh)
+    e = table.get("entries", {}).get(key)
+    return dict(e["tuning"]) if e else None
+
+
+def _tuning_struct(t: dict) -> Tuning:
+    s = Tuning()
+    s.rows, s.sor_wg_per_cu, s.sor_narrow = int(t["rows"]), int(t["sor_wg_per_cu"]), int(t["sor_narrow"])
+    return s
+
+
 class SgParams(C.Structure):
     _fields_ = [("tile", C.c_int32), ("max_batch", C.c_int32), ("field", C.c_int32 * 3), ("k", C.c_int32),
                 ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("adam_eps", C.c_double),
@@ -114,6 +153,9 @@ def load(build_if_missing: bool = False):
     L.lbfd_observables.argtypes = [vp, P(Obs)]
     L.lbfd_read_field.argtypes = [vp, C.c_int32, dp, C.c_size_t]
     L.lbfd_read_field_noalloc.argtypes = [vp, C.c_int32, dp, C.c_size_t]
+    L.lbfd_set_tuning.argtypes = [vp, P(Tuning)]
+    L.lbfd_get_tuning.argtypes = [vp, P(Tuning)]
+    L.lbfd_batch_set_tuning.argtypes = [vp, P(Tuning)]
     L.lbfd_profile.argtypes = [vp, C.c_int32]
     L.lbfd_profile_read.argtypes = [vp, C.c_int32, P(C.c_char_p), dp, P(C.c_int64), P(C.c_int32)]
     L.lbfd_destroy.argtypes = [vp]
@@ -303,9 +345,13 @@ class _Instance:
 
 
 class Solver(_Instance):
-    """One solver instance on one device: ``Solver(params).init_fields(init).step(n)``."""
+    """One solver instance on one device: ``Solver(params).init_fields(init).step(n)``.
 
-    def __init__(self, params: dict, device: str = "cuda:0", stream=None):
+    tuning: "auto" applies the tuned launch shape of the workload's key from
+    tuning.json when there is one (else the defaults), None keeps the defaults,
+    a dict sets one (rows, sor_wg_per_cu, sor_narrow). Results do not depend on it."""
+
+    def __init__(self, params: dict, device: str = "cuda:0", stream=None, tuning="auto"):
         import torch
 
         self._ps = params_struct(params)
@@ -320,6 +366,19 @@ class Solver(_Instance):
         _check(L.lbfd_create(C.byref(self._ps), C.c_void_p(ptr), C.c_size_t(nbytes),
                              C.c_void_p(self.stream.cuda_stream), C.byref(h)), "lbfd_create")
         self._bind(params, h)
+        t = tuned_shape(tuning_key(params)) if tuning == "auto" else tuning
+        if t:
+            self.set_tuning(t)
+
+    def set_tuning(self, t: dict):
+        """Launch shape (rows, sor_wg_per_cu, sor_narrow); drops captured graphs."""
+        _check(load().lbfd_set_tuning(self.h, C.byref(_tuning_struct(dict(DEFAULT_TUNING, **t)))), "lbfd_set_tuning")
+        return self
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(load().lbfd_get_tuning(self.h, C.byref(t)), "lbfd_get_tuning")
+        return dict(rows=t.rows, sor_wg_per_cu=t.sor_wg_per_cu, sor_narrow=t.sor_narrow)
 
     def close(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -353,7 +412,7 @@ class Batch:
     """Independent instances advanced together, one launch per kernel class:
     ``Batch([params0, params1, ...])``, then ``b[i].init_fields(...)`` and ``b.step(n)``."""
 
-    def __init__(self, params_list, device: str = "cuda:0", stream=None):
+    def __init__(self, params_list, device: str = "cuda:0", stream=None, tuning="auto"):
         import torch
 
         plist = [dict(p) for p in params_list]
@@ -379,6 +438,16 @@ class Batch:
                 raise LbfdError(LBFD_EINVAL, f"lbfd_batch_instance({i})")
             self.members.append(BatchMember(self, i, p, C.c_void_p(h)))
         self.nodes = sum(m.N for m in self.members)
+        self.key = tuning_key(plist[0], instances=n, nodes=self.nodes)
+        t = tuned_shape(self.key) if tuning == "auto" else tuning
+        if t:
+            self.set_tuning(t)
+
+    def set_tuning(self, t: dict):
+        """Launch shape of every instance (a batch uses only `rows`)."""
+        _check(load().lbfd_batch_set_tuning(self.b, C.byref(_tuning_struct(dict(DEFAULT_TUNING, **t)))),
+               "lbfd_batch_set_tuning")
+        return self
 
     def __len__(self):
         return len(self.members)
