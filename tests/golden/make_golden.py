@@ -10,9 +10,16 @@ tests run the same workloads and compare against these files:
   G psi and X phi on the plane y = 63 for z < 128 (the bubble and its wake),
   and the observables after 50, 100, 200 and 500 steps.
 
-Usage: ``python tests/golden/make_golden.py bubble`` (about 40 minutes on 8
-cores). The output is deterministic up to the oracle's OpenMP reduction order
-in the observables (1e-15 relative).
+* ``shear_deformation_20k.json`` -- the drop in simple shear (D2Q9 512 x 256,
+  walls at -/+ 0.02, R = 40, Sec 3.3 groups) at two corners of the parameter
+  range (Ca 0.1, Bi 0.1, E0 0.1 and Ca 0.4, Bi 1, E0 0.5), 20 000 FP64 steps:
+  the deformation D = (L - B)/(L + B) of the second moments, the centroid and
+  the velocity of eq 33 every 1000 steps.
+
+Usage: ``python tests/golden/make_golden.py bubble`` (about 90 minutes on 8
+cores), ``... shear CASE`` (one case, about an hour). The output is
+deterministic up to the oracle's OpenMP reduction order in the observables
+(1e-15 relative).
 """
 from __future__ import annotations
 
@@ -57,7 +64,38 @@ def bubble_column():
     print("wrote", BUBBLE_FILE, flush=True)
 
 
+SHEAR_FILE = os.path.join(HERE, "shear_deformation_20k.json")
+SHEAR_CASES = {"ca0.1_bi0.1_e0.1": dict(Ca=0.1, Bi=0.1, E0=0.1), "ca0.4_bi1_e0.5": dict(Ca=0.4, Bi=1.0, E0=0.5)}
+SHEAR_STEPS, SHEAR_EVERY = 20000, 1000
+
+
+def shear_case(name):
+    p, q = W.shear_droplet(precision="fp64", **SHEAR_CASES[name])
+    o = oracle.Oracle(p).init(q)
+    rec = []
+    t0 = time.time()
+    for c in range(0, SHEAR_STEPS + 1, SHEAR_EVERY):
+        if c:
+            o.step(SHEAR_EVERY)
+        ob = o.observables()
+        rec.append(dict(step=c, deformation=oracle.deformation(ob["second"], 2), centroid=ob["centroid"][:2],
+                        velocity=ob["velocity"][:2], psi_av=ob["psi_av"], total_surf=ob["total_surf"]))
+        print(f"{name} step {c} ({time.time() - t0:.0f} s): D {rec[-1]['deformation']:.6f}", flush=True)
+    table = {}
+    if os.path.exists(SHEAR_FILE):
+        with open(SHEAR_FILE) as fh:
+            table = json.load(fh)
+    table[name] = dict(params=SHEAR_CASES[name], steps=SHEAR_STEPS, every=SHEAR_EVERY, records=rec)
+    with open(SHEAR_FILE, "w") as fh:
+        json.dump(table, fh, indent=1)
+        fh.write("\n")
+    print("wrote", SHEAR_FILE, flush=True)
+
+
 if __name__ == "__main__":
     what = sys.argv[1:] or ["bubble"]
-    if "bubble" in what:
+    if what[0] == "bubble":
         bubble_column()
+    elif what[0] == "shear":
+        for name in what[1:] or list(SHEAR_CASES):
+            shear_case(name)

@@ -6,6 +6,9 @@ oracle at the tolerances stated per test. Inputs are the seeded synthetic
 workloads of ``workloads`` at sizes the oracle finishes in seconds, spanning
 several 64 x 4 thread tiles with ragged edges, plus the full-size 3-D column.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -489,3 +492,43 @@ def test_langmuir_near_saturation_fp32(lbfd):
     err = rel(Fg, Fo)
     say(f"force rel err {err:.3e}")
     assert err < 2e-5, err
+
+
+GOLDEN_COLUMN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bubble_column_500.npz")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16dev", "bf16dev"])
+def test_bubble_column_500_steps_vs_stored_oracle(lbfd, prec):
+    """The 3-D column at full size after 500 steps against the FP64 oracle's
+    stored result (tests/golden/make_golden.py, the oracle alone): u, rhoN,
+    G psi and X phi on the plane y = 63 through the bubble and its wake
+    (z < 128), and the observables. FP64 within 1e-10 (velocity of eq 33 and
+    centroid 1e-9); the reduced-precision modes, with their own solver
+    tolerance and FD background, within 1e-3 (BF16 velocity: the known miss)."""
+    if not os.path.exists(GOLDEN_COLUMN):
+        pytest.skip("stored oracle result missing (python tests/golden/make_golden.py bubble)")
+    g = np.load(GOLDEN_COLUMN)
+    say(f"[bubble128x128x384 {prec} 500 steps vs stored oracle]")
+    p, q = W.bubble_rise(precision=prec)
+    s = lbfd.Solver(p).init_fields(q).step(500)
+    sl = (slice(0, g["rhoN"].shape[0]), 63, slice(None))
+    rN = s.field("rhoN")
+    u = s.field("u")
+    got = dict(u=np.stack([u[a][sl] for a in range(3)]), rhoN=rN[sl], Gpsi=(s.field("G") * s.field("psi"))[sl],
+               Xphi=((1.0 - rN) * s.field("phi"))[sl])
+    errs = {k: rel(got[k], g[k]) for k in got}
+    say(errs)
+    ob = s.observables()
+    oo = json.loads(str(g["obs"]))["500"]
+    assert ob["status"] == 0
+    vz = abs(ob["velocity"][2] - oo["velocity"][2]) / abs(oo["velocity"][2])
+    cz = abs(ob["centroid"][2] - oo["centroid"][2])
+    say(f"eq 33 velocity rel err {vz:.2e}, centroid z diff {cz:.2e}")
+    if prec == "fp64":
+        assert max(errs.values()) < 1e-10, errs
+        assert vz < 1e-9 and cz < 1e-9
+        assert abs(ob["total_surf"] - float(g["initial_total"])) <= 1e-12 * float(g["initial_total"])
+        return
+    assert max(errs["rhoN"], errs["Gpsi"], errs["Xphi"]) < 1e-3, errs
+    assert vz < 1e-3 and cz < 1e-2
+    check_velocity(prec, errs["u"])
