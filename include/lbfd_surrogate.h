@@ -3,15 +3,25 @@
  * A method addition (the paper has no surrogate). The FD update of Sec 2.2
  * (eqs 20-28) applied k times with the flow held at the current state (the
  * operation lbfd_fd_substeps performs) is approximated by a small network:
- * four 3x3x3 "valid" convolutions, channels 6 -> 32 -> 32 -> 32 -> 2, ReLU
+ * four 3x3x3 "valid" convolutions, channels 6 -> 32 -> 32 -> 32 -> 7, ReLU
  * after the first three, BF16 weights and activations with FP32 accumulation
  * on the matrix cores, FP32 master weights trained with Adam.
  *
  * Inputs per node (channels-last, BF16, padded to 16 channels with zeros):
  * psi/psi_inf, phi/phi_s, rhoN, u_x/u_s, u_y/u_s, u_z/u_s (u_z = 0 in 2-D).
- * Outputs per node (FP32, 2 channels): the change of psi and of phi over the
- * k substeps, divided by dpsi_s and dphi_s. Grids are (z, y, x) with x
- * fastest; an input grid of d x h x w nodes gives (d-8) x (h-8) x (w-8).
+ * Outputs per node (FP32, 7 channels), read in a conservative form: flux
+ * coefficients f_psi,a and f_phi,a (a = x, y, z) and an exchange s. With the
+ * weights of eqs 20-21 held over the substeps, W = G + fd_eps and X = 1 - rhoN +
+ * fd_eps, the flux of W psi through the face between n and n + e_a is
+ * (W[n] + W[n + e_a])/2 f_psi,a[n] (likewise X phi with X), the exchange from
+ * bulk to interface at n is W[n] s[n], and the changes over the k substeps are
+ *   W dpsi = dpsi_s (W s - sum_a (face flux out - face flux in)),
+ *   X dphi = dphi_s (- sum_a (face flux out - face flux in)) - dpsi_s W s,
+ * so the total surfactant sum (W psi + X phi) is conserved by construction on
+ * a periodic grid. Grids are (z, y, x) with x fastest; an input grid of
+ * d x h x w nodes gives (d-8) x (h-8) x (w-8) outputs. A training tile of T^3
+ * outputs is scored on its interior [1, T-2]^3, where every face it needs lies
+ * in the tile.
  *
  * Parameter vector (FP32, lbfd_sg_n_params() entries): for each layer in turn
  * the weights w[a][p][q][i][o] (tap offsets a, p, q in z, y, x; input channel
@@ -37,14 +47,17 @@ extern "C" {
 typedef struct lbfd_sg lbfd_sg;
 
 typedef struct {
-    int32_t tile;       /* output edge of a training tile (its input edge is tile + 8), 1..64 */
+    int32_t tile;       /* output edge of a training tile (its input edge is tile + 8), 3..64 */
     int32_t max_batch;  /* most tiles per lbfd_sg_gradient / lbfd_sg_train_step / lbfd_sg_tiles call, >= 1 */
     int32_t field[3];   /* largest solver grid (nx, ny, nz) for the whole-field calls; 0s: none */
     int32_t k;          /* FD substeps one application replaces (>= 1) */
     double lr, beta1, beta2, adam_eps;             /* Adam */
     double psi_inf, phi_s, u_s, dpsi_s, dphi_s;    /* channel scales (all > 0) */
-    double drift_tol;   /* lbfd_sg_advance falls back to the FD update when the
-                           pre-rescale relative drift of the total surfactant exceeds it */
+    double drift_tol;   /* lbfd_sg_advance falls back to the FD update when the network's
+                           update changes the total surfactant (at the frozen weights,
+                           before any rescaling) by more than this relative amount, or
+                           when it is implausible: not finite, or a change of psi (phi)
+                           above 20 dpsi_s (20 dphi_s) where W (X) >= 1e-3 */
 } lbfd_sg_params;
 
 typedef struct {
@@ -55,7 +68,7 @@ typedef struct {
     double last_drift;  /* drift of the last application (kept or not) */
 } lbfd_sg_report;
 
-/* Number of FP32 parameters (62306). */
+/* Number of FP32 parameters (66631). */
 int64_t lbfd_sg_n_params(void);
 
 /* Device workspace for the surrogate described by p. */
@@ -72,14 +85,17 @@ int lbfd_sg_set_params(lbfd_sg *s, const float *host, int64_t n);
 int lbfd_sg_get_params(lbfd_sg *s, float *host, int64_t n);
 
 /* Network on B grids of d x h x w input nodes (d_in: BF16 bit patterns,
- * [B][d][h][w][16]); d_out: FP32 [B][d-8][h-8][w-8][2]. B * d * h * w and
+ * [B][d][h][w][16]); d_out: FP32 [B][d-8][h-8][w-8][7]. B * d * h * w and
  * the intermediate grids must fit the workspace (the tile batch or the
  * whole-field grid it was sized for). */
 int lbfd_sg_forward(lbfd_sg *s, const uint16_t *d_in, int32_t B, int32_t d, int32_t h, int32_t w, float *d_out);
 
-/* Mean squared error of the network on B training tiles (d_in as above with
- * d = h = w = tile + 8; d_target: FP32 [B][tile][tile][tile][2]) and its
- * gradient in parameter order (host, n entries). Synchronous. */
+/* Mean squared error of the network's conservative form on B training tiles
+ * (d_in as above with d = h = w = tile + 8; d_target: FP32
+ * [B][tile][tile][tile][4] = (W dpsi / dpsi_s, X dphi / dphi_s, W, X) per
+ * output node, as lbfd_sg_tiles writes it), over both fields and the tiles'
+ * interior nodes, and its gradient in parameter order (host, n entries).
+ * Synchronous. */
 int lbfd_sg_gradient(lbfd_sg *s, const uint16_t *d_in, const float *d_target, int32_t B, double *loss,
                      float *host_grad, int64_t n);
 
@@ -96,8 +112,10 @@ int lbfd_sg_features(lbfd_handle *h, lbfd_sg *s, uint16_t *d_feat);
 int lbfd_sg_snapshot(lbfd_handle *h, lbfd_sg *s, float *d_snap);
 
 /* Training tiles: inputs cropped from a feature grid (as lbfd_sg_features
- * wrote it) and targets (psi, phi of the solver now minus d_snap, scaled by
- * dpsi_s, dphi_s) over the tile's output nodes. Tile b has its output corner
+ * wrote it) and targets over the tile's output nodes: the changes of the
+ * conserved densities, W (psi now - d_snap psi) / dpsi_s and
+ * X (phi now - d_snap phi) / dphi_s, and the weights W, X of the current state
+ * (FP32 [B][tile][tile][tile][4]). Tile b has its output corner
  * at node (org[3b], org[3b+1], org[3b+2]) = (x, y, z) with x + tile <= nx,
  * y + tile <= ny, z + tile <= nz (so training tiles come from 3-D grids). */
 int lbfd_sg_tiles(lbfd_handle *h, lbfd_sg *s, const uint16_t *d_feat, const float *d_snap,
@@ -105,8 +123,10 @@ int lbfd_sg_tiles(lbfd_handle *h, lbfd_sg *s, const uint16_t *d_feat, const floa
 
 /* Advance the solver by nblocks blocks of k steps in surrogate mode. Each
  * block first advances psi and phi by k frozen-flow substeps with the network
- * (whole grid, one application) and checks the pre-rescale drift of the total
- * surfactant against drift_tol; if the check fails the network's result is
+ * (whole grid, one application, in the conservative form above) and checks the
+ * change it makes to the total surfactant before any rescaling against
+ * drift_tol, and its plausibility (see drift_tol); if a check fails the
+ * network's result is
  * discarded and lbfd_fd_substeps(k) is applied instead. Then the lattice
  * Boltzmann part advances k steps with psi and phi held (lagged coupling).
  * rep (if not NULL) accumulates counts over the call. Synchronises once per

@@ -9,12 +9,29 @@ channel) order, the node order of the solver's fields.
 * conv(x, w, b)[v, o] = b[o] + sum over taps (a, p, q) in {0,1,2}^3 and input
   channels i of x[v + (a, p, q), i] * w[a, p, q, i, o]  (a "valid" 3x3x3
   convolution: each spatial extent shrinks by two).
-* Four layers, channels 6 -> 32 -> 32 -> 32 -> 2, ReLU after the first three;
+* Four layers, channels 6 -> 32 -> 32 -> 32 -> 7, ReLU after the first three;
   the last layer is linear. A 40^3 input tile gives a 32^3 output tile.
 * Input channels per node: psi / psi_inf, phi / phi_s, rhoN, and u_x, u_y, u_z
-  divided by u_s (u_z = 0 in 2-D). Output channels: the change of psi and of
-  phi over the k substeps, divided by dpsi_s and dphi_s.
-* Loss: the mean over output nodes and both channels of the squared error.
+  divided by u_s (u_z = 0 in 2-D).
+* Output channels (conservative form): per node n, raw flux coefficients
+  f_psi_a, f_phi_a (a = x, y, z) and an exchange coefficient s. The fluxes of
+  the conserved densities W psi and X phi (W = G + fd_eps, X = 1 - rhoN +
+  fd_eps, the weights of eqs 20-21, held over the substeps) through the face
+  between n and n + e_a carry the face weight of their field, and the exchange
+  from bulk to interface carries the interface weight, as the transport terms
+  and the source G j of eqs 20-21 do:
+      Fpsi_a[n] = (W[n] + W[n + e_a])/2 f_psi_a[n],  Fphi_a[n] = (X[n] + X[n + e_a])/2 f_phi_a[n],
+      S[n] = W[n] s[n].
+  The changes of the conserved densities over the k substeps are
+      dM_psi[n] = dpsi_s (-sum_a (Fpsi_a[n] - Fpsi_a[n - e_a]) + S[n])
+      dM_phi[n] = dphi_s (-sum_a (Fphi_a[n] - Fphi_a[n - e_a])) - dpsi_s S[n]
+  so sum_n (dM_psi + dM_phi) = 0 on a periodic grid whatever the network
+  outputs: the total surfactant of eqs 20-21 is conserved by construction.
+  psi and phi change by dM_psi / W and dM_phi / X. On a tile of T^3 output
+  nodes the changes exist on the interior nodes [1, T - 2]^3 (every face they
+  need lies inside the tile).
+* Targets: W dpsi / dpsi_s and X dphi / dphi_s on the interior nodes. Loss: the
+  mean over them and both fields of the squared error of the changes above.
 * Adam with bias correction (Kingma and Ba, 2015), on FP32-like master weights
   (here FP64).
 
@@ -25,7 +42,8 @@ from __future__ import annotations
 
 import numpy as np
 
-LAYERS = ((6, 32), (32, 32), (32, 32), (32, 2))
+LAYERS = ((6, 32), (32, 32), (32, 32), (32, 7))
+NOUT = LAYERS[-1][1]        # 3 + 3 fluxes and the exchange
 HALO = len(LAYERS)          # each layer trims one node per side
 
 
@@ -109,13 +127,59 @@ def forward(ps, x):
     return h, acts
 
 
-def loss_and_grads(ps, x, t):
-    """Mean squared error of the output against t, and its gradient for every
-    weight and bias (backpropagation through the layers above)."""
+def _interior(shape, axis=None, d=0):
+    """Slices of the interior nodes (1 .. extent - 2 along each spatial axis) of a
+    [B, D, H, W, ...] grid, shifted by d along the spatial axis `axis` (0 = x,
+    the last one; 1 = y; 2 = z)."""
+    sl = [slice(1, e - 1) for e in shape[1:4]]
+    if axis is not None:
+        e = shape[3 - axis]
+        sl[2 - axis] = slice(1 + d, e - 1 + d)
+    return (slice(None),) + tuple(sl)
+
+
+def conserved_changes(o, W, X, ratio):
+    """Scaled changes (A_psi, A_phi) = (dM_psi / dpsi_s, dM_phi / dphi_s) of the
+    conserved densities on the interior nodes of the output o[B, T, T, T, 7],
+    with the weights W, X[B, T, T, T]; ratio = dpsi_s / dphi_s."""
+    I = _interior(o.shape)
+    Ap = W[I] * o[I + (6,)]
+    Af = -ratio * W[I] * o[I + (6,)]
+    for a in range(3):
+        up, lo = _interior(o.shape, a, 1), _interior(o.shape, a, -1)
+        for A, Wt, c in ((Ap, W, a), (Af, X, 3 + a)):
+            A -= 0.5 * (Wt[I] + Wt[up]) * o[I + (c,)]     # out through the upper face
+            A += 0.5 * (Wt[lo] + Wt[I]) * o[lo + (c,)]    # in through the lower face
+    return Ap, Af
+
+
+def conserved_changes_adjoint(g_psi, g_phi, W, X, ratio, shape):
+    """Adjoint of `conserved_changes` in o: the gradient with respect to o of
+    sum(g_psi A_psi + g_phi A_phi)."""
+    do = np.zeros(shape)
+    I = _interior(shape)
+    do[I + (6,)] += W[I] * (g_psi - ratio * g_phi)
+    for a in range(3):
+        up, lo = _interior(shape, a, 1), _interior(shape, a, -1)
+        for g, Wt, c in ((g_psi, W, a), (g_phi, X, 3 + a)):
+            do[I + (c,)] -= 0.5 * (Wt[I] + Wt[up]) * g
+            do[lo + (c,)] += 0.5 * (Wt[lo] + Wt[I]) * g
+    return do
+
+
+def loss_and_grads(ps, x, t, ratio=1.0):
+    """Mean squared error of the conserved changes against the targets
+    t[B, T, T, T, 4] = (W dpsi / dpsi_s, X dphi / dphi_s, W, X) on the interior
+    nodes, and its gradient for every weight and bias (backpropagation through
+    the conservative form and the layers above)."""
     o, acts = forward(ps, x)
-    r = o - t
-    L = float((r * r).mean())
-    dy = 2.0 * r / r.size
+    W, X = t[..., 2], t[..., 3]
+    Ap, Af = conserved_changes(o, W, X, ratio)
+    I = _interior(o.shape)
+    rp, rf = Ap - t[I + (0,)], Af - t[I + (1,)]
+    n = 2 * rp.size
+    L = float(((rp * rp).sum() + (rf * rf).sum()) / n)
+    dy = conserved_changes_adjoint(2.0 * rp / n, 2.0 * rf / n, W, X, ratio, o.shape)
     grads = [None] * len(ps)
     for li in range(len(ps) - 1, -1, -1):
         w, _ = ps[li]
@@ -156,8 +220,14 @@ def pad_periodic(x, h=HALO):
     return np.pad(x, ((h, h), (h, h), (h, h), (0, 0)), mode="wrap")
 
 
-def predict_fields(ps, psi, phi, rhoN, u, scales):
-    """psi and phi after k substeps as the network predicts them on a periodic grid."""
+def predict_fields(ps, psi, phi, rhoN, u, G, scales):
+    """psi and phi after k substeps as the network predicts them on a periodic grid
+    (every face and neighbour taken periodically)."""
     x = pad_periodic(features(psi, phi, rhoN, u, scales))[None]
     o, _ = forward(ps, x)
-    return psi + scales["dpsi_s"] * o[0, ..., 0], phi + scales["dphi_s"] * o[0, ..., 1]
+    W = (G + scales["fd_eps"])[None]
+    X = (1.0 - rhoN + scales["fd_eps"])[None]
+    # one periodic layer around the grid makes every node an interior node
+    wrap = lambda a: np.pad(a, ((0, 0), (1, 1), (1, 1), (1, 1)) + ((0, 0),) * (a.ndim - 4), mode="wrap")
+    Ap, Af = conserved_changes(wrap(o), wrap(W), wrap(X), scales["dpsi_s"] / scales["dphi_s"])
+    return psi + scales["dpsi_s"] * Ap[0] / W[0], phi + scales["dphi_s"] * Af[0] / X[0]

@@ -1411,7 +1411,9 @@ template <class R> __global__ __launch_bounds__(256) void k_sg_snapshot(KP<R> k,
 }
 
 // Training tiles: the input crop of tile b from the feature grid (edge T + 8) and the
-// target over its T^3 output nodes: (psi, phi now - snap) / (dpsi_s, dphi_s).
+// targets over its T^3 output nodes: the changes of the conserved densities,
+// W (psi now - snap) / dpsi_s and X (phi now - snap) / dphi_s, and the weights
+// W = G + fd_eps, X = 1 - rhoN + fd_eps (held over the frozen-flow substeps).
 template <class R>
 __global__ __launch_bounds__(256) void k_sg_tiles(KP<R> k, const uint16_t *feat, const float *snap, const int *org,
                                                  int T, uint16_t *tin, float *tgt, float idpsi, float idphi)
@@ -1433,24 +1435,61 @@ __global__ __launch_bounds__(256) void k_sg_tiles(KP<R> k, const uint16_t *feat,
         const long long i = t % T, j = (t / T) % T, l = t / ((long long)T * T);
         const uint32_t n = (uint32_t)((ox + i) + k.nx * ((oy + j) + (long long)k.ny * (oz + l)));
         const float ps = (float)(sc * (double)ld(k.fld.psi[k.pc], n)), ph = (float)(sc * (double)ld(k.fld.phi[k.pc], n));
-        float *o = tgt + ((long long)b * nout + t) * 2;
-        o[0] = (ps - snap[2 * (long long)n]) * idpsi;
-        o[1] = (ph - snap[2 * (long long)n + 1]) * idphi;
+        const float W = (float)(ld(k.fld.G[k.lev], n) + k.fd_eps);
+        const float X = (float)((R(1) - ld(k.fld.mac[k.lev] + 2 * k.N, n)) + k.fd_eps);
+        float *o = tgt + ((long long)b * nout + t) * 4;
+        o[0] = W * (ps - snap[2 * (long long)n]) * idpsi;
+        o[1] = X * (ph - snap[2 * (long long)n + 1]) * idphi;
+        o[2] = W;
+        o[3] = X;
     }
 }
 
-// Candidate of a surrogate update into the other FD buffers: psi + dpsi_s o[.][0],
-// phi + dphi_s o[.][1] (physical values, as an FD update leaves them).
+// Candidate of a surrogate update into the other FD buffers, from the network's
+// output o[N][7] on the periodic grid (the conservative form: face fluxes
+// weighted by the face weights of their field, the exchange by the interface
+// weight): psi + dpsi_s A_psi / W, phi + dphi_s A_phi / X (physical values, as
+// an FD update leaves them). Nodes where the result is not finite, or where the
+// interface (W >= 1e-3) or the bulk (X >= 1e-3) carries weight and psi or phi
+// changes by more than 20 times its change scale (dpsi_s, dphi_s: the 99.9 %
+// quantile of the FD update's changes), are counted.
 template <class R>
 __global__ __launch_bounds__(256) void k_sg_apply(KP<R> k, const float *o, float dpsi, float dphi)
 {
     const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
     if (n >= k.N) return;
     const uint32_t i = (uint32_t)n;
+    const int x = (int)(n % k.nx), y = (int)((n / k.nx) % k.ny), z = (int)(n / ((long long)k.nx * k.ny));
+    const R *G = k.fld.G[k.lev], *rN = k.fld.mac[k.lev] + 2 * k.N;
+    const auto Wof = [&](uint32_t m) { return (float)(ld(G, m) + k.fd_eps); };
+    const auto Xof = [&](uint32_t m) { return (float)((R(1) - ld(rN, m)) + k.fd_eps); };
+    const float ratio = dpsi / dphi;
+    const float Wn = Wof(i), Xn = Xof(i);
+    float Ap = Wn * o[sg::NOUT * n + 6], Af = -ratio * Wn * o[sg::NOUT * n + 6];
+    const int c[3] = {x, y, z}, ext[3] = {k.nx, k.ny, k.nz};
+    const long long sd[3] = {1, k.nx, (long long)k.nx * k.ny};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t u = (uint32_t)(c[a] + 1 < ext[a] ? n + sd[a] : n - (ext[a] - 1) * sd[a]);
+        const uint32_t d = (uint32_t)(c[a] > 0 ? n - sd[a] : n + (ext[a] - 1) * sd[a]);
+        Ap -= 0.5f * (Wn + Wof(u)) * o[sg::NOUT * n + a];
+        Ap += 0.5f * (Wof(d) + Wn) * o[sg::NOUT * (long long)d + a];
+        Af -= 0.5f * (Xn + Xof(u)) * o[sg::NOUT * n + 3 + a];
+        Af += 0.5f * (Xof(d) + Xn) * o[sg::NOUT * (long long)d + 3 + a];
+    }
     const double sc = k.fld.sc->scale;
-    st(k.fld.psi[1 - k.pc], i, (R)(sc * (double)ld(k.fld.psi[k.pc], i) + (double)dpsi * (double)o[2 * n]));
-    st(k.fld.phi[1 - k.pc], i, (R)(sc * (double)ld(k.fld.phi[k.pc], i) + (double)dphi * (double)o[2 * n + 1]));
+    const double dps = (double)dpsi * (double)Ap / (double)Wn, dph = (double)dphi * (double)Af / (double)Xn;
+    const double ps = sc * (double)ld(k.fld.psi[k.pc], i) + dps;
+    const double ph = sc * (double)ld(k.fld.phi[k.pc], i) + dph;
+    st(k.fld.psi[1 - k.pc], i, (R)ps);
+    st(k.fld.phi[1 - k.pc], i, (R)ph);
+    const bool bad = !(std::isfinite(ps) && std::isfinite(ph)) || (Wn >= 1e-3f && fabs(dps) > 20.0 * (double)dpsi) ||
+                     (Xn >= 1e-3f && fabs(dph) > 20.0 * (double)dphi);
+    if (bad) atomicAdd(&k.fld.sc->sg_bad, 1u);
 }
+
+// Clears the candidate's range counter (one thread).
+template <class R> __global__ void k_sg_clear(KP<R> k) { k.fld.sc->sg_bad = 0u; }
 
 // ============================================================== reductions
 
@@ -1473,13 +1512,15 @@ template <int NV> __device__ __forceinline__ void block_sum_store(double (&v)[NV
 }
 
 // Per-block FP64 sums of G psi + X phi (the conserved integrand of eqs 20-21)
-// at `level`, psi/phi from buffer `buf` times `mult`.
+// at `level`, psi/phi from buffer `buf` times `mult` (mult < 0: the device's
+// rescaling factor, which turns stored values into physical ones).
 template <int LAT, class P>
 __device__ __forceinline__ void total_part_body(const KP<typename P::R> &k, int level, int buf, double mult, int blk,
                                                 int nblk, int from_split)
 {
     using R = typename P::R;
     const long long N = k.N;
+    if (mult < 0.0) mult = k.fld.sc->scale;
     double v[1] = {0.0};
     for (long long n = (long long)blk * blockDim.x + threadIdx.x; n < N; n += (long long)nblk * blockDim.x) {
         const uint32_t i = (uint32_t)n;
@@ -1540,8 +1581,11 @@ template <class R> __device__ __forceinline__ void total_final_body(const KP<R> 
             sc->scale = 1.0;
             sc->scale_prev = 1.0;
         } else if (mode == 2) {
-            // probe: the relative drift of a candidate only (nothing else changes)
-            sc->drift_pre = sc->M0 != 0.0 ? (M - sc->M0) / sc->M0 : 0.0;
+            // probe: the relative change of the total that a candidate makes to the
+            // state it starts from (mode 3), at the same weights (nothing else changes)
+            sc->drift_pre = sc->Mref != 0.0 ? (M - sc->Mref) / sc->Mref : 0.0;
+        } else if (mode == 3) {
+            sc->Mref = M;
         } else {
             sc->scale_prev = sc->scale;
             sc->Mlast = M;
@@ -2288,6 +2332,8 @@ template <int LAT, class P> struct Impl {
     {
         sync_levels(h);
         KP<R> &k = kp(h);
+        LAUNCH(KC_OTHER, (k_sg_clear<R>), dim3(1), dim3(1), k);
+        totals(h, k.lev, k.pc, -1.0, 3);   // the total the candidate starts from (stored values x scale)
         LAUNCH(KC_OTHER, (k_sg_apply<R>), dim3((unsigned)((h->N + 255) / 256)), dim3(256), k, o, dpsi, dphi);
         totals(h, k.lev, 1 - k.pc, 1.0, 2);
         return hipGetLastError() == hipSuccess ? LBFD_OK : LBFD_EHIP;
@@ -3111,7 +3157,7 @@ struct lbfd_sg {
     double *loss;            // FP64 loss accumulator
     uint16_t *act[3];        // outputs of layers 1-3, BF16 [nodes][32]
     uint16_t *dy[2];         // gradients of layer outputs, BF16 [nodes][32]
-    float *out;              // network output, FP32 [nodes][2]
+    float *out;              // network output, FP32 [nodes][NOUT]
     uint16_t *feat;          // whole-field input grid, BF16 [nz+8][ny+8][nx+8][16]
     int *org;                // tile origins [3 max_batch]
     long long cap_act, cap_out, cap_feat;
@@ -3135,7 +3181,7 @@ struct SgLayout {
 
 static int sg_layout(const lbfd_sg_params *p, SgLayout *L)
 {
-    if (!p || p->tile < 1 || p->tile > 64 || p->max_batch < 1 || p->k < 1) return LBFD_EINVAL;
+    if (!p || p->tile < 3 || p->tile > 64 || p->max_batch < 1 || p->k < 1) return LBFD_EINVAL;
     if (!(p->psi_inf > 0 && p->phi_s > 0 && p->u_s > 0 && p->dpsi_s > 0 && p->dphi_s > 0)) return LBFD_EINVAL;
     if (!(p->lr > 0 && p->beta1 >= 0 && p->beta1 < 1 && p->beta2 >= 0 && p->beta2 < 1 && p->adam_eps > 0))
         return LBFD_EINVAL;
@@ -3167,7 +3213,7 @@ static int sg_layout(const lbfd_sg_params *p, SgLayout *L)
     L->loss = take(8);
     for (int i = 0; i < 3; ++i) L->act[i] = take((size_t)ca * sg::CO * 2);
     for (int i = 0; i < 2; ++i) L->dy[i] = take((size_t)ca * sg::CO * 2);
-    L->out = take((size_t)co * 2 * 4);
+    L->out = take((size_t)co * sg::NOUT * 4);
     L->feat = take((size_t)cf * sg::IN_CH * 2);
     L->org = take(sizeof(int) * 3 * (size_t)B);
     L->total = o;
@@ -3337,9 +3383,10 @@ static int sg_backward(lbfd_sg *s, const uint16_t *in, const float *tgt, int B)
     }
     if (hipMemsetAsync(s->loss, 0, sizeof(double), st) != hipSuccess) return LBFD_EHIP;
     const long long M4 = layer_nodes(4, B, E, E, E);
-    const float scale = (float)(2.0 / (2.0 * (double)M4));
-    hipLaunchKernelGGL(sg::k_loss, dim3(std::min(1024u, blocks_for(M4, 256))), dim3(256), 0, st, s->out, tgt, M4,
-                       scale, s->loss, s->dy[0]);
+    const long long T = s->p.tile;
+    const float scale = (float)(2.0 / (2.0 * (double)B * (double)cube(T - 2)));
+    hipLaunchKernelGGL(sg::k_cons_loss, dim3(std::min(1024u, blocks_for(M4, 256))), dim3(256), 0, st, s->out, tgt,
+                       (int)T, M4, (float)(s->p.dpsi_s / s->p.dphi_s), scale, s->loss, s->dy[0]);
     int cur = 0;   // s->dy[cur]: gradient at the output of layer l + 1
     for (int l = sg::NL - 1; l >= 0; --l) {
         const int Di = E - 2 * l;
@@ -3388,7 +3435,7 @@ int lbfd_sg_gradient(lbfd_sg *s, const uint16_t *d_in, const float *d_target, in
         hipStreamSynchronize(s->stream) != hipSuccess)
         return LBFD_EHIP;
     const long long E = s->p.tile;
-    if (loss) *loss = L / (2.0 * (double)B * (double)cube(E));
+    if (loss) *loss = L / (2.0 * (double)B * (double)cube(E - 2));
     return LBFD_OK;
 }
 
@@ -3406,7 +3453,7 @@ int lbfd_sg_train_step(lbfd_sg *s, const uint16_t *d_in, const float *d_target, 
         if (hipMemcpyAsync(&L, s->loss, sizeof(double), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
             hipStreamSynchronize(s->stream) != hipSuccess)
             return LBFD_EHIP;
-        *loss = L / (2.0 * (double)B * (double)cube(s->p.tile));
+        *loss = L / (2.0 * (double)B * (double)cube(s->p.tile - 2));
     }
     return LBFD_OK;
 }
@@ -3476,8 +3523,10 @@ int lbfd_sg_advance(lbfd_handle *h, lbfd_sg *s, int64_t nblocks, lbfd_sg_report 
         DevScalars sc;
         if (rc == LBFD_OK) rc = dp.read_scalars(h, &sc);
         if (rc != LBFD_OK) return rc;
+        // the conservation check (the candidate's relative change of the total at the
+        // frozen weights, before any rescaling) and the plausibility check
         const double drift = sc.drift_pre;
-        const bool keep = std::isfinite(drift) && std::fabs(drift) <= s->p.drift_tol;
+        const bool keep = std::isfinite(drift) && std::fabs(drift) <= s->p.drift_tol && sc.sg_bad == 0;
         rc = keep ? dp.sg_accept(h) : dp.fd_substeps(h, k);
         if (rc != LBFD_OK) return rc;
         if (rep) {

@@ -169,6 +169,8 @@ struct DevScalars {
     int32_t status;               // sticky lbfd_status of device-detected errors
     uint32_t tick;                // geometry launches since the state was set (one per step):
                                   // the time input of the stochastic rounding
+    uint32_t sg_bad;              // nodes where a surrogate candidate changed psi or phi implausibly
+    double Mref;                  // total of the state a surrogate candidate starts from
 };
 
 // FP16 helpers of the packed descriptor (round to nearest even).

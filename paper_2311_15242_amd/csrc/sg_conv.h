@@ -28,7 +28,8 @@ constexpr int NL = 4;                                  // layers
 constexpr int CO = 32;                                 // padded output channels of every layer
 constexpr int CIN_REAL[NL] = {6, 32, 32, 32};
 constexpr int CIN_PAD[NL] = {16, 32, 32, 32};
-constexpr int COUT_REAL[NL] = {32, 32, 32, 2};
+constexpr int COUT_REAL[NL] = {32, 32, 32, 7};
+constexpr int NOUT = 7;                                // network outputs: 3 + 3 flux coefficients, the exchange
 constexpr int IN_CH = 16;                              // channels of an input grid (6 used)
 
 __host__ __device__ constexpr long long layer_params(int l) { return 27LL * CIN_REAL[l] * COUT_REAL[l] + COUT_REAL[l]; }
@@ -63,7 +64,7 @@ constexpr int FWD_NODES = 4 * 32 * FWD_NT;   // output nodes per workgroup
 
 // Forward layer: out[m][o] = act(b[o] + sum_{tap,i} in[m + tap][i] w[tap][o][i]) over the
 // M = B (Di-2)(Hi-2)(Wi-2) output nodes. wb: BF16 [27][32][CIN] (input channel fastest).
-// out: BF16 [M][32], or with OUTF32 FP32 [M][2] (the first two channels, no activation).
+// out: BF16 [M][32], or with OUTF32 FP32 [M][NOUT] (the first NOUT channels, no activation).
 // Each wavefront computes FWD_NT tiles of 32 nodes x 32 channels; every weight
 // fragment read from LDS feeds FWD_NT matrix instructions.
 template <int CIN, bool RELU, bool OUTF32>
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ in, co
             if (m >= M) continue;
             float v = acc[t][r] + bv;
             if constexpr (OUTF32) {
-                if (mr < 2) ((float *)out)[m * 2 + mr] = v;
+                if (mr < NOUT) ((float *)out)[m * NOUT + mr] = v;
             } else {
                 if (RELU) v = fmaxf(v, 0.0f);
                 ((u16 *)out)[m * CO + mr] = f2bf(v);
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_brick(const u16 *__restrict__ 
             const long long m = ((b * Do + z) * Ho + y) * (long long)Wo + x;
             float v = acc[t][r] + bv;
             if constexpr (OUTF32) {
-                if (mr < 2) ((float *)out)[m * 2 + mr] = v;
+                if (mr < NOUT) ((float *)out)[m * NOUT + mr] = v;
             } else {
                 if (RELU) v = fmaxf(v, 0.0f);
                 ((u16 *)out)[m * CO + mr] = f2bf(v);
@@ -388,23 +389,86 @@ __global__ __launch_bounds__(256) void k_bias_grad(const u16 *__restrict__ dy, l
     }
 }
 
-// Loss: squared error of the output o (FP32 [M][2]) against t, summed into *acc (FP64),
-// and the output gradient dy = scale (o - t) as BF16 [M][32] (channels 2.. zero).
-__global__ __launch_bounds__(256) void k_loss(const float *__restrict__ o, const float *__restrict__ t, long long M,
-                                             float scale, double *__restrict__ acc, u16 *__restrict__ dy)
+// Conservative form of the output (the network's 7 channels per node n of a T^3
+// tile: flux coefficients f_psi,a, f_phi,a, a = x, y, z, and the exchange s):
+//   A_psi[n] = W[n] s[n] - sum_a (Wf_a[n] f_psi,a[n] - Wf_a[n - e_a] f_psi,a[n - e_a])
+//   A_phi[n] = -ratio W[n] s[n] - sum_a (Xf_a[n] f_phi,a[n] - Xf_a[n - e_a] f_phi,a[n - e_a])
+// with face weights Wf_a[n] = (W[n] + W[n + e_a])/2 (the same for X), on the
+// interior nodes [1, T - 2]^3. t holds per node (W dpsi / dpsi_s, X dphi / dphi_s, W, X).
+__device__ __forceinline__ void cons_changes(const float *o, const float *t, int T, long long base, int i, int j,
+                                             int l, float ratio, float &Ap, float &Af)
+{
+    const long long n = base + ((long long)l * T + j) * T + i;
+    const long long st[3] = {1, T, (long long)T * T};
+    const float Wn = t[4 * n + 2], Xn = t[4 * n + 3];
+    Ap = Wn * o[NOUT * n + 6];
+    Af = -ratio * Wn * o[NOUT * n + 6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long long u = n + st[a], d = n - st[a];
+        Ap -= 0.5f * (Wn + t[4 * u + 2]) * o[NOUT * n + a];
+        Ap += 0.5f * (t[4 * d + 2] + Wn) * o[NOUT * d + a];
+        Af -= 0.5f * (Xn + t[4 * u + 3]) * o[NOUT * n + 3 + a];
+        Af += 0.5f * (t[4 * d + 3] + Xn) * o[NOUT * d + 3 + a];
+    }
+}
+
+// Loss of B tiles of T^3 output nodes: squared error of the conservative form
+// against the targets, summed into *acc (FP64), and the output gradient dy (BF16
+// [M][32], channels NOUT.. zero) of scale/2 times that sum: per node the adjoint
+// of the form above, from the residuals g = scale (A - target) of the node and of
+// its upper neighbours.
+__global__ __launch_bounds__(256) void k_cons_loss(const float *__restrict__ o, const float *__restrict__ t, int T,
+                                                  long long M, float ratio, float scale, double *__restrict__ acc,
+                                                  u16 *__restrict__ dy)
 {
     __shared__ double sh[256];
     double s = 0.0;
+    const long long TT = (long long)T * T * T;
     for (long long m = (long long)blockIdx.x * 256 + threadIdx.x; m < M; m += (long long)gridDim.x * 256) {
-        const float r0 = o[2 * m] - t[2 * m], r1 = o[2 * m + 1] - t[2 * m + 1];
-        s += (double)r0 * r0 + (double)r1 * r1;
-        u32x4 head = {(uint32_t)f2bf(scale * r0) | ((uint32_t)f2bf(scale * r1) << 16), 0u, 0u, 0u};
+        const long long b = m / TT, r = m - b * TT, base = b * TT;
+        const int i = (int)(r % T), j = (int)((r / T) % T), l = (int)(r / ((long long)T * T));
+        const auto inner = [&](int ii, int jj, int ll) {
+            return ii >= 1 && jj >= 1 && ll >= 1 && ii <= T - 2 && jj <= T - 2 && ll <= T - 2;
+        };
+        // residuals at the node (gp0, gf0) and at its upper neighbours along x, y, z
+        float gp[4] = {0, 0, 0, 0}, gf[4] = {0, 0, 0, 0};
+        const int ci[4] = {i, i + 1, i, i}, cj[4] = {j, j, j + 1, j}, cl[4] = {l, l, l, l + 1};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (!inner(ci[c], cj[c], cl[c])) continue;
+            float Ap, Af;
+            cons_changes(o, t, T, base, ci[c], cj[c], cl[c], ratio, Ap, Af);
+            const long long nc = base + ((long long)cl[c] * T + cj[c]) * T + ci[c];
+            const float rp = Ap - t[4 * nc], rf = Af - t[4 * nc + 1];
+            if (c == 0) s += (double)rp * rp + (double)rf * rf;
+            gp[c] = scale * rp;
+            gf[c] = scale * rf;
+        }
+        const long long n = base + r;
+        const float Wn = t[4 * n + 2], Xn = t[4 * n + 3];
+        float d[8];
+        const long long st[3] = {1, T, (long long)T * T};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            // face between n and n + e_a: out of n (g at n), into n + e_a (g there)
+            const bool up_in = (a == 0 ? i : a == 1 ? j : l) + 1 <= T - 1;
+            const float Wf = up_in ? 0.5f * (Wn + t[4 * (n + st[a]) + 2]) : 0.0f;
+            const float Xf = up_in ? 0.5f * (Xn + t[4 * (n + st[a]) + 3]) : 0.0f;
+            d[a] = Wf * (gp[1 + a] - gp[0]);
+            d[3 + a] = Xf * (gf[1 + a] - gf[0]);
+        }
+        d[6] = Wn * (gp[0] - ratio * gf[0]);
+        d[7] = 0.0f;
+        u32x4 head = {(uint32_t)f2bf(d[0]) | ((uint32_t)f2bf(d[1]) << 16),
+                      (uint32_t)f2bf(d[2]) | ((uint32_t)f2bf(d[3]) << 16),
+                      (uint32_t)f2bf(d[4]) | ((uint32_t)f2bf(d[5]) << 16), (uint32_t)f2bf(d[6])};
         u32x4 zero = {0u, 0u, 0u, 0u};
-        u32x4 *d = (u32x4 *)&dy[m * CO];
-        d[0] = head;
-        d[1] = zero;
-        d[2] = zero;
-        d[3] = zero;
+        u32x4 *dd = (u32x4 *)&dy[m * CO];
+        dd[0] = head;
+        dd[1] = zero;
+        dd[2] = zero;
+        dd[3] = zero;
     }
     sh[threadIdx.x] = s;
     __syncthreads();

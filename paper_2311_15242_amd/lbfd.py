@@ -478,11 +478,14 @@ def _dptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+SG_NOUT = 7   # network outputs per node: flux coefficients of psi and phi along x, y, z, and the exchange
+
+
 class Surrogate:
     """The learned surrogate of k frozen-flow FD substeps (weights, Adam state and
     work buffers on one device workspace). Tensors passed in are torch device
     tensors: inputs as int16/uint16-sized BF16 bit patterns (torch.bfloat16 is
-    accepted as is), targets and outputs FP32."""
+    accepted as is), targets [..., 4] and outputs [..., SG_NOUT] FP32."""
 
     DEFAULTS = dict(tile=32, max_batch=8, field=(0, 0, 0), k=8, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8,
                     psi_inf=1.0, phi_s=0.1, u_s=0.01, dpsi_s=0.01, dphi_s=0.001, drift_tol=1e-6)

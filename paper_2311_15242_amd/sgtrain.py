@@ -54,7 +54,7 @@ def snapshot_tiles(solver, sg, n_tiles: int, rng, bufs=None, interface_share: fl
     sg.snapshot(solver, snap)
     solver.fd_substeps(sg.cfg["k"])
     X = torch.empty((n_tiles, T + 8, T + 8, T + 8, 16), dtype=torch.int16, device=solver.device)
-    Y = torch.empty((n_tiles, T, T, T, 2), dtype=torch.float32, device=solver.device)
+    Y = torch.empty((n_tiles, T, T, T, 4), dtype=torch.float32, device=solver.device)
     mb = sg.cfg["max_batch"]
     for a in range(0, n_tiles, mb):
         b = min(n_tiles, a + mb)
@@ -91,27 +91,53 @@ def train(sg, X, Y, steps: int, batch: int, rng, log_every: int = 0):
     return hist
 
 
+def conserved_changes(o, Y, ratio):
+    """The conservative form of the network's tile output o[B, T, T, T, 7] (the
+    changes of W psi / dpsi_s and X phi / dphi_s on the interior nodes), with the
+    weights W, X of the targets Y[..., 2:4]; for the error measure only (training
+    and application evaluate it in the library's kernels)."""
+    W, X = Y[..., 2], Y[..., 3]
+    I = (slice(None), slice(1, -1), slice(1, -1), slice(1, -1))
+
+    def sh(a, axis, d):
+        sl = [slice(1, -1)] * 3
+        sl[2 - axis] = slice(1 + d, a.shape[3 - axis] - 1 + d)
+        return a[(slice(None),) + tuple(sl)]
+
+    Ap = W[I] * o[I + (6,)]
+    Af = -ratio * W[I] * o[I + (6,)]
+    for a in range(3):
+        for A, Wt, c in ((Ap, W, a), (Af, X, 3 + a)):
+            A -= 0.5 * (Wt[I] + sh(Wt, a, 1)) * o[I + (c,)]
+            A += 0.5 * (sh(Wt, a, -1) + Wt[I]) * sh(o[..., c], a, -1)
+    return Ap, Af
+
+
 def tile_error(sg, X, Y):
-    """Relative L2 error of the network's tile outputs against the targets, and
-    that of predicting no change at all (the trivial predictor)."""
+    """Relative L2 error of the network's conserved changes on the tiles' interior
+    nodes against the targets, and that of predicting no change at all."""
     import torch
 
     mb = sg.cfg["max_batch"]
     T = sg.cfg["tile"]
+    ratio = sg.cfg["dpsi_s"] / sg.cfg["dphi_s"]
+    I = (slice(None), slice(1, -1), slice(1, -1), slice(1, -1))
     num = den = 0.0
     for a in range(0, X.shape[0], mb):
         b = min(X.shape[0], a + mb)
-        out = torch.empty((b - a, T, T, T, 2), dtype=torch.float32, device=X.device)
+        out = torch.empty((b - a, T, T, T, lbfd.SG_NOUT), dtype=torch.float32, device=X.device)
         sg.forward(X[a:b].contiguous(), out)
-        num += float(((out - Y[a:b]) ** 2).sum().item())
-        den += float((Y[a:b] ** 2).sum().item())
+        Ap, Af = conserved_changes(out, Y[a:b], ratio)
+        tp, tf = Y[a:b][I + (0,)], Y[a:b][I + (1,)]
+        num += float(((Ap - tp) ** 2).sum().item() + ((Af - tf) ** 2).sum().item())
+        den += float((tp ** 2).sum().item() + (tf ** 2).sum().item())
     return float(np.sqrt(num / max(den, 1e-300))), 1.0
 
 
 def initial_params(seed: int = 0, out_scale: float = 0.1):
     """He-normal weights, zero biases, a small last layer (parameter order of the C ABI)."""
     rng = np.random.default_rng(seed)
-    layers = ((6, 32), (32, 32), (32, 32), (32, 2))
+    layers = ((6, 32), (32, 32), (32, 32), (32, lbfd.SG_NOUT))
     parts = []
     for li, (ci, co) in enumerate(layers):
         w = rng.standard_normal(27 * ci * co) * np.sqrt(2.0 / (27 * ci))
@@ -121,4 +147,5 @@ def initial_params(seed: int = 0, out_scale: float = 0.1):
     return np.concatenate(parts).astype(np.float32)
 
 
-__all__ = ["feature_buffers", "tile_origins", "snapshot_tiles", "change_scales", "train", "tile_error", "initial_params", "lbfd"]
+__all__ = ["feature_buffers", "tile_origins", "snapshot_tiles", "change_scales", "train", "conserved_changes",
+           "tile_error", "initial_params", "lbfd"]

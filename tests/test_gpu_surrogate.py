@@ -64,22 +64,28 @@ def ref_forward(ps, x):
     return h, acts
 
 
-def ref_gradient(ps, x, t):
+def ref_gradient(ps, x, t, ratio):
+    """Loss of the conservative form and its gradient, with the kernels' BF16
+    roundings of the output gradient and of the layer gradients."""
     o, acts = ref_forward(ps, x)
-    r = o - t
-    dy = bf16(2.0 * r / r.size)
-    dy = np.concatenate([dy, np.zeros(dy.shape[:-1] + (30,))], axis=-1)   # padded output channels
+    W, X = t[..., 2], t[..., 3]
+    Ap, Af = OS.conserved_changes(o, W, X, ratio)
+    I = (slice(None), slice(1, -1), slice(1, -1), slice(1, -1))
+    rp, rf = Ap - t[I + (0,)], Af - t[I + (1,)]
+    n = 2 * rp.size
+    dy = bf16(OS.conserved_changes_adjoint(2.0 * rp / n, 2.0 * rf / n, W, X, ratio, o.shape))
+    dy = np.concatenate([dy, np.zeros(dy.shape[:-1] + (32 - OS.NOUT,))], axis=-1)   # padded output channels
     grads = [None] * len(ps)
     for li in range(len(ps) - 1, -1, -1):
         w, _ = ps[li]
-        wpad = w if w.shape[-1] == 32 else np.concatenate([w, np.zeros(w.shape[:-1] + (30,))], axis=-1)
+        wpad = w if w.shape[-1] == 32 else np.concatenate([w, np.zeros(w.shape[:-1] + (32 - w.shape[-1],))], axis=-1)
         dw, db = OS.conv_grad_weight(acts[li], dy)
         co = w.shape[-1]
         grads[li] = [dw[..., :co], db[:co]]
         if li > 0:
             dx = OS.conv_grad_input(dy, wpad, acts[li].shape)
             dy = bf16(dx * (acts[li] > 0.0))
-    return float((r * r).mean()), grads
+    return float(((rp * rp).sum() + (rf * rf).sum()) / n), grads
 
 
 def make_sg(L, **kw):
@@ -119,7 +125,7 @@ def test_forward_matches_reference(lbfd):
     x6 = bf16(rng.uniform(-1.0, 1.0, (2, 11, 12, 13, 6)))
     sg = make_sg(lbfd, tile=4, max_batch=2)
     sg.set_params(OS.flatten(ps))
-    out = torch.empty((2, 3, 4, 5, 2), dtype=torch.float32, device="cuda")
+    out = torch.empty((2, 3, 4, 5, OS.NOUT), dtype=torch.float32, device="cuda")
     sg.forward(bf16_tensor(padded_input(x6)), out)
     ref, _ = ref_forward(ps, x6)
     err = float(np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max())
@@ -136,11 +142,12 @@ def test_gradient_matches_reference(lbfd):
     ps = gpu_params(OS.init_params(4, out_scale=1.0))
     T = 4
     x6 = bf16(rng.uniform(-1.0, 1.0, (2, T + 8, T + 8, T + 8, 6)))
-    t = rng.standard_normal((2, T, T, T, 2)).astype(np.float32)
-    sg = make_sg(lbfd, tile=T, max_batch=2)
+    t = rng.standard_normal((2, T, T, T, 4)).astype(np.float32)
+    t[..., 2:] = rng.uniform(0.05, 2.0, (2, T, T, T, 2))     # the weights W, X
+    sg = make_sg(lbfd, tile=T, max_batch=2, dpsi_s=0.02, dphi_s=0.005)
     sg.set_params(OS.flatten(ps))
     loss, g = sg.gradient(bf16_tensor(padded_input(x6)), torch.from_numpy(t).cuda())
-    Lr, gr = ref_gradient(ps, x6, t.astype(np.float64))
+    Lr, gr = ref_gradient(ps, x6, t.astype(np.float64), 0.02 / 0.005)
     say(f"loss gpu {loss:.6e} ref {Lr:.6e}")
     assert abs(loss - Lr) <= 1e-3 * Lr
     o = 0
@@ -193,9 +200,10 @@ def test_training_lowers_the_error(lbfd):
 
 
 def test_advance_fallback_is_the_fd_update(lbfd):
-    """Weights that predict nonsense fail the drift check every time; surrogate
-    mode then equals frozen-flow FD substeps followed by LB steps with psi held,
-    bit for bit."""
+    """Weights that predict nonsense fail the range check every time (the
+    conservative form keeps the total whatever the weights); surrogate mode then
+    equals frozen-flow FD substeps followed by LB steps with psi held, bit for
+    bit."""
     rng = np.random.default_rng(6)
     p, q = W.multi_bubble(n=24, count=1, diameter=10.0, seed=2, precision="fp32")
     a = lbfd.Solver(p).init_fields(q).step(6)
@@ -211,6 +219,25 @@ def test_advance_fallback_is_the_fd_update(lbfd):
     for name in ("f", "psi", "phi", "u", "rhoN"):
         assert np.array_equal(a.field(name), b.field(name)), name
     assert a.observables()["step"] == b.observables()["step"] == 18
+
+
+def test_advance_passes_the_strict_drift_check(lbfd):
+    """With the drift check at 1e-6 a network with small outputs is kept every
+    time: the conservative form changes the total surfactant only by rounding
+    before the rescaling, and the applied update is the network's own."""
+    from paper_2311_15242_amd import sgtrain
+
+    p, q = W.multi_bubble(n=24, count=1, diameter=10.0, seed=3, precision="fp32")
+    s = lbfd.Solver(p).init_fields(q).step(6)
+    psi0 = s.field("psi")
+    sg = make_sg(lbfd, tile=8, max_batch=1, k=4, field=(24, 24, 24), drift_tol=1e-6)
+    sg.set_params(sgtrain.initial_params(1, out_scale=0.01))
+    rep = sg.advance(s, 3)
+    say(rep)
+    assert rep["accepted"] == 3 and rep["fallbacks"] == 0
+    assert rep["max_drift"] <= 1e-6
+    assert s.observables()["status"] == 0
+    assert np.abs(s.field("psi") - psi0).max() > 0
 
 
 def test_advance_accepts_and_conserves(lbfd):
@@ -243,7 +270,7 @@ def test_forward_wide_grid_matches_reference(lbfd):
     x6 = bf16(rng.uniform(-1.0, 1.0, (1, 11, 14, 75, 6)))
     sg = make_sg(lbfd, tile=4, max_batch=1, field=(67, 6, 3))
     sg.set_params(OS.flatten(ps))
-    out = torch.empty((1, 3, 6, 67, 2), dtype=torch.float32, device="cuda")
+    out = torch.empty((1, 3, 6, 67, OS.NOUT), dtype=torch.float32, device="cuda")
     sg.forward(bf16_tensor(padded_input(x6)), out)
     ref, _ = ref_forward(ps, x6)
     err = float(np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max())

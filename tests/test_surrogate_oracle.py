@@ -62,9 +62,11 @@ def test_adjoint_identities():
 def test_gradients_match_central_differences():
     rng = np.random.default_rng(4)
     ps = S.init_params(5, out_scale=1.0)
-    x = rng.standard_normal((2, 10, 9, 9, 6))
-    t = rng.standard_normal((2, 2, 1, 1, 2))
-    L, grads = S.loss_and_grads(ps, x, t)
+    x = rng.standard_normal((2, 12, 12, 11, 6))
+    t = rng.standard_normal((2, 4, 4, 3, 4))
+    t[..., 2:] = rng.uniform(0.1, 2.0, (2, 4, 4, 3, 2))      # the weights W, X
+    ratio = 1.7
+    L, grads = S.loss_and_grads(ps, x, t, ratio)
     flat, g = S.flatten(ps), S.flatten(grads)
     idx = rng.choice(flat.size, 40, replace=False)
     # include biases of every layer
@@ -78,7 +80,7 @@ def test_gradients_match_central_differences():
         up, dn = flat.copy(), flat.copy()
         up[k] += h
         dn[k] -= h
-        fd = (S.loss_and_grads(S.unflatten(up), x, t)[0] - S.loss_and_grads(S.unflatten(dn), x, t)[0]) / (2 * h)
+        fd = (S.loss_and_grads(S.unflatten(up), x, t, ratio)[0] - S.loss_and_grads(S.unflatten(dn), x, t, ratio)[0]) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(abs(g[k]), 1e-3 * np.abs(g).max()), (k, fd, g[k])
 
 
@@ -96,7 +98,7 @@ def test_adam_first_step_closed_form():
 
 def test_parameter_layout():
     ps = S.init_params(8)
-    assert S.n_params() == 27 * (6 * 32 + 32 * 32 * 2 + 32 * 2) + 32 * 3 + 2 == 62306
+    assert S.n_params() == 27 * (6 * 32 + 32 * 32 * 2 + 32 * 7) + 32 * 3 + 7 == 66631
     assert np.array_equal(S.flatten(S.unflatten(S.flatten(ps))), S.flatten(ps))
 
 
@@ -104,11 +106,79 @@ def test_periodic_prediction_is_translation_equivariant():
     """On a periodic grid the predicted fields shift with the inputs."""
     rng = np.random.default_rng(9)
     ps = S.init_params(10, out_scale=1.0)
-    sc = dict(psi_inf=1.0, phi_s=0.1, u_s=0.01, dpsi_s=0.01, dphi_s=0.001)
+    sc = dict(psi_inf=1.0, phi_s=0.1, u_s=0.01, dpsi_s=0.01, dphi_s=0.001, fd_eps=1e-6)
     shape = (6, 7, 8)
     psi, phi, rN = rng.random(shape), 0.1 * rng.random(shape), rng.uniform(-1, 1, shape)
+    G = 0.3 * rng.random(shape)
     u = 0.01 * rng.standard_normal((3,) + shape)
-    a = S.predict_fields(ps, psi, phi, rN, u, sc)
+    a = S.predict_fields(ps, psi, phi, rN, u, G, sc)
     sh = lambda f: np.roll(f, (1, -2, 3), axis=(-3, -2, -1))
-    b = S.predict_fields(ps, sh(psi), sh(phi), sh(rN), sh(u), sc)
-    assert np.abs(sh(a[0]) - b[0]).max() < 1e-13 and np.abs(sh(a[1]) - b[1]).max() < 1e-13
+    b = S.predict_fields(ps, sh(psi), sh(phi), sh(rN), sh(u), sh(G), sc)
+    assert np.abs(sh(a[0]) - b[0]).max() < 1e-12 and np.abs(sh(a[1]) - b[1]).max() < 1e-12
+
+
+def _periodic_case(seed):
+    rng = np.random.default_rng(seed)
+    sc = dict(psi_inf=1.0, phi_s=0.1, u_s=0.01, dpsi_s=0.02, dphi_s=0.003, fd_eps=1e-6)
+    shape = (6, 7, 8)
+    return (rng.random(shape), 0.1 * rng.random(shape), rng.uniform(-1, 1, shape),
+            0.01 * rng.standard_normal((3,) + shape), 0.3 * rng.random(shape), sc)
+
+
+def test_prediction_conserves_the_total_surfactant():
+    """Whatever the weights, the flux form changes sum(W psi + X phi) only by
+    rounding (eqs 20-21: the divergences telescope on the periodic grid and
+    the exchange moves conserved density between the fields)."""
+    psi, phi, rN, u, G, sc = _periodic_case(11)
+    ps = S.init_params(12, out_scale=5.0)
+    W, X = G + sc["fd_eps"], 1.0 - rN + sc["fd_eps"]
+    p2, f2 = S.predict_fields(ps, psi, phi, rN, u, G, sc)
+    M0, M1 = (W * psi + X * phi).sum(), (W * p2 + X * f2).sum()
+    assert np.abs(p2 - psi).max() > 1e-3                      # the update is not small
+    assert abs(M1 - M0) < 1e-13 * M0
+
+
+def test_pure_exchange_closed_form():
+    """All weights zero and only the exchange bias b_S: every node moves
+    dpsi_s b_S W of conserved density from the bulk field to the interface field."""
+    psi, phi, rN, u, G, sc = _periodic_case(13)
+    ps = S.init_params(14)
+    for w, b in ps:
+        w[...] = 0.0
+        b[...] = 0.0
+    ps[-1][1][6] = 0.25
+    W, X = G + sc["fd_eps"], 1.0 - rN + sc["fd_eps"]
+    p2, f2 = S.predict_fields(ps, psi, phi, rN, u, G, sc)
+    assert np.abs(W * (p2 - psi) - sc["dpsi_s"] * 0.25 * W).max() < 1e-15
+    assert np.abs(X * (f2 - phi) + sc["dpsi_s"] * 0.25 * W).max() < 1e-15
+
+
+def test_conserved_changes_adjoint_identity():
+    rng = np.random.default_rng(15)
+    o = rng.standard_normal((2, 5, 6, 7, 7))
+    W, X = rng.uniform(0.1, 1.0, (2, 5, 6, 7)), rng.uniform(0.1, 2.0, (2, 5, 6, 7))
+    gp, gf = rng.standard_normal((2, 3, 4, 5)), rng.standard_normal((2, 3, 4, 5))
+    Ap, Af = S.conserved_changes(o, W, X, 2.5)
+    lhs = float((gp * Ap).sum() + (gf * Af).sum())
+    do = S.conserved_changes_adjoint(gp, gf, W, X, 2.5, o.shape)
+    assert abs(lhs - float((do * o).sum())) < 1e-12 * abs(lhs)
+
+
+def test_uniform_flux_and_linear_flux_closed_forms():
+    """With unit weights a uniform flux has no divergence, a flux growing by c per
+    node along an axis removes c from every node; with a weight that is linear
+    along x and a uniform coefficient f, the face fluxes grow by f times the slope."""
+    o = np.zeros((1, 5, 6, 7, 7))
+    one = np.ones((1, 5, 6, 7))
+    o[..., 0] = 3.0
+    o[..., 4] = -2.0
+    Ap, Af = S.conserved_changes(o, one, one, 1.0)
+    assert np.abs(Ap).max() == 0.0 and np.abs(Af).max() == 0.0
+    o[..., 0] = 0.5 * np.arange(7)[None, None, None, :]
+    Ap, _ = S.conserved_changes(o, one, one, 1.0)
+    assert np.allclose(Ap, -0.5, rtol=0, atol=1e-15)
+    o[...] = 0.0
+    o[..., 1] = 2.0                       # uniform y coefficient
+    Wy = 1.0 + 0.25 * np.arange(6)[None, None, :, None] * one
+    Ap, _ = S.conserved_changes(o, Wy, one, 1.0)
+    assert np.allclose(Ap, -2.0 * 0.25, rtol=0, atol=1e-14)
