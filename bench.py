@@ -215,7 +215,7 @@ def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, seed=0):
     del X, Y
     # one whole-grid application (features + network) against the k FD substeps it replaces
     feat, _ = bufs
-    out = torch.empty((n, n, n, 2), dtype=torch.float32, device="cuda")
+    out = torch.empty((n, n, n, lbfd.SG_NOUT), dtype=torch.float32, device="cuda")
     x = feat.view(1, n + 8, n + 8, n + 8, 16)
     sg.features(s, feat)
     sg.forward(x, out)
@@ -1023,6 +1023,44 @@ def autotune(out_path, workload, precision, warmup):
                                                 default_ms_per_step=r["default_ms_per_step"]) for r in res])
 
 
+def shear_precision_report(steps=None):
+    """The sheared drop (D2Q9 512 x 256) at the parameter corners stored by
+    tests/golden/make_golden.py: deformation D(t) every 1000 steps in the FP64,
+    FP32 and FP16-deviation modes against the FP64 oracle's, to 20 000 steps."""
+    import workloads as W
+    from paper_2311_15242_amd import lbfd
+
+    path = os.path.join(ROOT, "tests", "golden", "shear_deformation_20k.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    out = {}
+    for name, case in gold.items():
+        recs = case["records"]
+        every = case["every"]
+        last = steps or case["steps"]
+        ref = {r["step"]: r for r in recs if r["step"] <= last}
+        out[name] = dict(params=case["params"], steps=last)
+        for prec in ("fp64", "fp32", "fp16dev"):
+            p, q = W.shear_droplet(precision=prec, **case["params"])
+            s = lbfd.Solver(p).init_fields(q)
+            worst = wv = 0.0
+            curve = []
+            for c in range(0, last + 1, every):
+                if c:
+                    s.step(every)
+                ob = s.observables()
+                d = ob["deformation"]
+                r = ref[c]
+                if r["deformation"] > 1e-3:
+                    worst = max(worst, abs(d - r["deformation"]) / r["deformation"])
+                curve.append(round(d, 6))
+            out[name][prec] = dict(max_rel_error_D=float(f"{worst:.3e}"), D_final=curve[-1],
+                                   D_final_oracle=round(ref[last]["deformation"], 6), status=ob["status"])
+            s.close()
+            print(f"[shear] {name} {prec}: max rel error of D {worst:.2e}", file=sys.stderr, flush=True)
+    return out
+
+
 def accuracy_report(workload, precision, steps):
     """The benchmarked mode and the other deviation mode against the plain FP32
     GPU solver and the FP64 GPU solver (which matches the FP64 oracle to 1e-10)
@@ -1244,6 +1282,9 @@ def main():
     ap.add_argument("--autotune", metavar="OUT_JSON",
                     help="tune the launch shapes of the headline workload and of the 64-instance batch, write "
                          "the table to OUT_JSON and exit")
+    ap.add_argument("--shear-report", action="store_true",
+                    help="deformation D(t) of the sheared drop in FP64 / FP32 / FP16-dev against the stored FP64 "
+                         "oracle curves (tests/golden/shear_deformation_20k.json), print JSON and exit")
     ap.add_argument("--cpu-windows", action="store_true",
                     help="time the oracle over the fixed windows (C1 2000, C2 1000, C3 10 + 50 steps) on all host "
                          "cores and a shortened window on one thread, print a table and exit")
@@ -1262,6 +1303,9 @@ def main():
         return
     if args.cpu_windows:
         print(cpu_windows(), flush=True)
+        return
+    if args.shear_report:
+        print(json.dumps(shear_precision_report()), flush=True)
         return
     if args.autotune:
         print(json.dumps(autotune(args.autotune, args.workload, args.precision, args.warmup)), flush=True)

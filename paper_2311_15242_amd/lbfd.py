@@ -539,11 +539,22 @@ class Surrogate:
 
     def forward(self, x, out):
         B, d, h, w, c = x.shape
-        assert c == 16 and x.is_contiguous() and out.is_contiguous()
+        if c != 16 or not x.is_contiguous() or not out.is_contiguous():
+            raise ValueError("forward: inputs [B][d][h][w][16] and outputs must be contiguous")
+        if out.numel() != B * (d - 8) * (h - 8) * (w - 8) * SG_NOUT or out.element_size() != 4:
+            raise ValueError(f"forward: the output must hold B (d-8)(h-8)(w-8) x {SG_NOUT} FP32 values")
         _check(load().lbfd_sg_forward(self.h, _dptr(x), B, d, h, w, _dptr(out)), "lbfd_sg_forward")
         return out
 
+    def _check_tiles(self, x, t):
+        T = self.cfg["tile"]
+        if tuple(x.shape[1:]) != (T + 8, T + 8, T + 8, 16) or tuple(t.shape) != (x.shape[0], T, T, T, 4):
+            raise ValueError(f"tiles: inputs [B][{T + 8}]^3[16], targets [B][{T}]^3[4]")
+        if not (x.is_contiguous() and t.is_contiguous()) or t.element_size() != 4:
+            raise ValueError("tiles must be contiguous, targets FP32")
+
     def gradient(self, x, t):
+        self._check_tiles(x, t)
         g = np.zeros(self.n, dtype=np.float32)
         loss = C.c_double()
         _check(load().lbfd_sg_gradient(self.h, _dptr(x), _dptr(t), x.shape[0], C.byref(loss),
@@ -551,6 +562,7 @@ class Surrogate:
         return loss.value, g
 
     def train_step(self, x, t, want_loss=True):
+        self._check_tiles(x, t)
         loss = C.c_double()
         _check(load().lbfd_sg_train_step(self.h, _dptr(x), _dptr(t), x.shape[0],
                                          C.byref(loss) if want_loss else None), "lbfd_sg_train_step")
@@ -567,6 +579,9 @@ class Surrogate:
     def tiles(self, solver, feat, snap, origins, x, t):
         org = np.ascontiguousarray(np.asarray(origins, dtype=np.int32).reshape(-1))
         B = org.size // 3
+        if x.shape[0] != B or t.shape[0] != B:
+            raise ValueError("tiles: one input and one target tile per origin")
+        self._check_tiles(x, t)
         _check(load().lbfd_sg_tiles(solver.h, self.h, _dptr(feat), _dptr(snap),
                                     org.ctypes.data_as(C.POINTER(C.c_int32)), B, _dptr(x), _dptr(t)), "lbfd_sg_tiles")
         return x, t
