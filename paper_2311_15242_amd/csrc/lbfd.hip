@@ -3162,7 +3162,8 @@ struct lbfd_sg {
     int *org;                // tile origins [3 max_batch]
     long long cap_act, cap_out, cap_feat;
     long long t;             // Adam steps taken
-    bool brick = true;       // brick kernels on wide grids
+    bool wide = true;        // z-marching kernel on wide grids
+    int cus = 256;           // compute units of the device (persistent grid of that kernel)
 };
 
 static long long cube(long long e) { return e * e * e; }
@@ -3269,6 +3270,12 @@ int lbfd_sg_create(const lbfd_sg_params *p, void *d_workspace, size_t bytes, voi
     s->cap_out = L.cap_out;
     s->cap_feat = L.cap_feat;
     s->t = 0;
+    {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            s->cus = n;
+    }
     // weights, moments and the padded layouts start at zero
     if (hipMemsetAsync(ws, 0, L.loss, s->stream) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) {
         delete s;
@@ -3321,6 +3328,9 @@ int lbfd_sg_get_params(lbfd_sg *s, float *host, int64_t n)
 
 static unsigned blocks_for(long long n, long long per) { return (unsigned)((n + per - 1) / per); }
 
+// Output planes per column of the z-marching forward kernel.
+constexpr int SG_ZC = 32;
+
 // Forward pass over B grids of d x h x w input nodes on stream st; the layer
 // outputs stay in s->act for a backward pass.
 static int sg_forward_on(lbfd_sg *s, hipStream_t st, const uint16_t *in, int B, int d, int h, int w, float *out)
@@ -3332,20 +3342,24 @@ static int sg_forward_on(lbfd_sg *s, hipStream_t st, const uint16_t *in, int B, 
     for (int l = 0; l < sg::NL; ++l) {
         const int Di = d - 2 * l, Hi = h - 2 * l, Wi = w - 2 * l;
         const long long M = layer_nodes(l + 1, B, d, h, w);
-        if (Wi - 2 >= 2 * sg::BRX && s->brick) {
-            // wide grids: output bricks with their input staged in LDS
-            const int nbx = (Wi - 2 + sg::BRX - 1) / sg::BRX, nby = (Hi - 2 + sg::BRY - 1) / sg::BRY,
-                      nbz = (Di - 2 + sg::BRZ - 1) / sg::BRZ;
-            const dim3 grid((unsigned)((long long)nbx * nby * nbz * B));
+        if (Wi - 2 >= 2 * sg::ZX && s->wide) {
+            // wide grids: columns of 30 x 4 output nodes over SG_ZC planes, one persistent
+            // workgroup per compute unit (the kernel's LDS and registers allow one)
+            const int nbx = (Wi - 2 + sg::ZX - 1) / sg::ZX, nby = (Hi - 2 + sg::ZY - 1) / sg::ZY,
+                      nbz = (Di - 2 + SG_ZC - 1) / SG_ZC;
+            const long long ncol = (long long)nbx * nby * nbz * B;
+            const dim3 grid((unsigned)std::min<long long>(ncol, s->cus));
             if (l == 0)
-                hipLaunchKernelGGL((sg::k_conv_fwd_brick<16, true, false>), grid, dim3(256), 0, st, (const uint16_t *)x,
-                                   s->net.wb[0], s->net.bias[0], (void *)s->act[0], Di, Hi, Wi, nbx, nby, nbz);
+                hipLaunchKernelGGL((sg::k_conv_fwd_zm<16, true, false>), grid, dim3(256), 0, st, (const uint16_t *)x,
+                                   s->net.wb[0], s->net.bias[0], (void *)s->act[0], Di, Hi, Wi, nbx, nby, nbz, SG_ZC,
+                                   ncol);
             else if (l < 3)
-                hipLaunchKernelGGL((sg::k_conv_fwd_brick<32, true, false>), grid, dim3(256), 0, st, (const uint16_t *)x,
-                                   s->net.wb[l], s->net.bias[l], (void *)s->act[l], Di, Hi, Wi, nbx, nby, nbz);
+                hipLaunchKernelGGL((sg::k_conv_fwd_zm<32, true, false>), grid, dim3(256), 0, st, (const uint16_t *)x,
+                                   s->net.wb[l], s->net.bias[l], (void *)s->act[l], Di, Hi, Wi, nbx, nby, nbz, SG_ZC,
+                                   ncol);
             else
-                hipLaunchKernelGGL((sg::k_conv_fwd_brick<32, false, true>), grid, dim3(256), 0, st, (const uint16_t *)x,
-                                   s->net.wb[3], s->net.bias[3], (void *)out, Di, Hi, Wi, nbx, nby, nbz);
+                hipLaunchKernelGGL((sg::k_conv_fwd_zm<32, false, true>), grid, dim3(256), 0, st, (const uint16_t *)x,
+                                   s->net.wb[3], s->net.bias[3], (void *)out, Di, Hi, Wi, nbx, nby, nbz, SG_ZC, ncol);
             if (l < 3) x = s->act[l];
             continue;
         }

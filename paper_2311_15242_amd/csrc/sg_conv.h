@@ -4,8 +4,9 @@
 // surrogate; the network and its training are defined in the public header.
 //
 // Every layer is an implicit GEMM. Forward: rows = output nodes, columns = the 32
-// (padded) output channels, reduction over 27 taps x input channels; one wavefront
-// computes two 32 x 32 tiles, the layer's weights sit in LDS. Input gradient: rows =
+// (padded) output channels, reduction over 27 taps x input channels; on tiles one
+// wavefront computes several 32 x 32 tiles with the layer's weights in LDS, on wide
+// grids the weights stay in registers and the input marches through LDS by planes. Input gradient: rows =
 // input nodes, columns = input channels, reduction over taps x output channels
 // (the transposed weights). Weight gradient: one 32 x 32 tile (input x output
 // channels) per tap, reduction over nodes in 64-node chunks staged in LDS
@@ -20,6 +21,7 @@ namespace lbfd {
 namespace sg {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16;
@@ -137,99 +139,189 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const u16 *__restrict__ in, co
         }
 }
 
-// The same layer on grids wide enough for bricks: a workgroup stages the input
-// nodes of a 32 x 4 x BRZ output brick (34 x 6 x (BRZ + 2) nodes, zeros outside
-// the grid) in LDS once, and its wavefronts read every input fragment of the 27
-// taps from there; each wavefront owns BRZ rows of 32 nodes, so each weight
-// fragment feeds BRZ matrix instructions. Weight fragments come from LDS
-// (BR_WLDS) or from global memory (L2 resident). Same summation order as
-// k_conv_fwd.
-#ifndef LBFD_SG_BRZ
-#define LBFD_SG_BRZ 2
-#endif
-#ifndef LBFD_SG_BR_WLDS
-#define LBFD_SG_BR_WLDS 0
-#endif
-constexpr int BRX = 32, BRY = 4, BRZ = LBFD_SG_BRZ;
+// The same layer on wide grids, marching along z. A workgroup owns columns of
+// ZX x ZY output nodes (x, y) over zc consecutive output planes; wavefront w computes
+// output row y0 + w. The layer's weight fragments stay in registers for the whole
+// kernel (27 taps x CIN/16 fragments), so the only operand read per matrix
+// instruction is the input fragment, from LDS. Input planes (ZY + 2 rows of 32 nodes)
+// rotate through four LDS slots; each plane is fetched into registers two planes
+// ahead of the one being computed. The three x-taps share one input fragment: for tap
+// q the partial sums P_q[j] = sum in[x0 + j] w_q are kept per input node j of the
+// row, and out[x0 + i] = P_0[i] + P_1[i + 1] + P_2[i + 2] (i < ZX = 30): the three
+// partial tiles go to a per-wavefront LDS scratch, from which each lane reads 8
+// consecutive channels of a node (16-byte stores, hardware BF16 conversion, round to
+// nearest even). A persistent grid walks the columns.
+constexpr int ZX = 30, ZY = 4;
 template <int CIN, bool RELU, bool OUTF32>
-__global__ __launch_bounds__(256) void k_conv_fwd_brick(const u16 *__restrict__ in, const u16 *__restrict__ wb,
-                                                       const float *__restrict__ bias, void *__restrict__ out,
-                                                       int Di, int Hi, int Wi, int nbx, int nby, int nbz)
+__global__ __launch_bounds__(256) void k_conv_fwd_zm(const u16 *__restrict__ in, const u16 *__restrict__ wb,
+                                                    const float *__restrict__ bias, void *__restrict__ out, int Di,
+                                                    int Hi, int Wi, int nbx, int nby, int nbz, int zc, long long ncol)
 {
-    constexpr int NT = BRZ;       // rows per wavefront (4 wavefronts x BRZ rows = BRY x BRZ)
-    constexpr int CP = CIN + 8;   // padded node stride in LDS
-    constexpr int EX = BRX + 2, EY = BRY + 2, EZ = BRZ + 2;
-    constexpr bool WLDS = LBFD_SG_BR_WLDS != 0;
-    constexpr int LDW = CIN + 8;
-    __shared__ __attribute__((aligned(16))) u16 sx[EZ * EY * EX * CP];
-    __shared__ __attribute__((aligned(16))) u16 sw[WLDS ? 27 * CO * LDW : 8];
-    const int Do = Di - 2, Ho = Hi - 2, Wo = Wi - 2;
-    int bid = blockIdx.x;
-    const int bxi = bid % nbx;
-    bid /= nbx;
-    const int byi = bid % nby;
-    bid /= nby;
-    const int bzi = bid % nbz;
-    const long long b = bid / nbz;
-    const int x0 = bxi * BRX, y0 = byi * BRY, z0 = bzi * BRZ;
-    for (int i = threadIdx.x; i < EZ * EY * EX * (CIN / 8); i += 256) {
-        const int piece = i % (CIN / 8), node = i / (CIN / 8);
-        const int ex = node % EX, ey = (node / EX) % EY, ez = node / (EX * EY);
-        const int gx = x0 + ex, gy = y0 + ey, gz = z0 + ez;
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (gx < Wi && gy < Hi && gz < Di)
-            v = *(const u32x4 *)&in[(((b * Di + gz) * Hi + gy) * (long long)Wi + gx) * CIN + piece * 8];
-        *(u32x4 *)&sx[node * CP + piece * 8] = v;
-    }
-    if constexpr (WLDS)
-        for (int i = threadIdx.x; i < 27 * CO * (CIN / 8); i += 256) {
-            const int row = i / (CIN / 8), piece = i % (CIN / 8);
-            *(u32x4 *)&sw[row * LDW + piece * 8] = *(const u32x4 *)&wb[row * CIN + piece * 8];
-        }
-    __syncthreads();
+    constexpr int CP = CIN + 8;                   // node stride in LDS (elements)
+    constexpr int PR = ZY + 2;                    // input rows of a plane
+    constexpr int PLANE = PR * 32 * CP;           // elements of a plane slot
+    constexpr int NC = CIN / 16;                  // reduction fragments per tap
+    constexpr int PCS = CIN / 8;                  // 16-byte pieces per node
+    constexpr int PIECES = PR * 32 * PCS;         // 16-byte pieces per plane
+    constexpr int PPT = (PIECES + 255) / 256;     // pieces per thread
+    constexpr int SS = 36;                        // scratch row stride (floats; rows 16-byte aligned)
+    __shared__ __attribute__((aligned(16))) u16 ring[4 * PLANE];
+    __shared__ __attribute__((aligned(16))) float scr[4][3 * 32 * SS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int mr = lane & 31, kg = lane >> 5;
-    f32x16 acc[NT];
+    const int Do = Di - 2, Ho = Hi - 2, Wo = Wi - 2;
+    bf16x8 Bw[27][NC];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < 27; ++t)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
-    for (int a = 0; a < 3; ++a)
-        for (int p = 0; p < 3; ++p)
+        for (int c = 0; c < NC; ++c) Bw[t][c] = frag(wb + (t * CO + mr) * CIN + c * 16 + kg * 8);
+    // the epilogue: lane l stores 8 channels (c8 = 8 (l mod 4)) of rows l / 4 and
+    // l / 4 + 16, or (last layer) channels 4 (l mod 2) .. of row l / 2
+    const int c8 = OUTF32 ? 4 * (lane & 1) : 8 * (lane & 3);
+    float bb[8];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const int tap = (a * 3 + p) * 3 + q;
+    for (int k = 0; k < 8; ++k) bb[k] = (OUTF32 && k >= 4) ? 0.0f : bias[c8 + k];
+    float *const sw = scr[wave];
+    const long long pstride = (long long)Hi * Wi * CIN;   // elements between input planes
+    for (long long col = blockIdx.x; col < ncol; col += gridDim.x) {
+        long long r = col;
+        const int bxi = (int)(r % nbx);
+        r /= nbx;
+        const int byi = (int)(r % nby);
+        r /= nby;
+        const int bzi = (int)(r % nbz);
+        const long long b = r / nbz;
+        const int x0 = bxi * ZX, y0 = byi * ZY, z0 = bzi * zc;
+        const int nzo = min(zc, Do - z0);
+        // this thread's pieces of a plane: source in plane z0 (zeros outside the grid;
+        // they only reach outputs that are not stored) and place in a slot
+        const u16 *srcp[PPT];
+        bool okp[PPT];
+        int dst[PPT];
 #pragma unroll
-                for (int c = 0; c < CIN / 16; ++c) {
-                    const bf16x8 B = WLDS ? frag(&sw[(tap * CO + mr) * LDW + c * 16 + kg * 8])
-                                          : frag(wb + (tap * CO + mr) * CIN + c * 16 + kg * 8);
+        for (int k = 0; k < PPT; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
+            const int piece = i % PCS, node = i / PCS;
+            const int gx = x0 + (node & 31), gy = y0 + (node >> 5);
+            okp[k] = i < PIECES && gx < Wi && gy < Hi;
+            srcp[k] = okp[k] ? in + (((b * Di + z0) * Hi + gy) * (long long)Wi + gx) * CIN + piece * 8 : in;
+            dst[k] = i < PIECES ? node * CP + piece * 8 : -1;
+        }
+        const auto fetch = [&](int pz, u32x4 *v) {
+            const bool inz = z0 + pz < Di;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        // wavefront w owns y row w of the brick, at every z of the brick
-                        const int yr = wave, zr = t;
-                        const bf16x8 A = frag(&sx[(((zr + a) * EY + (yr + p)) * EX + (mr + q)) * CP + c * 16 + kg * 8]);
-                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[t], 0, 0, 0);
+            for (int k = 0; k < PPT; ++k)
+                v[k] = okp[k] && inz ? *(const u32x4 *)(srcp[k] + pz * pstride) : u32x4{0u, 0u, 0u, 0u};
+        };
+        const auto put = [&](int slot, const u32x4 *v) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                if (dst[k] >= 0) *(u32x4 *)&ring[slot * PLANE + dst[k]] = v[k];
+        };
+        // planes 0-2 in slots 0-2; plane 3 in flight in registers (it is stored at the
+        // end of plane 0, plane 4 fetched meanwhile)
+        u32x4 nx0[PPT], nx1[PPT];
+        {
+            u32x4 v0[PPT], v1[PPT], v2[PPT];
+            fetch(0, v0);
+            fetch(1, v1);
+            fetch(2, v2);
+            if (nzo > 1) fetch(3, nx0);
+            put(0, v0);
+            put(1, v1);
+            put(2, v2);
+        }
+        __syncthreads();
+        const int y = y0 + wave;
+        const int lim = min(ZX, Wo - x0);   // output nodes of this row tile
+        // output node x0 + i of this wavefront's row at plane z0 + iz is node
+        // orow + iz oplane + i; a lane stores rows acc_row(e, kg) of channel mr
+        const long long orow = ((b * Do + z0) * Ho + y) * (long long)Wo + x0;
+        const long long oplane = (long long)Ho * Wo;
+        // one output plane; cur holds plane iz + 3, nxt receives plane iz + 4 (the two
+        // register sets swap roles every plane, so the loop below takes planes in pairs)
+        const auto plane = [&](int iz, u32x4 *cur, u32x4 *nxt) __attribute__((always_inline)) {
+            if (iz + 2 < nzo) fetch(iz + 4, nxt);
+            f32x16 acc[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[q][e] = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const u16 *pl = ring + ((iz + a) & 3) * PLANE;
+#pragma unroll
+                for (int p = 0; p < 3; ++p)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const bf16x8 A = frag(pl + ((wave + p) * 32 + mr) * CP + c * 16 + kg * 8);
+#pragma unroll
+                        for (int q = 0; q < 3; ++q)
+                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bw[(a * 3 + p) * 3 + q][c], acc[q], 0,
+                                                                             0, 0);
                     }
+            }
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int j = acc_row(e, kg);
+                sw[j * SS + mr] = acc[0][e];
+                sw[(32 + j) * SS + mr] = acc[1][e];
+                sw[(64 + j) * SS + mr] = acc[2][e];
+            }
+            if (iz + 1 < nzo) put((iz + 3) & 3, cur);
+            __syncthreads();
+            if (y >= Ho) return;
+            const long long mrow = orow + iz * oplane;
+            // P_0[i] + P_1[i + 1] + P_2[i + 2] + bias of 4 channels at c of row i
+            const auto sum4 = [&](int i, int c, int k0, float *v) {
+                const float4 a = *(const float4 *)&sw[i * SS + c];
+                const float4 p = *(const float4 *)&sw[(33 + i) * SS + c];
+                const float4 q = *(const float4 *)&sw[(66 + i) * SS + c];
+                v[0] = a.x + p.x + q.x + bb[k0];
+                v[1] = a.y + p.y + q.y + bb[k0 + 1];
+                v[2] = a.z + p.z + q.z + bb[k0 + 2];
+                v[3] = a.w + p.w + q.w + bb[k0 + 3];
+            };
+            if constexpr (OUTF32) {
+                const int i = lane >> 1;
+                if (i < lim) {
+                    float v[4];
+                    sum4(i, c8, 0, v);
+                    float *o = (float *)out + (mrow + i) * NOUT + c8;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (c8 + k < NOUT) o[k] = v[k];
+                }
+            } else {
+#pragma unroll
+                for (int pass = 0; pass < 2; ++pass) {
+                    const int i = (lane >> 2) + 16 * pass;
+                    if (i >= lim) continue;
+                    float v[8];
+                    sum4(i, c8, 0, v);
+                    sum4(i, c8 + 4, 4, v + 4);
+                    bf16x2 h[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        float lo = v[2 * k], hi = v[2 * k + 1];
+                        if (RELU) {
+                            lo = fmaxf(lo, 0.0f);
+                            hi = fmaxf(hi, 0.0f);
+                        }
+                        h[k] = bf16x2{(__bf16)lo, (__bf16)hi};
+                    }
+                    *(u32x4 *)&((u16 *)out)[(mrow + i) * CO + c8] =
+                        u32x4{__builtin_bit_cast(uint32_t, h[0]), __builtin_bit_cast(uint32_t, h[1]),
+                              __builtin_bit_cast(uint32_t, h[2]), __builtin_bit_cast(uint32_t, h[3])};
                 }
             }
-    const float bv = bias[mr];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int y = y0 + wave, z = z0 + t;
-        if (y >= Ho || z >= Do) continue;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int x = x0 + acc_row(r, kg);
-            if (x >= Wo) continue;
-            const long long m = ((b * Do + z) * Ho + y) * (long long)Wo + x;
-            float v = acc[t][r] + bv;
-            if constexpr (OUTF32) {
-                if (mr < NOUT) ((float *)out)[m * NOUT + mr] = v;
-            } else {
-                if (RELU) v = fmaxf(v, 0.0f);
-                ((u16 *)out)[m * CO + mr] = f2bf(v);
-            }
+        };
+        for (int iz = 0; iz < nzo; iz += 2) {
+            plane(iz, nx0, nx1);
+            if (iz + 1 < nzo) plane(iz + 1, nx1, nx0);
         }
+        // every wavefront is past its last read of the slots before the next column fills them
+        __syncthreads();
     }
 }
 
