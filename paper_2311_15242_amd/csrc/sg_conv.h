@@ -23,6 +23,7 @@ namespace sg {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16;
 
@@ -170,17 +171,21 @@ __global__ __launch_bounds__(256) void k_conv_fwd_zm(const u16 *__restrict__ in,
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int mr = lane & 31, kg = lane >> 5;
     const int Do = Di - 2, Ho = Hi - 2, Wo = Wi - 2;
-    bf16x8 Bw[27][NC];
+    // The last layer (NOUT = 7 outputs) takes 16 x 16 x 32 matrix instructions: 16
+    // output columns instead of 32, half the matrix work; every other layer 32 x 32 x 16.
+    constexpr bool N16 = OUTF32;
+    constexpr int NCB = N16 ? CIN / 32 : NC;      // weight fragments per tap
+    const int l16 = lane & 15, k16 = lane >> 4;
+    bf16x8 Bw[27][NCB];
 #pragma unroll
     for (int t = 0; t < 27; ++t)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) Bw[t][c] = frag(wb + (t * CO + mr) * CIN + c * 16 + kg * 8);
+        for (int c = 0; c < NCB; ++c)
+            Bw[t][c] = N16 ? frag(wb + (t * CO + l16) * CIN + c * 32 + k16 * 8)
+                           : frag(wb + (t * CO + mr) * CIN + c * 16 + kg * 8);
     // the epilogue: lane l stores 8 channels (c8 = 8 (l mod 4)) of rows l / 4 and
     // l / 4 + 16, or (last layer) channels 4 (l mod 2) .. of row l / 2
     const int c8 = OUTF32 ? 4 * (lane & 1) : 8 * (lane & 3);
-    float bb[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) bb[k] = (OUTF32 && k >= 4) ? 0.0f : bias[c8 + k];
     float *const sw = scr[wave];
     const long long pstride = (long long)Hi * Wi * CIN;   // elements between input planes
     for (long long col = blockIdx.x; col < ncol; col += gridDim.x) {
@@ -193,30 +198,31 @@ __global__ __launch_bounds__(256) void k_conv_fwd_zm(const u16 *__restrict__ in,
         const long long b = r / nbz;
         const int x0 = bxi * ZX, y0 = byi * ZY, z0 = bzi * zc;
         const int nzo = min(zc, Do - z0);
-        // this thread's pieces of a plane: source in plane z0 (zeros outside the grid;
-        // they only reach outputs that are not stored) and place in a slot
-        const u16 *srcp[PPT];
-        bool okp[PPT];
-        int dst[PPT];
+        // this thread's pieces of a plane: offset from the column's first input node in
+        // plane z0 (-1 outside the grid: zeros, which only reach outputs that are not
+        // stored) and place in a slot
+        const u16 *cbase = in + (((b * Di + z0) * Hi + y0) * (long long)Wi + x0) * CIN;
+        int off[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int i = (int)threadIdx.x + 256 * k;
             const int piece = i % PCS, node = i / PCS;
-            const int gx = x0 + (node & 31), gy = y0 + (node >> 5);
-            okp[k] = i < PIECES && gx < Wi && gy < Hi;
-            srcp[k] = okp[k] ? in + (((b * Di + z0) * Hi + gy) * (long long)Wi + gx) * CIN + piece * 8 : in;
-            dst[k] = i < PIECES ? node * CP + piece * 8 : -1;
+            const bool ok = i < PIECES && x0 + (node & 31) < Wi && y0 + (node >> 5) < Hi;
+            off[k] = ok ? ((node >> 5) * Wi + (node & 31)) * CIN + piece * 8 : -1;
         }
         const auto fetch = [&](int pz, u32x4 *v) {
             const bool inz = z0 + pz < Di;
+            const u16 *pb = cbase + pz * pstride;
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
-                v[k] = okp[k] && inz ? *(const u32x4 *)(srcp[k] + pz * pstride) : u32x4{0u, 0u, 0u, 0u};
+                v[k] = off[k] >= 0 && inz ? *(const u32x4 *)(pb + off[k]) : u32x4{0u, 0u, 0u, 0u};
         };
         const auto put = [&](int slot, const u32x4 *v) {
 #pragma unroll
-            for (int k = 0; k < PPT; ++k)
-                if (dst[k] >= 0) *(u32x4 *)&ring[slot * PLANE + dst[k]] = v[k];
+            for (int k = 0; k < PPT; ++k) {
+                const int i = (int)threadIdx.x + 256 * k;
+                if (i < PIECES) *(u32x4 *)&ring[slot * PLANE + (i / PCS) * CP + (i % PCS) * 8] = v[k];
+            }
         };
         // planes 0-2 in slots 0-2; plane 3 in flight in registers (it is stored at the
         // end of plane 0, plane 4 fetched meanwhile)
@@ -242,51 +248,83 @@ __global__ __launch_bounds__(256) void k_conv_fwd_zm(const u16 *__restrict__ in,
         // register sets swap roles every plane, so the loop below takes planes in pairs)
         const auto plane = [&](int iz, u32x4 *cur, u32x4 *nxt) __attribute__((always_inline)) {
             if (iz + 2 < nzo) fetch(iz + 4, nxt);
-            f32x16 acc[3];
+            if constexpr (N16) {
+                // rows = 16 nodes (two halves of the row tile), k = 32 channels of one tap
+                f32x4 acc[3][2];
 #pragma unroll
-            for (int q = 0; q < 3; ++q)
+                for (int q = 0; q < 3; ++q)
 #pragma unroll
-                for (int e = 0; e < 16; ++e) acc[q][e] = 0.0f;
+                    for (int h = 0; h < 2; ++h) acc[q][h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const u16 *pl = ring + ((iz + a) & 3) * PLANE;
+                for (int g = 0; g < 9 * NCB; ++g) {
+                    const int a = g / (3 * NCB), p = (g / NCB) % 3, c = g % NCB;
+                    const u16 *base = ring + ((iz + a) & 3) * PLANE + ((wave + p) * 32 + l16) * CP + c * 32 + k16 * 8;
+                    const bf16x8 A0 = frag(base), A1 = frag(base + 16 * CP);
 #pragma unroll
-                for (int p = 0; p < 3; ++p)
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        const bf16x8 A = frag(pl + ((wave + p) * 32 + mr) * CP + c * 16 + kg * 8);
-#pragma unroll
-                        for (int q = 0; q < 3; ++q)
-                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bw[(a * 3 + p) * 3 + q][c], acc[q], 0,
-                                                                             0, 0);
+                    for (int q = 0; q < 3; ++q) {
+                        acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, Bw[(a * 3 + p) * 3 + q][c], acc[q][0],
+                                                                            0, 0, 0);
+                        acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, Bw[(a * 3 + p) * 3 + q][c], acc[q][1],
+                                                                            0, 0, 0);
                     }
-            }
+                }
+                // lane l holds column l mod 16, rows 16 h + 4 (l / 16) + r
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int j = acc_row(e, kg);
-                sw[j * SS + mr] = acc[0][e];
-                sw[(32 + j) * SS + mr] = acc[1][e];
-                sw[(64 + j) * SS + mr] = acc[2][e];
+                for (int q = 0; q < 3; ++q)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) sw[(32 * q + 16 * h + 4 * k16 + r) * SS + l16] = acc[q][h][r];
+            } else {
+                f32x16 acc[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) acc[q][e] = 0.0f;
+                // input fragment g = ((a 3 + p) NC + c); the next one is read while the
+                // three matrix instructions of the current one run
+                const auto afrag = [&](int g) __attribute__((always_inline)) {
+                    const int a = g / (3 * NC), p = (g / NC) % 3, c = g % NC;
+                    return frag(ring + ((iz + a) & 3) * PLANE + ((wave + p) * 32 + mr) * CP + c * 16 + kg * 8);
+                };
+                bf16x8 A = afrag(0);
+#pragma unroll
+                for (int g = 0; g < 9 * NC; ++g) {
+                    const bf16x8 An = g + 1 < 9 * NC ? afrag(g + 1) : A;
+                    const int ap = g / NC, c = g % NC;
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bw[ap * 3 + q][c], acc[q], 0, 0, 0);
+                    A = An;
+                }
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int j = acc_row(e, kg);
+                    sw[j * SS + mr] = acc[0][e];
+                    sw[(32 + j) * SS + mr] = acc[1][e];
+                    sw[(64 + j) * SS + mr] = acc[2][e];
+                }
             }
             if (iz + 1 < nzo) put((iz + 3) & 3, cur);
             __syncthreads();
             if (y >= Ho) return;
             const long long mrow = orow + iz * oplane;
             // P_0[i] + P_1[i + 1] + P_2[i + 2] + bias of 4 channels at c of row i
-            const auto sum4 = [&](int i, int c, int k0, float *v) {
+            const auto sum4 = [&](int i, int c, float *v) {
                 const float4 a = *(const float4 *)&sw[i * SS + c];
                 const float4 p = *(const float4 *)&sw[(33 + i) * SS + c];
                 const float4 q = *(const float4 *)&sw[(66 + i) * SS + c];
-                v[0] = a.x + p.x + q.x + bb[k0];
-                v[1] = a.y + p.y + q.y + bb[k0 + 1];
-                v[2] = a.z + p.z + q.z + bb[k0 + 2];
-                v[3] = a.w + p.w + q.w + bb[k0 + 3];
+                const float4 bz = *(const float4 *)&bias[c];
+                v[0] = a.x + p.x + q.x + bz.x;
+                v[1] = a.y + p.y + q.y + bz.y;
+                v[2] = a.z + p.z + q.z + bz.z;
+                v[3] = a.w + p.w + q.w + bz.w;
             };
             if constexpr (OUTF32) {
                 const int i = lane >> 1;
                 if (i < lim) {
                     float v[4];
-                    sum4(i, c8, 0, v);
+                    sum4(i, c8, v);
                     float *o = (float *)out + (mrow + i) * NOUT + c8;
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
@@ -298,8 +336,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd_zm(const u16 *__restrict__ in,
                     const int i = (lane >> 2) + 16 * pass;
                     if (i >= lim) continue;
                     float v[8];
-                    sum4(i, c8, 0, v);
-                    sum4(i, c8 + 4, 4, v + 4);
+                    sum4(i, c8, v);
+                    sum4(i, c8 + 4, v + 4);
                     bf16x2 h[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
