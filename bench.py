@@ -1265,7 +1265,7 @@ def main():
                     help="orderings of the surfactant-covered drop in simple shear (Sec 3.3)")
     ap.add_argument("--sg-size", type=int, default=256)
     ap.add_argument("--sg-snapshots", type=int, default=16)
-    ap.add_argument("--sg-tiles", type=int, default=64)
+    ap.add_argument("--sg-tiles", type=int, default=512, help="training tiles per snapshot")
     ap.add_argument("--sg-train-steps", type=int, default=3000)
     ap.add_argument("--sg-blocks", type=int, default=4)
     ap.add_argument("--omega", type=float, default=None, help="SOR relaxation factor (default: the workload's)")

@@ -391,8 +391,7 @@ template <int LAT, class P> __device__ __forceinline__ void geom_body(const KP<t
     // X + eps = 1 - rhoN + eps (phi), in the solve's colour-split arrays: the level
     // a geometry launch computes is always the one the next solve needs
     const uint32_t j = split_idx(k, nd.x, nd.y, nd.z);
-    st(k.fld.cwP, j, G + k.fd_eps);
-    st(k.fld.cwF, j, (R(1) - ld(rN, n)) + k.fd_eps);
+    st(k.fld.cw2, j, V2<R>{G + k.fd_eps, (R(1) - ld(rN, n)) + k.fd_eps});
 }
 template <int LAT, class P> __global__ __launch_bounds__(256) void k_geom(KP<typename P::R> k, int level)
 {
@@ -999,10 +998,8 @@ template <int LAT, class P> __device__ __forceinline__ void fd_body(const KP<typ
     // the solve's right-hand sides and initial guesses in its colour-split arrays
     // (the geometry kernel of the new level wrote the node weights there)
     const uint32_t j = split_idx(k, x, y, z);
-    st(k.fld.rhsP, j, rhP);
-    st(k.fld.rhsF, j, rhF);
-    st(k.fld.csP, j, psig);
-    st(k.fld.csF, j, phig);
+    st(k.fld.rhs2, j, V2<R>{rhP, rhF});
+    st(k.fld.cs2, j, V2<R>{psig, phig});
 }
 template <int LAT, class P> __global__ __launch_bounds__(256) void k_fd(KP<typename P::R> k)
 {
@@ -1061,66 +1058,64 @@ template <int D, class R> __device__ __forceinline__ bool on_seam(const KP<R> &k
            (D == 3 && (k.seam & 4) && z == k.nz - 1);
 }
 
-// Operands of the implicit systems at this step (colour-split arrays).
+// Operands of the implicit systems at this step (colour-split arrays of (psi, phi) pairs).
 template <class R> struct SorOps {
-    const R *wP, *wF;    // node weights W = G^{n+1} + eps (psi) and X^{n+1} + eps (phi)
-    R *psi, *phi;        // iterates (initial guess on entry)
-    const R *rhsP, *rhsF;
+    const V2<R> *w;      // node weights W = G^{n+1} + eps (psi) and X^{n+1} + eps (phi)
+    V2<R> *chi;          // iterates (initial guess on entry)
+    const V2<R> *rhs;
     R hdP, hdF, om;
 };
 template <class R> __device__ __forceinline__ SorOps<R> sor_ops(const KP<R> &k, const StepArgs &)
 {
     SorOps<R> a;
-    a.wP = k.fld.cwP;
-    a.wF = k.fld.cwF;
-    a.psi = k.fld.csP;
-    a.phi = k.fld.csF;
-    a.rhsP = k.fld.rhsP;
-    a.rhsF = k.fld.rhsF;
+    a.w = k.fld.cw2;
+    a.chi = k.fld.cs2;
+    a.rhs = k.fld.rhs2;
     a.hdP = R(0.5) * k.Ds;
     a.hdF = R(0.5) * k.Db;
     a.om = k.omega;
     return a;
 }
 
-// Operands of one SOR row, loaded before any update is stored: the two systems'
-// loads are then in flight together instead of the second system's waiting
-// behind the first one's store (the arrays could alias as far as the compiler
-// knows).
+// Operands of one SOR row of both systems, all loaded before the update is stored
+// (the loads of the row are then in flight together).
 template <class R, int NF> struct SorRow {
-    R Wn, Wf[NF], cf[NF], rhs, c0;
+    V2<R> Wn, Wf[NF], cf[NF], rhs, c0;
 };
 template <class R, int NF>
-__device__ __forceinline__ void sor_load(SorRow<R, NF> &o, const R *W, const R *chi, const R *rhsA, uint32_t n,
-                                         const uint32_t *q, const bool *on)
+__device__ __forceinline__ void sor_load(SorRow<R, NF> &o, const SorOps<R> &a, uint32_t n, const uint32_t *q,
+                                         const bool *on)
 {
-    o.Wn = ld(W, n);
+    o.Wn = ld(a.w, n);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        o.Wf[f] = on[f] ? ld(W, q[f]) : R(0);
-        o.cf[f] = on[f] ? ld(chi, q[f]) : R(0);
+        o.Wf[f] = on[f] ? ld(a.w, q[f]) : V2<R>{R(0), R(0)};
+        o.cf[f] = on[f] ? ld((const V2<R> *)a.chi, q[f]) : V2<R>{R(0), R(0)};
     }
-    o.rhs = ld(rhsA, n);
-    o.c0 = ld(chi, n);
+    o.rhs = ld(a.rhs, n);
+    o.c0 = ld((const V2<R> *)a.chi, n);
 }
 
-// The update: diag = W_n + sum_f w_f, off = sum_f w_f chi_f over the faces present
-// (a wall face carries no flux), w_f = (Dc/2) (W_n + W_f)/2; the pre-update
-// residual |rhs - (diag chi - off)| and |rhs| feed the maxima.
-template <class R, int NF>
+// The update of system S (0: psi, 1: phi): diag = W_n + sum_f w_f, off = sum_f
+// w_f chi_f over the faces present (a wall face carries no flux), w_f = (Dc/2)
+// (W_n + W_f)/2; the pre-update residual |rhs - (diag chi - off)| and |rhs| feed
+// the maxima.
+template <int S, class R> __device__ __forceinline__ R comp(const V2<R> &v) { return S == 0 ? v.x : v.y; }
+template <int S, class R, int NF>
 __device__ __forceinline__ R sor_update(const SorRow<R, NF> &o, const bool *on, R hd, R om, R &rmax, R &bmax)
 {
-    R diag = o.Wn, off = 0;
+    const R Wn = comp<S>(o.Wn), c0 = comp<S>(o.c0), rhs = comp<S>(o.rhs);
+    R diag = Wn, off = 0;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         if (!on[f]) continue;
-        const R wf = hd * (R(0.5) * (o.Wn + o.Wf[f]));
+        const R wf = hd * (R(0.5) * (Wn + comp<S>(o.Wf[f])));
         diag += wf;
-        off += wf * o.cf[f];
+        off += wf * comp<S>(o.cf[f]);
     }
-    rmax = fmax(rmax, fabs(o.rhs - (diag * o.c0 - off)));
-    bmax = fmax(bmax, fabs(o.rhs));
-    return (R(1) - om) * o.c0 + om * (o.rhs + off) / diag;
+    rmax = fmax(rmax, fabs(rhs - (diag * c0 - off)));
+    bmax = fmax(bmax, fabs(rhs));
+    return (R(1) - om) * c0 + om * (rhs + off) / diag;
 }
 
 // One SOR update of node (x, y, z) in both implicit systems (a converged system is
@@ -1154,11 +1149,12 @@ __device__ __forceinline__ void sor_node(const KP<typename P::R> &k, const SorOp
         on[5] = z < nz - 1 || !k.bc[2];
         q[5] = z < nz - 1 ? o + sz : split_idx(k, x, y, 0);
     }
-    SorRow<R, NF> rp, rf;
-    if (!conv[0]) sor_load(rp, a.wP, (const R *)a.psi, a.rhsP, n, q, on);
-    if (!conv[1]) sor_load(rf, a.wF, (const R *)a.phi, a.rhsF, n, q, on);
-    if (!conv[0]) st(a.psi, n, sor_update(rp, on, a.hdP, a.om, rloc[0], bloc[0]));
-    if (!conv[1]) st(a.phi, n, sor_update(rf, on, a.hdF, a.om, rloc[1], bloc[1]));
+    SorRow<R, NF> row;
+    sor_load(row, a, n, q, on);
+    V2<R> v = row.c0;   // a converged system keeps its value
+    if (!conv[0]) v.x = sor_update<0>(row, on, a.hdP, a.om, rloc[0], bloc[0]);
+    if (!conv[1]) v.y = sor_update<1>(row, on, a.hdF, a.om, rloc[1], bloc[1]);
+    st(a.chi, n, v);
 }
 
 // One tile of a colour half-sweep: 256 consecutive entries of the colour's index
@@ -1532,8 +1528,9 @@ __device__ __forceinline__ void total_part_body(const KP<typename P::R> &k, int 
             const uint32_t yz = udiv(i, (uint32_t)k.nx, k.inv_nx);
             const uint32_t z = udiv(yz, (uint32_t)k.ny, k.inv_ny);
             const uint32_t j = split_idx(k, (int)(i - yz * (uint32_t)k.nx), (int)(yz - z * (uint32_t)k.ny), (int)z);
-            vp = ld((const R *)k.fld.csP, j);
-            vf = ld((const R *)k.fld.csF, j);
+            const V2<R> c = ld((const V2<R> *)k.fld.cs2, j);
+            vp = c.x;
+            vf = c.y;
             st(k.fld.psi[buf], i, vp);
             st(k.fld.phi[buf], i, vf);
         } else {
@@ -1843,7 +1840,7 @@ size_t pop_bytes(int prec) { return prec == LBFD_FP64 ? 8 : prec == LBFD_FP32 ? 
 size_t real_bytes(int prec) { return prec == LBFD_FP64 ? 8 : 4; }
 
 struct Layout {
-    size_t f[2], mac[2], desc, G[2], nrm, u, F, qf, sorres, psi[2], phi[2], Sp, Bp, rhsP, rhsF, csP, csF, cwP, cwF,
+    size_t f[2], mac[2], desc, G[2], nrm, u, F, qf, sorres, psi[2], phi[2], Sp, Bp, rhs2, cs2, cw2,
         part, sc, obs, total;
 };
 
@@ -1872,12 +1869,9 @@ Layout layout(const lbfd_params *p)
     L.Bp = take(sr * N);
     // arrays of the implicit solve, two colour planes of ((nx + 1) / 2) ny nz entries each
     const long long NS = 2LL * ((p->nx + 1) / 2) * p->ny * p->nz;
-    L.rhsP = take(sr * NS);
-    L.rhsF = take(sr * NS);
-    L.csP = take(sr * NS);
-    L.csF = take(sr * NS);
-    L.cwP = take(sr * NS);
-    L.cwF = take(sr * NS);
+    L.rhs2 = take(2 * sr * NS);
+    L.cs2 = take(2 * sr * NS);
+    L.cw2 = take(2 * sr * NS);
     const size_t npart = (size_t)NRED * (size_t)nblocks;
     L.part = take(sizeof(double) * (npart > (size_t)TOTAL_BLOCKS ? npart : (size_t)TOTAL_BLOCKS));
     L.sc = take(sizeof(DevScalars));
@@ -2046,12 +2040,9 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
     F.sorres = (unsigned long long *)(ws + Lo.sorres);
     F.Sp = (R *)(ws + Lo.Sp);
     F.Bp = (R *)(ws + Lo.Bp);
-    F.rhsP = (R *)(ws + Lo.rhsP);
-    F.rhsF = (R *)(ws + Lo.rhsF);
-    F.csP = (R *)(ws + Lo.csP);
-    F.csF = (R *)(ws + Lo.csF);
-    F.cwP = (R *)(ws + Lo.cwP);
-    F.cwF = (R *)(ws + Lo.cwF);
+    F.rhs2 = (V2<R> *)(ws + Lo.rhs2);
+    F.cs2 = (V2<R> *)(ws + Lo.cs2);
+    F.cw2 = (V2<R> *)(ws + Lo.cw2);
     F.part = (double *)(ws + Lo.part);
     F.sc = (DevScalars *)(ws + Lo.sc);
 }

@@ -17,7 +17,9 @@
 //   u, F      fluid velocity (eq 10) and total force (D each)
 //   qf        sum_k qcoef_k rho^k u_a (D), the field whose derivative is the
 //             colour-summed correction Q_a
-//   psi[2], phi[2], Sprev, Bprev, rhsP, rhsF   finite-difference fields
+//   psi[2], phi[2], Sprev, Bprev   finite-difference fields (node order)
+//   rhs2, cs2, cw2   the implicit solve's right-hand sides, iterates and node
+//             weights as (psi, phi) pairs in colour-split order
 //
 // Only the total population is stored. Recolouring (eq 11) splits the
 // post-collision f_dag_i of a node into a red part a f_dag_i + r_i and a blue
@@ -185,6 +187,8 @@ __device__ __forceinline__ float h_hi(uint32_t v) { return (float)__builtin_bit_
 
 // Four reals read or written by one vector access (the packed descriptor).
 template <class R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
+// A (psi, phi) pair of the implicit solve: one load serves both systems.
+template <class R> struct alignas(2 * sizeof(R)) V2 { R x, y; };
 
 // Recolouring descriptor of a node in the 16-bit deviation modes (16 bytes): colour
 // share and density in FP32, the recolouring vector c and the reference velocity u*
@@ -209,7 +213,7 @@ template <class R> struct Fields {
     R *Sp, *Bp;
     // The implicit solve works on colour-split arrays (split_idx): right-hand
     // sides, iterates and node weights W = G + eps, X + eps of both systems
-    R *rhsP, *rhsF, *csP, *csF, *cwP, *cwF;
+    V2<R> *rhs2, *cs2, *cw2;   // implicit solve: (psi, phi) pairs of right-hand sides, iterates, node weights
     double *part;   // reduction partials
     unsigned long long *sorres;  // residual and |rhs| maxima per field, sweep and slot (bits of doubles)
     DevScalars *sc;
