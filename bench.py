@@ -1034,11 +1034,9 @@ def shear_precision_report(steps=20000, every=1000, field_every=5000):
     FP16-deviation modes for `steps` steps. Deformation D(t) every `every` steps
     against the FP64 oracle's curve where tests/golden/make_golden.py stored one,
     and against the FP64 GPU solver (which matches the oracle to 1e-10) at every
-    corner; velocity and psi at every `field_every` steps against the FP64 GPU
-    solver (max |a - b| / max |b| and RMS / max |b|); MLUPS of each mode."""
+    corner; velocity, G psi and psi on the interface band at every `field_every`
+    steps against the FP64 GPU solver (max |a - b| / max |b| and RMS / max |b|)."""
     import itertools
-
-    import torch
 
     import workloads as W
     from paper_2311_15242_amd import lbfd
@@ -1049,55 +1047,55 @@ def shear_precision_report(steps=20000, every=1000, field_every=5000):
         with open(path) as fh:
             for case in json.load(fh).values():
                 gold[tuple(case["params"][k] for k in ("Ca", "Bi", "E0"))] = {r["step"]: r for r in case["records"]}
-    N = 512 * 256
-
     def run(prec, cfg):
         p, q = W.shear_droplet(precision=prec, **cfg)
         s = lbfd.Solver(p).init_fields(q)
-        D, fields, ms = {}, {}, 0.0
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        D, fields = {}, {}
         for c in range(0, steps + 1, every):
             if c:
-                torch.cuda.synchronize()
-                ev0.record()
                 s.step(every)
-                ev1.record()
-                torch.cuda.synchronize()
-                ms += ev0.elapsed_time(ev1)
             ob = s.observables()
             if ob["status"] != 0:
                 raise RuntimeError(f"shear {cfg} {prec}: status {ob['status']} at step {c}")
             D[c] = ob["deformation"]
             if c % field_every == 0:
-                fields[c] = (s.field("u"), s.field("psi"))
+                G, rN, psi = s.field("G"), s.field("rhoN"), s.field("psi")
+                fields[c] = (s.field("u"), G * psi, np.where(np.abs(rN) <= 0.5, psi, np.nan))
         s.close()
-        return D, fields, N * steps / (ms / 1e3) / 1e6
+        return D, fields
 
     def rel_D(D, ref):
         return max((abs(D[c] - ref[c]) / ref[c] for c in D if c in ref and ref[c] > 1e-3), default=0.0)
 
     out = dict(steps=steps, grid=[512, 256], D_norm="max over t of |D - D_ref| / D_ref (D_ref > 1e-3)",
-               field_norm="max over checkpoints of max |a - b| / max |b| (RMS / max |b|)", corners={})
+               field_norm="max over checkpoints of max |a - b| / max |b| (RMS / max |b|); Gpsi: the "
+                          "conserved interface density G psi; psi_band: psi where |rhoN| <= 0.5 (the band of "
+                          "psi_av); MLUPS of the three modes on this grid are in the bench line's secondary block",
+               corners={})
     for Ca, Bi, E0 in itertools.product((0.1, 0.4), (0.1, 1.0), (0.1, 0.5)):
         cfg = dict(Ca=Ca, Bi=Bi, E0=E0)
         name = f"ca{Ca:g}_bi{Bi:g}_e{E0:g}"
-        D64, F64, mlups64 = run("fp64", cfg)
+        D64, F64 = run("fp64", cfg)
         orc = gold.get((Ca, Bi, E0))
-        rec = dict(D_final_fp64=round(D64[steps], 6), fp64=dict(mlups=round(mlups64, 1)))
+        rec = dict(D_final_fp64=round(D64[steps], 6), fp64={})
         if orc:
             rec["fp64"]["D_vs_oracle"] = float(f"{rel_D(D64, {c: r['deformation'] for c, r in orc.items()}):.3e}")
         for prec in ("fp32", "fp16dev"):
-            D, F, mlups = run(prec, cfg)
-            e = dict(mlups=round(mlups, 1), D_vs_fp64=float(f"{rel_D(D, D64):.3e}"))
+            D, F = run(prec, cfg)
+            e = dict(D_vs_fp64=float(f"{rel_D(D, D64):.3e}"))
             if orc:
                 e["D_vs_oracle"] = float(f"{rel_D(D, {c: r['deformation'] for c, r in orc.items()}):.3e}")
-            for k, i in (("u", 0), ("psi", 1)):
+            for k, i in (("u", 0), ("Gpsi", 1), ("psi_band", 2)):
                 mx = rms = 0.0
                 for c in F:
                     a, b = F[c][i], F64[c][i]
-                    sc = max(float(np.abs(b).max()), 1e-300)
-                    mx = max(mx, float(np.abs(a - b).max()) / sc)
-                    rms = max(rms, float(np.sqrt(np.mean((a - b) ** 2))) / sc)
+                    m = np.isfinite(a) & np.isfinite(b)     # the band of the two runs can differ by a node
+                    if not m.any():
+                        continue
+                    d = np.abs(a[m] - b[m])
+                    sc = max(float(np.abs(b[m]).max()), 1e-300)
+                    mx = max(mx, float(d.max()) / sc)
+                    rms = max(rms, float(np.sqrt(np.mean(d ** 2))) / sc)
                 e[k] = float(f"{mx:.3e}")
                 e[k + "_rms"] = float(f"{rms:.3e}")
             rec[prec] = e
