@@ -1304,7 +1304,7 @@ def main():
     ap.add_argument("--sg-size", type=int, default=256)
     ap.add_argument("--sg-snapshots", type=int, default=16)
     ap.add_argument("--sg-tiles", type=int, default=512, help="training tiles per snapshot")
-    ap.add_argument("--sg-train-steps", type=int, default=3000)
+    ap.add_argument("--sg-train-steps", type=int, default=12000)
     ap.add_argument("--sg-blocks", type=int, default=4)
     ap.add_argument("--omega", type=float, default=None, help="SOR relaxation factor (default: the workload's)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
