@@ -1077,47 +1077,6 @@ template <class R> __device__ __forceinline__ SorOps<R> sor_ops(const KP<R> &k, 
     return a;
 }
 
-// Operands of one SOR row of both systems, all loaded before the update is stored
-// (the loads of the row are then in flight together).
-template <class R, int NF> struct SorRow {
-    V2<R> Wn, Wf[NF], cf[NF], rhs, c0;
-};
-template <class R, int NF>
-__device__ __forceinline__ void sor_load(SorRow<R, NF> &o, const SorOps<R> &a, uint32_t n, const uint32_t *q,
-                                         const bool *on)
-{
-    o.Wn = ld(a.w, n);
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        o.Wf[f] = on[f] ? ld(a.w, q[f]) : V2<R>{R(0), R(0)};
-        o.cf[f] = on[f] ? ld((const V2<R> *)a.chi, q[f]) : V2<R>{R(0), R(0)};
-    }
-    o.rhs = ld(a.rhs, n);
-    o.c0 = ld((const V2<R> *)a.chi, n);
-}
-
-// The update of system S (0: psi, 1: phi): diag = W_n + sum_f w_f, off = sum_f
-// w_f chi_f over the faces present (a wall face carries no flux), w_f = (Dc/2)
-// (W_n + W_f)/2; the pre-update residual |rhs - (diag chi - off)| and |rhs| feed
-// the maxima.
-template <int S, class R> __device__ __forceinline__ R comp(const V2<R> &v) { return S == 0 ? v.x : v.y; }
-template <int S, class R, int NF>
-__device__ __forceinline__ R sor_update(const SorRow<R, NF> &o, const bool *on, R hd, R om, R &rmax, R &bmax)
-{
-    const R Wn = comp<S>(o.Wn), c0 = comp<S>(o.c0), rhs = comp<S>(o.rhs);
-    R diag = Wn, off = 0;
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        if (!on[f]) continue;
-        const R wf = hd * (R(0.5) * (Wn + comp<S>(o.Wf[f])));
-        diag += wf;
-        off += wf * comp<S>(o.cf[f]);
-    }
-    rmax = fmax(rmax, fabs(rhs - (diag * c0 - off)));
-    bmax = fmax(bmax, fabs(rhs));
-    return (R(1) - om) * c0 + om * (rhs + off) / diag;
-}
-
 // One SOR update of node (x, y, z) in both implicit systems (a converged system is
 // left alone), recording its pre-update residual and |rhs|. Face neighbours in the
 // interior lie in the other colour plane at the same row offset; across a periodic
@@ -1149,11 +1108,33 @@ __device__ __forceinline__ void sor_node(const KP<typename P::R> &k, const SorOp
         on[5] = z < nz - 1 || !k.bc[2];
         q[5] = z < nz - 1 ? o + sz : split_idx(k, x, y, 0);
     }
-    SorRow<R, NF> row;
-    sor_load(row, a, n, q, on);
-    V2<R> v = row.c0;   // a converged system keeps its value
-    if (!conv[0]) v.x = sor_update<0>(row, on, a.hdP, a.om, rloc[0], bloc[0]);
-    if (!conv[1]) v.y = sor_update<1>(row, on, a.hdF, a.om, rloc[1], bloc[1]);
+    // diag = W_n + sum_f w_f, off = sum_f w_f chi_f over the faces present (a wall
+    // face carries no flux), w_f = (Dc/2) (W_n + W_f)/2, for both systems at once
+    const V2<R> Wn = ld(a.w, n), c0 = ld((const V2<R> *)a.chi, n), rhs = ld(a.rhs, n);
+    R dP = Wn.x, oP = 0, dF = Wn.y, oF = 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        if (!on[f]) continue;
+        const V2<R> Wf = ld(a.w, q[f]), cf = ld((const V2<R> *)a.chi, q[f]);
+        const R wP = a.hdP * (R(0.5) * (Wn.x + Wf.x)), wF = a.hdF * (R(0.5) * (Wn.y + Wf.y));
+        dP += wP;
+        oP += wP * cf.x;
+        dF += wF;
+        oF += wF * cf.y;
+    }
+    // the pre-update residual |rhs - (diag chi - off)| and |rhs| feed the maxima; a
+    // converged system keeps its value
+    V2<R> v = c0;
+    if (!conv[0]) {
+        rloc[0] = fmax(rloc[0], fabs(rhs.x - (dP * c0.x - oP)));
+        bloc[0] = fmax(bloc[0], fabs(rhs.x));
+        v.x = (R(1) - a.om) * c0.x + a.om * (rhs.x + oP) / dP;
+    }
+    if (!conv[1]) {
+        rloc[1] = fmax(rloc[1], fabs(rhs.y - (dF * c0.y - oF)));
+        bloc[1] = fmax(bloc[1], fabs(rhs.y));
+        v.y = (R(1) - a.om) * c0.y + a.om * (rhs.y + oF) / dF;
+    }
     st(a.chi, n, v);
 }
 
