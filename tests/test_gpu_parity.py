@@ -128,10 +128,11 @@ def test_random_state_steps_fp64(lbfd, lat, n):
 
 def test_adsorption_droplet_full_size_fp64(lbfd):
     """The stationary-droplet adsorption workload at its full size (D2Q9,
-    128 x 128, R = 25), 500 steps, FP64: parity and conservation."""
-    say("[droplet128 fp64 500 steps]")
+    128 x 128, R = 25), its whole 2000-step window, FP64: parity and
+    conservation."""
+    say("[droplet128 fp64 2000 steps]")
     p, q = W.droplet_adsorption()
-    s, o = run_pair(lbfd, p, q, 500)
+    s, o = run_pair(lbfd, p, q, 2000)
     errs = state_errors(s, o)
     say(errs)
     assert max(errs.values()) < 1e-10, errs
