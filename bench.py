@@ -1028,6 +1028,67 @@ def autotune(out_path, workload, precision, warmup):
                                                 default_ms_per_step=r["default_ms_per_step"]) for r in res])
 
 
+def column_rise_report(eos=(1.0, 10.0, 50.0), bis=(None, 0.01, 1.0, 10.0), precision="bf16dev", steps=50000,
+                       sor_sweeps=16):
+    """The benchmark column itself (D3Q19 128 x 128 x 384, walls in x and y,
+    periodic z, bubble diameter 32, density and viscosity ratio 10, Mo = 0.1 at
+    Eo = 1, C = 0.5 outside, Gamma = 0) over the configuration's 50 000 steps:
+    terminal rise velocity (eq 33, mean over the last tenth of the run) of each
+    Eo with a clean interface (bis entry None) and with surfactant at each Biot
+    number, and its ratio to the clean run of the same Eo. buoyancy_ref = 1
+    (the domain-mean density): with the printed reference the periodic column
+    as a whole accelerates and no terminal velocity exists."""
+    import workloads as W
+    from paper_2311_15242_amd import lbfd
+
+    say = lambda *a: print("[column]", *a, file=sys.stderr, flush=True)
+    out = dict(grid=[128, 128, 384], precision=precision, steps=steps, sor_sweeps_launched=sor_sweeps,
+               velocity="eq 33, mean over the last tenth; U_th of eq 35", cases={})
+    for Eo in eos:
+        clean_u = None
+        for Bi in bis:
+            name = f"Eo{Eo:g} " + ("clean" if Bi is None else f"Bi{Bi:g}")
+            p, q = W.bubble_rise(Eo=Eo, Bi=Bi if Bi is not None else 1.0, clean=Bi is None, precision=precision,
+                                 buoyancy_ref=1)
+            p["sor_max_sweeps"] = sor_sweeps
+            g = -p["gravity"][2]
+            drho, muB, muR, R = p["rhoB0"] - p["rhoR0"], p["muB0"], p["muR0"], 16.0
+            u_th = (2.0 / 3.0) * g * drho * R * R / muB * (muB + muR) / (2.0 * muB + 3.0 * muR)
+            chunk = steps // 100
+            s = lbfd.Solver(p).init_fields(q)
+            t0 = time.time()
+            hist = []
+            try:
+                for c in range(100):
+                    s.step(chunk)
+                    ob = s.observables()
+                    hist.append((ob["velocity"][2], ob["psi_av"], ob["centroid"][2], ob["deformation"]))
+                    if c % 25 == 24:
+                        say(f"{name}: {(c + 1) * chunk} steps, U/U_th {ob['velocity'][2] / u_th:.4f} "
+                            f"({time.time() - t0:.1f} s)")
+            except lbfd.LbfdError as e:
+                out["cases"][name] = dict(error=str(e), steps_done=len(hist) * chunk)
+                say(f"{name}: {e}")
+                s.close()
+                continue
+            s.close()
+            h = np.array(hist)
+            u_end = float(h[90:, 0].mean())
+            rec = dict(u_terminal=float(f"{u_end:.6g}"), u_over_uth=round(u_end / u_th, 4),
+                       re=round(2.0 * p["rhoB0"] * u_end * R / muB, 3),
+                       u_change_last_tenth=float(f"{abs(h[99, 0] - h[89, 0]) / max(abs(u_end), 1e-30):.3e}"),
+                       deformation=round(float(h[99, 3]), 4), seconds=round(time.time() - t0, 1))
+            if Bi is None:
+                clean_u = u_end
+            else:
+                rec["psi_av"] = round(float(h[90:, 1].mean()), 5)
+                if clean_u:
+                    rec["u_over_clean"] = round(u_end / clean_u, 4)
+            out["cases"][name] = rec
+            say(f"{name}: {json.dumps(rec)}")
+    return out
+
+
 def shear_precision_report(steps=20000, every=1000, field_every=5000):
     """The sheared drop (D2Q9 512 x 256, Sec 3.3 groups) at the eight corners
     Ca in {0.1, 0.4}, Bi in {0.1, 1}, E0 in {0.1, 0.5}, in the FP64, FP32 and
@@ -1327,6 +1388,12 @@ def main():
     ap.add_argument("--autotune", metavar="OUT_JSON",
                     help="tune the launch shapes of the headline workload and of the 64-instance batch, write "
                          "the table to OUT_JSON and exit")
+    ap.add_argument("--column-report", default=None, metavar="EOS",
+                    help="terminal rise velocity on the benchmark column (128x128x384, 50000 steps) at the "
+                         "comma-separated Eo values, clean and at Bi 0.01, 1, 10; print JSON and exit")
+    ap.add_argument("--column-precision", default="bf16dev")
+    ap.add_argument("--column-bis", default="clean,0.01,1,10")
+    ap.add_argument("--column-sweeps", type=int, default=16, help="SOR sweeps launched per step")
     ap.add_argument("--shear-report", action="store_true",
                     help="deformation D(t) of the sheared drop in FP64 / FP32 / FP16-dev against the stored FP64 "
                          "oracle curves (tests/golden/shear_deformation_20k.json), print JSON and exit")
@@ -1348,6 +1415,12 @@ def main():
         return
     if args.cpu_windows:
         print(cpu_windows(), flush=True)
+        return
+    if args.column_report:
+        eos = tuple(float(e) for e in args.column_report.split(","))
+        bis = tuple(None if b == "clean" else float(b) for b in args.column_bis.split(","))
+        print(json.dumps(column_rise_report(eos, bis, args.column_precision, sor_sweeps=args.column_sweeps)),
+              flush=True)
         return
     if args.shear_report:
         print(json.dumps(shear_precision_report()), flush=True)
