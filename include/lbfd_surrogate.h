@@ -48,7 +48,8 @@ typedef struct lbfd_sg lbfd_sg;
 
 typedef struct {
     int32_t tile;       /* output edge of a training tile (its input edge is tile + 8), 3..64 */
-    int32_t max_batch;  /* most tiles per lbfd_sg_gradient / lbfd_sg_train_step / lbfd_sg_tiles call, >= 1 */
+    int32_t max_batch;  /* most tiles per lbfd_sg_gradient / lbfd_sg_train_step / lbfd_sg_tiles call, >= 1,
+                           with max_batch (tile + 6)^3 < 2^31 (LBFD_EINVAL otherwise) */
     int32_t field[3];   /* largest solver grid (nx, ny, nz) for the whole-field calls; 0s: none */
     int32_t k;          /* FD substeps one application replaces (>= 1) */
     double lr, beta1, beta2, adam_eps;             /* Adam */

@@ -3162,6 +3162,7 @@ static int sg_layout(const lbfd_sg_params *p, SgLayout *L)
     if (field && (p->field[0] < 1 || p->field[1] < 1 || p->field[2] < 1)) return LBFD_EINVAL;
     const long long T = p->tile, B = p->max_batch;
     long long ca = layer_nodes(1, B, T + 8, T + 8, T + 8), co = B * cube(T), cf = 0;
+    if (ca >= (1LL << 31)) return LBFD_EINVAL;   // node indices of a tile batch stay 32-bit
     if (field) {
         const long long fx = p->field[0] + 8, fy = p->field[1] + 8, fz = p->field[2] + 8;
         ca = std::max(ca, layer_nodes(1, 1, fz, fy, fx));
@@ -3379,15 +3380,13 @@ static int sg_backward(lbfd_sg *s, const uint16_t *in, const float *tgt, int B)
         const long long M = layer_nodes(l + 1, B, E, E, E);
         const uint16_t *x = l == 0 ? in : s->act[l - 1];
         const long long S = std::min<long long>(256, std::max<long long>(1, (M + 4095) / 4096));
-        const long long per = ((M + S - 1) / S + 63) / 64 * 64;
+        const long long per = ((M + S - 1) / S + 255) / 256 * 256;
         if (l == 0)
             hipLaunchKernelGGL((sg::k_conv_wgrad<16>), dim3(27, (unsigned)S), dim3(256), 0, st, x, s->dy[cur],
-                               s->net.gw[l], Di, Di, Di, M, per);
+                               s->net.gw[l], s->net.gb[l], Di, Di, Di, M, per);
         else
             hipLaunchKernelGGL((sg::k_conv_wgrad<32>), dim3(27, (unsigned)S), dim3(256), 0, st, x, s->dy[cur],
-                               s->net.gw[l], Di, Di, Di, M, per);
-        hipLaunchKernelGGL(sg::k_bias_grad, dim3(std::min(1024u, blocks_for(M, 2048))), dim3(256), 0, st,
-                           s->dy[cur], M, s->net.gb[l]);
+                               s->net.gw[l], s->net.gb[l], Di, Di, Di, M, per);
         if (l > 0) {
             const long long Mi = layer_nodes(l, B, E, E, E);
             hipLaunchKernelGGL(sg::k_conv_dgrad, dim3(blocks_for(Mi, 256)), dim3(256), 0, st, s->dy[cur],

@@ -9,9 +9,9 @@
 // grids the weights stay in registers and the input marches through LDS by planes. Input gradient: rows =
 // input nodes, columns = input channels, reduction over taps x output channels
 // (the transposed weights). Weight gradient: one 32 x 32 tile (input x output
-// channels) per tap, reduction over nodes in 64-node chunks staged in LDS
+// channels) per tap, reduction over nodes in 256-node chunks staged in LDS
 // transposed so every operand fragment is a 16-byte LDS read; partial tiles meet
-// in FP32 atomics.
+// in FP32 atomics (the bias gradient rides along in the blocks of one tap).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -439,21 +439,27 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const u16 *__restrict__ dy, 
 
 // Weight gradient of a layer: dw[tap][i][o] += sum_v x[v + tap][i] dy[v][o] over the
 // output nodes [v0, v1) of this block's split; grid (27 taps, splits). x: BF16 layer
-// input [B][Di][Hi][Wi][CIN]; dy: BF16 [M][32]; dw: FP32 [27][CIN][32].
+// input [B][Di][Hi][Wi][CIN]; dy: BF16 [M][32]; dw: FP32 [27][CIN][32]. The blocks of
+// tap 0 also add the bias gradient db[o] += sum_v dy[v][o]. Each stage stages 256
+// output nodes (input and output gradient transposed to [channel][node] in LDS, so
+// every operand fragment is a 16-byte LDS read); each wavefront reduces over 64 of
+// them in four matrix instructions; partial tiles meet in FP32 atomics.
 template <int CIN>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const u16 *__restrict__ x, const u16 *__restrict__ dy,
-                                                   float *__restrict__ dw, int Di, int Hi, int Wi, long long M,
-                                                   long long per_split)
+                                                   float *__restrict__ dw, float *__restrict__ db, int Di, int Hi,
+                                                   int Wi, long long M, long long per_split)
 {
-    constexpr int LDV = 64 + 8;
+    constexpr int CH = 256;                 // output nodes per stage
+    constexpr int LDV = CH + 8;
     __shared__ __attribute__((aligned(16))) u16 xs[32 * LDV];   // [channel][node]
     __shared__ __attribute__((aligned(16))) u16 ds[32 * LDV];
     __shared__ float red[3][16][64];
+    __shared__ float bred[8][32];
     const int tap = blockIdx.x;
     const int a = tap / 9, p = (tap / 3) % 3, q = tap % 3;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int mr = lane & 31, kg = lane >> 5;
-    const int Do = Di - 2, Ho = Hi - 2, Wo = Wi - 2;
+    const uint32_t Do = Di - 2, Ho = Hi - 2, Wo = Wi - 2;
     const long long v_begin = (long long)blockIdx.y * per_split;
     long long v_end = v_begin + per_split;
     if (v_end > M) v_end = M;
@@ -462,38 +468,61 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const u16 *__restrict__ x, c
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-    const int j = threadIdx.x & 63, part = threadIdx.x >> 6;   // staging: node j, channels part*8..+7
-    for (long long v0 = v_begin; v0 < v_end; v0 += 64) {
+    float bsum = 0.0f;                      // tap 0: channel t mod 32 over nodes t/32, t/32 + 8, ...
+    const int j = threadIdx.x;              // staging: node j of the stage, every channel
+    for (long long v0 = v_begin; v0 < v_end; v0 += CH) {
         const long long m = v0 + j;
         const bool ok = m < v_end;
-        u32x4 xv = {0u, 0u, 0u, 0u}, dv = {0u, 0u, 0u, 0u};
+        u32x4 xv[CIN / 8], dv[4];
+#pragma unroll
+        for (int k = 0; k < CIN / 8; ++k) xv[k] = u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dv[k] = u32x4{0u, 0u, 0u, 0u};
         if (ok) {
-            long long r = m;
-            const int xo = (int)(r % Wo);
+            uint32_t r = (uint32_t)m;       // the host keeps M below 2^31
+            const uint32_t xo = r % Wo;
             r /= Wo;
-            const int yo = (int)(r % Ho);
+            const uint32_t yo = r % Ho;
             r /= Ho;
-            const int zo = (int)(r % Do);
-            const long long b = r / Do;
-            const long long src = (((b * Di + zo + a) * Hi + yo + p) * (long long)Wi + xo + q) * CIN;
-            if (part * 8 < CIN) xv = *(const u32x4 *)&x[src + part * 8];
-            dv = *(const u32x4 *)&dy[m * CO + part * 8];
+            const uint32_t zo = r % Do;
+            const uint32_t b = r / Do;
+            const long long src = ((((long long)b * Di + zo + a) * Hi + yo + p) * (long long)Wi + xo + q) * CIN;
+#pragma unroll
+            for (int k = 0; k < CIN / 8; ++k) xv[k] = *(const u32x4 *)&x[src + k * 8];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) dv[k] = *(const u32x4 *)&dy[m * CO + k * 8];
         }
-        const u16 *xe = (const u16 *)&xv, *de = (const u16 *)&dv;
-        if (part * 8 < CIN)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) xs[(part * 8 + e) * LDV + j] = xe[e];
+        for (int k = 0; k < CIN / 8; ++k) {
+            const u16 *xe = (const u16 *)&xv[k];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) ds[(part * 8 + e) * LDV + j] = de[e];
+            for (int e = 0; e < 8; ++e) xs[(k * 8 + e) * LDV + j] = xe[e];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const u16 *de = (const u16 *)&dv[k];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) ds[(k * 8 + e) * LDV + j] = de[e];
+        }
         __syncthreads();
-        const bf16x8 A = frag(&xs[mr * LDV + 16 * wave + 8 * kg]);
-        const bf16x8 B = frag(&ds[mr * LDV + 16 * wave + 8 * kg]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc, 0, 0, 0);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int col = 64 * wave + 16 * kk + 8 * kg;
+            const bf16x8 A = frag(&xs[mr * LDV + col]);
+            const bf16x8 B = frag(&ds[mr * LDV + col]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc, 0, 0, 0);
+        }
+        if (tap == 0) {
+            const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+#pragma unroll 8
+            for (int n = g; n < CH; n += 8) bsum += bf2f(ds[c * LDV + n]);
+        }
         __syncthreads();
     }
     if (wave > 0)
 #pragma unroll
         for (int r = 0; r < 16; ++r) red[wave - 1][r][lane] = acc[r];
+    if (tap == 0) bred[threadIdx.x >> 5][threadIdx.x & 31] = bsum;
     __syncthreads();
     if (wave == 0)
 #pragma unroll
@@ -502,20 +531,11 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const u16 *__restrict__ x, c
             const int i = acc_row(r, kg);
             if (i < CIN && s != 0.0f) atomicAdd(&dw[((long long)tap * CIN + i) * CO + mr], s);
         }
-}
-
-// Bias gradient: db[o] += sum over nodes of dy[v][o] (BF16 [M][32]).
-__global__ __launch_bounds__(256) void k_bias_grad(const u16 *__restrict__ dy, long long M, float *__restrict__ db)
-{
-    __shared__ float sh[8][32];
-    const int o = threadIdx.x & 31, g = threadIdx.x >> 5;
-    float s = 0.0f;
-    for (long long m = (long long)blockIdx.x * 8 + g; m < M; m += (long long)gridDim.x * 8) s += bf2f(dy[m * CO + o]);
-    sh[g][o] = s;
-    __syncthreads();
-    if (g == 0) {
-        for (int k = 1; k < 8; ++k) s += sh[k][o];
-        atomicAdd(&db[o], s);
+    if (tap == 0 && threadIdx.x < 32) {
+        float t = 0.0f;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) t += bred[g][threadIdx.x];
+        if (t != 0.0f) atomicAdd(&db[threadIdx.x], t);
     }
 }
 
