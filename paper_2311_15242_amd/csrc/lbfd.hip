@@ -547,7 +547,9 @@ template <int LAT, class P> __device__ __forceinline__ void collide_body(const K
     const R *mac = k.fld.mac[sa.lev];
 
     const Nbhd nb = make_nbhd(k, x, y, z);
-    const R rR = ld(mac, n), rB = ld(mac + N, n), rN = ld(mac + 2 * N, n);
+    const R rR = ld(mac, n), rB = ld(mac + N, n);
+    // the colour function of eq 6, as the macroscopic kernel forms it from rho^R, rho^B
+    const R rr = rR * k.irho0[0], bb = rB * k.irho0[1], rN = (rr - bb) / (rr + bb);
     const R rho = rR + rB, irho = R(1) / rho;
     R u[3] = {0, 0, 0}, F[3] = {0, 0, 0}, nv[3] = {0, 0, 0};
 #pragma unroll
