@@ -260,20 +260,21 @@ def test_advance_accepts_and_conserves(lbfd):
     assert abs(ob["total_surf"] - M0) <= 1e-3 * M0
 
 
-@pytest.mark.parametrize("shape", [(11, 14, 75), (45, 13, 71)])
-def test_forward_wide_grid_matches_reference(lbfd, shape):
+@pytest.mark.parametrize("shape,batch", [((11, 14, 75), 1), ((45, 13, 71), 1), ((9, 10, 70), 2)])
+def test_forward_wide_grid_matches_reference(lbfd, shape, batch):
     """Grids at least 60 output nodes wide run the z-marching kernel (columns of
     30 x 4 output nodes over 32 planes, weights in registers, input planes in LDS);
-    ragged in every direction, and the second grid spans two column heights."""
+    ragged in every direction, the second grid spans two column heights and the
+    third is a batch of two grids."""
     import torch
 
     rng = np.random.default_rng(13)
     ps = gpu_params(OS.init_params(5, out_scale=1.0))
     d, h, w = shape
-    x6 = bf16(rng.uniform(-1.0, 1.0, (1, d, h, w, 6)))
-    sg = make_sg(lbfd, tile=4, max_batch=1, field=(w - 8, h - 8, d - 8))
+    x6 = bf16(rng.uniform(-1.0, 1.0, (batch, d, h, w, 6)))
+    sg = make_sg(lbfd, tile=16, max_batch=batch, field=(w - 8, h - 8, d - 8))
     sg.set_params(OS.flatten(ps))
-    out = torch.empty((1, d - 8, h - 8, w - 8, OS.NOUT), dtype=torch.float32, device="cuda")
+    out = torch.empty((batch, d - 8, h - 8, w - 8, OS.NOUT), dtype=torch.float32, device="cuda")
     sg.forward(bf16_tensor(padded_input(x6)), out)
     ref, _ = ref_forward(ps, x6)
     err = float(np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max())
