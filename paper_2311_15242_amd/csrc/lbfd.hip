@@ -1111,18 +1111,32 @@ __device__ __forceinline__ void sor_node(const KP<typename P::R> &k, const SorOp
         q[5] = z < nz - 1 ? o + sz : split_idx(k, x, y, 0);
     }
     // diag = W_n + sum_f w_f, off = sum_f w_f chi_f over the faces present (a wall
-    // face carries no flux), w_f = (Dc/2) (W_n + W_f)/2, for both systems at once
+    // face carries no flux), w_f = (Dc/2) (W_n + W_f)/2, for both systems at once.
+    // FP32: each face's pairs are loaded as it is accumulated; FP64 (16-byte pairs):
+    // all faces are loaded first (measured faster in each mode; same arithmetic).
     const V2<R> Wn = ld(a.w, n), c0 = ld((const V2<R> *)a.chi, n), rhs = ld(a.rhs, n);
     R dP = Wn.x, oP = 0, dF = Wn.y, oF = 0;
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        if (!on[f]) continue;
-        const V2<R> Wf = ld(a.w, q[f]), cf = ld((const V2<R> *)a.chi, q[f]);
+    const auto face = [&](const V2<R> &Wf, const V2<R> &cf) {
         const R wP = a.hdP * (R(0.5) * (Wn.x + Wf.x)), wF = a.hdF * (R(0.5) * (Wn.y + Wf.y));
         dP += wP;
         oP += wP * cf.x;
         dF += wF;
         oF += wF * cf.y;
+    };
+    if constexpr (sizeof(R) == 8) {
+        V2<R> Wf[NF], cf[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            Wf[f] = on[f] ? ld(a.w, q[f]) : V2<R>{R(0), R(0)};
+            cf[f] = on[f] ? ld((const V2<R> *)a.chi, q[f]) : V2<R>{R(0), R(0)};
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (on[f]) face(Wf[f], cf[f]);
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (on[f]) face(ld(a.w, q[f]), ld((const V2<R> *)a.chi, q[f]));
     }
     // the pre-update residual |rhs - (diag chi - off)| and |rhs| feed the maxima; a
     // converged system keeps its value
