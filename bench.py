@@ -195,17 +195,17 @@ def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, seed=0):
                         dpsi_s=dps, dphi_s=dph, drift_tol=1e-6)
     sg.set_params(sgtrain.initial_params(seed))
     bufs = sgtrain.feature_buffers(s)
-    Xs, Ys = [], []
+    # the training set is filled in place (at 65,536 tiles it takes 168 GB of HBM)
+    T = 32
+    X = torch.empty((snapshots * tiles_per_snap, T + 8, T + 8, T + 8, 16), dtype=torch.int16, device="cuda")
+    Y = torch.empty((snapshots * tiles_per_snap, T, T, T, 4), dtype=torch.float32, device="cuda")
     t0 = time.time()
     for i in range(snapshots):
         s.step(25)
-        X, Y = sgtrain.snapshot_tiles(s, sg, tiles_per_snap, rng, bufs)
-        Xs.append(X)
-        Ys.append(Y)
-    X, Y = torch.cat(Xs), torch.cat(Ys)
-    del Xs, Ys
+        a = i * tiles_per_snap
+        sgtrain.snapshot_tiles(s, sg, tiles_per_snap, rng, bufs, out=(X[a:a + tiles_per_snap], Y[a:a + tiles_per_snap]))
     s.step(25)
-    Xh, Yh = sgtrain.snapshot_tiles(s, sg, 32, rng, bufs)
+    Xh, Yh = sgtrain.snapshot_tiles(s, sg, 128, rng, bufs)
     torch.cuda.synchronize()
     t_data = time.time() - t0
     say(f"{X.shape[0]} training tiles in {t_data:.1f} s")

@@ -41,10 +41,11 @@ def tile_origins(solver, T: int, n_tiles: int, rng, interface_share: float = 0.7
     return org.astype(np.int32)
 
 
-def snapshot_tiles(solver, sg, n_tiles: int, rng, bufs=None, interface_share: float = 0.75):
+def snapshot_tiles(solver, sg, n_tiles: int, rng, bufs=None, interface_share: float = 0.75, out=None):
     """n_tiles training tiles of the solver's current state: inputs from the
     state now, targets from the state after k frozen-flow FD substeps (the
-    solver's psi and phi are left advanced by those substeps)."""
+    solver's psi and phi are left advanced by those substeps). out: optional
+    (X, Y) device tensors of n_tiles tiles to fill (a slice of a larger set)."""
     import torch
 
     T = sg.cfg["tile"]
@@ -53,8 +54,13 @@ def snapshot_tiles(solver, sg, n_tiles: int, rng, bufs=None, interface_share: fl
     sg.features(solver, feat)
     sg.snapshot(solver, snap)
     solver.fd_substeps(sg.cfg["k"])
-    X = torch.empty((n_tiles, T + 8, T + 8, T + 8, 16), dtype=torch.int16, device=solver.device)
-    Y = torch.empty((n_tiles, T, T, T, 4), dtype=torch.float32, device=solver.device)
+    if out is not None:
+        X, Y = out
+        if tuple(X.shape) != (n_tiles, T + 8, T + 8, T + 8, 16) or tuple(Y.shape) != (n_tiles, T, T, T, 4):
+            raise ValueError("snapshot_tiles: out tensors of the wrong shape")
+    else:
+        X = torch.empty((n_tiles, T + 8, T + 8, T + 8, 16), dtype=torch.int16, device=solver.device)
+        Y = torch.empty((n_tiles, T, T, T, 4), dtype=torch.float32, device=solver.device)
     mb = sg.cfg["max_batch"]
     for a in range(0, n_tiles, mb):
         b = min(n_tiles, a + mb)
