@@ -22,8 +22,9 @@
  * separately written NumPy brute force and exact dense solves. Parity partly
  * pinned: rows 16-18 of the 3-D moment equilibrium (eq 40) beyond u = 0
  * (pinned at u = 0 and by covariance under the lattice symmetries only).
- * Parity unpinned: the form of the rescaling of the total surfactant (Sec 2.2
- * cites it without giving it; the single factor used here is a reading).
+ * The rescaling of the total surfactant (Sec 2.2 cites it without giving it)
+ * is pinned to its reading: one factor for psi and phi from the new level's
+ * weights, checked against the factor summed from an unrescaled step.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math).
  */

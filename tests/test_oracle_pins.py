@@ -576,6 +576,33 @@ def test_mass_conservation_and_rescaled_total():
     assert 0 < abs(b["drift_pre"]) < 1e-6
 
 
+def test_rescaling_is_one_common_factor_at_the_new_level():
+    """Sec 2.2 restores the total surfactant with the multiplicative rescaling of
+    Xu et al. Reading: one factor M0 / M for psi and phi, M = sum(G psi + X phi)
+    with the weights of the new level. From one state, a step with and a step
+    without rescaling leave the same populations, and psi and phi differ by that
+    one factor, summed here from the unrescaled step's fields. Rescaling psi
+    alone (5e-6 off) or weighting with the old level's G and X (4e-5) fails."""
+    p, q = W.droplet_adsorption(n=32, radius=8.0)
+    p["bc"] = [1, 0, 0]
+    a = oracle.Oracle(dict(p, rescale=1)).init(q)
+    b = oracle.Oracle(dict(p, rescale=0)).init(q)
+    M0 = b.initial_total
+    a.step(1)
+    b.step(1)
+    for name in ("fR", "fB"):
+        assert np.array_equal(a.field(name), b.field(name)), name
+    eps = p["fd_eps"]
+    Gw = b.field("G") + eps
+    Xw = 1.0 - b.field("rhoN") + eps
+    M = float(np.sum(Gw * b.field("psi") + Xw * b.field("phi")))
+    sc = M0 / M
+    assert 1e-9 < abs(sc - 1.0) < 1e-6   # the step drifted, the factor is not 1
+    for name in ("psi", "phi"):
+        x, y = a.field(name), b.field(name)
+        assert np.abs(x - sc * y).max() <= 1e-14 * np.abs(y).max(), name
+
+
 def test_frozen_flow_conserves_surfactant_without_rescaling():
     """With no force the fluid stays at rest (to rounding); the FD scheme then
     conserves sum(G psi + X phi) to the solver tolerance on its own."""
