@@ -531,7 +531,8 @@ __global__ __launch_bounds__(256) void kb_force(const KP<typename P::R> *tab, co
 // MRT collision in moment space (eqs 1-4 with the equilibria, corrections and
 // relaxation rates of Appendix A), the recolouring descriptor of eqs 11-12,
 // and push propagation (eq 13) into the other population buffer.
-template <int LAT, class P> __device__ __forceinline__ void collide_body(const KP<typename P::R> &k, int tile, const StepArgs &sa)
+template <int LAT, class P, bool WM>
+__device__ __forceinline__ void collide_body(const KP<typename P::R> &k, int tile, const StepArgs &sa)
 {
     using R = typename P::R;
     using S = typename P::S;
@@ -665,25 +666,38 @@ template <int LAT, class P> __device__ __forceinline__ void collide_body(const K
     // propagation with periodic wrap or half-way bounce-back of f_dag_i = (M^-1 m*)_i
     // (deviation modes: minus ref_i)
     Dither dz(n, P::DEV ? k.fld.sc->tick : 0u, 1u);
-    auto emit = [&](const int i, R v) {
+    // deviation modes: a reflected population is stored in direction opp(i), and
+    // ref_i - ref_opp(i) = 6 rho w_i e_i.u*; refl(i) is that term (zero components
+    // of e_i skipped), and refl(opp(i)) = -refl(i)
+    auto refl = [&](const int i) -> R {
+        R eus = R(0);
+        bool first = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (L::E[i][d] == 0) continue;
+            eus = first ? R(L::E[i][d]) * us[d] : eus + R(L::E[i][d]) * us[d];
+            first = false;
+        }
+        return R(6 * L::W[i]) * rho * eus;
+    };
+    auto emit = [&](const int i, R v, R rf) {
         const int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
         // the first wall axis the population crosses reflects it, with Ladd's moving-wall
-        // term -6 w_i rho (e_i . u_w) (a per-wall table); every index is a compile-time constant
+        // term -6 w_i rho (e_i . u_w) (a per-wall table; WM false: no wall moves and the
+        // term is zero); every index is a compile-time constant
         const bool bx = ex != 0 && nb_wall_axis(nb, 0, ex);
         const bool by = !bx && ey != 0 && nb_wall_axis(nb, 1, ey);
         const bool bz = !bx && !by && ez != 0 && nb_wall_axis(nb, 2, ez);
         const bool bo = bx || by || bz;
-        R wt = R(0);
-        if (ex != 0) wt = bx ? k.wterm[ex > 0 ? 1 : 0][i] : wt;
-        if (ey != 0) wt = by ? k.wterm[ey > 0 ? 3 : 2][i] : wt;
-        if (ez != 0) wt = bz ? k.wterm[ez > 0 ? 5 : 4][i] : wt;
-        v -= rho * wt;
+        if constexpr (WM) {
+            R wt = R(0);
+            if (ex != 0) wt = bx ? k.wterm[ex > 0 ? 1 : 0][i] : wt;
+            if (ey != 0) wt = by ? k.wterm[ey > 0 ? 3 : 2][i] : wt;
+            if (ez != 0) wt = bz ? k.wterm[ez > 0 ? 5 : 4][i] : wt;
+            v -= rho * wt;
+        }
         if constexpr (P::DEV) {
-            // a reflected population is stored in direction opp(i): ref_i - ref_opp(i) = 6 rho w_i e_i.u*
-            if (i != 0) {
-                const R eus = R(ex) * us[0] + R(ey) * us[1] + R(ez) * us[2];
-                v += bo ? R(6 * L::W[i]) * rho * eus : R(0);
-            }
+            if (i != 0) v += bo ? rf : R(0);
         }
         // one store: base at the lower plane of the pair (i, opp(i)), which are at most
         // two planes apart, so the offset stays below 3 N elements
@@ -699,7 +713,7 @@ template <int LAT, class P> __device__ __forceinline__ void collide_body(const K
 #pragma unroll
         for (int r = 0; r < Q; ++r)
             if (L::MINV[0][r] != 0.0) v += R(L::MINV[0][r]) * m[r];
-        emit(0, v);
+        emit(0, v, R(0));
     }
     // opposite pairs: the even rows of M^-1 m* are shared, the odd ones change sign
 #pragma unroll
@@ -712,20 +726,21 @@ template <int LAT, class P> __device__ __forceinline__ void collide_body(const K
             if (row_even<LAT>(r)) ev += R(L::MINV[i][r]) * m[r];
             else od += R(L::MINV[i][r]) * m[r];
         }
-        emit(i, ev + od);
-        emit(L::OPP[i], ev - od);
+        const R rf = P::DEV ? refl(i) : R(0);
+        emit(i, ev + od, rf);
+        emit(L::OPP[i], ev - od, -rf);
     }
 }
-template <int LAT, class P> __global__ __launch_bounds__(256) void k_collide(KP<typename P::R> k)
+template <int LAT, class P, bool WM> __global__ __launch_bounds__(256) void k_collide(KP<typename P::R> k)
 {
-    collide_body<LAT, P>(k, xcd_tile((int)blockIdx.x, (int)gridDim.x), step_args(k));
+    collide_body<LAT, P, WM>(k, xcd_tile((int)blockIdx.x, (int)gridDim.x), step_args(k));
 }
-template <int LAT, class P>
+template <int LAT, class P, bool WM>
 __global__ __launch_bounds__(256) void kb_collide(const KP<typename P::R> *tab, const int *prefix, int ninst, StepArgs sa)
 {
     int inst, local;
     batch_tile(prefix, ninst, inst, local);
-    collide_body<LAT, P>(tab[inst], local, sa);
+    collide_body<LAT, P, WM>(tab[inst], local, sa);
 }
 
 // ============================================================== macroscopic fields
@@ -801,12 +816,17 @@ __device__ __forceinline__ void macro_body(const KP<typename P::R> &k, int tile,
     const Nbhd nb = make_nbhd(k, x, y, z);
     // halo cell of this node
     const int hself = (int)(threadIdx.x + 1) + HX * ((int)(threadIdx.y + 1) + HY * (D == 3 ? 1 : 0));
+    // sums start at their first term (0 + x is not folded in IEEE arithmetic); the
+    // flags are compile-time constants once the loops are unrolled
     R rR = 0, rB = 0, j[3] = {0, 0, 0};
+    bool jset[3] = {false, false, false}, rset = false;
     R m[P::DEV ? Q : 1];
+    bool mset[P::DEV ? Q : 1];
     if constexpr (P::DEV) {
 #pragma unroll
-        for (int r = 0; r < Q; ++r) m[r] = 0;
+        for (int r = 0; r < Q; ++r) { m[r] = 0; mset[r] = false; }
     }
+    auto acc = [](R &sum, bool &set, R v) { sum = set ? sum + v : v; set = true; };
     // one arrival: its population (deviation modes: plus the reference of the node it
     // left) and its recoloured share of rho^R, rho^B
     auto arrive = [&](const int q) -> R {
@@ -845,13 +865,20 @@ __device__ __forceinline__ void macro_body(const KP<typename P::R> &k, int tile,
             c[2] = A.w;
         }
         const R sgn = bo ? R(-1) : R(1);   // a reflected arrival left its source along -e_q
-        R ec = R(L::E[q][0]) * c[0] + R(L::E[q][1]) * c[1];
-        if constexpr (D == 3) ec += R(L::E[q][2]) * c[2];
+        R ec = R(0);   // zero components of e_q skipped
+        bool first = true;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if (L::E[q][d] == 0) continue;
+            ec = first ? R(L::E[q][d]) * c[d] : ec + R(L::E[q][d]) * c[d];
+            first = false;
+        }
         ec *= sgn;
         R wgt = k.recolour_literal ? R(L::W[q]) : as * k.rest[0][q] + (R(1) - as) * k.rest[1][q];
         R r = wgt * ec;
-        rR += as * fq + r;
-        rB += (R(1) - as) * fq - r;
+        bool rs = rset;
+        acc(rR, rset, as * fq + r);
+        acc(rB, rs, (R(1) - as) * fq - r);
         return fq;
     };
     {
@@ -859,7 +886,7 @@ __device__ __forceinline__ void macro_body(const KP<typename P::R> &k, int tile,
         if constexpr (P::DEV) {
 #pragma unroll
             for (int r2 = 0; r2 < Q; ++r2)
-                if (L::M[r2][0] != 0 && !conserved_row<LAT>(r2)) m[r2] += R(L::M[r2][0]) * f0;
+                if (L::M[r2][0] != 0 && !conserved_row<LAT>(r2)) acc(m[r2], mset[r2], R(L::M[r2][0]) * f0);
         }
     }
     // opposite pairs: momentum and the odd moment rows take f_q - f_opp(q), the even
@@ -871,11 +898,12 @@ __device__ __forceinline__ void macro_body(const KP<typename P::R> &k, int tile,
         const R sp = fa + fb, sm = fa - fb;
 #pragma unroll
         for (int d = 0; d < D; ++d)
-            if (L::E[q][d] != 0) j[d] += R(L::E[q][d]) * sm;
+            if (L::E[q][d] != 0) acc(j[d], jset[d], R(L::E[q][d]) * sm);
         if constexpr (P::DEV) {
 #pragma unroll
             for (int r2 = 0; r2 < Q; ++r2)
-                if (L::M[r2][q] != 0 && !conserved_row<LAT>(r2)) m[r2] += R(L::M[r2][q]) * (row_even<LAT>(r2) ? sp : sm);
+                if (L::M[r2][q] != 0 && !conserved_row<LAT>(r2))
+                    acc(m[r2], mset[r2], R(L::M[r2][q]) * (row_even<LAT>(r2) ? sp : sm));
         }
     }
     R *mac = k.fld.mac[1 - sa.lev];
@@ -1952,6 +1980,7 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
 {
     const bool three = p->lattice == LBFD_D3Q19;
     k.nx = p->nx; k.ny = p->ny; k.nz = p->nz;
+    k.wmove = 0;
     {
         // moving-wall term of the half-way bounce-back per wall and direction: 6 w_i (e_i . u_w)
         const int Q = three ? 19 : 9;
@@ -1964,6 +1993,7 @@ template <class R> void fill_kp(KP<R> &k, const lbfd_params *p, char *ws, const 
                     v = 6.0 * wi * (e[0] * p->wall_u[w][0] + e[1] * p->wall_u[w][1] + e[2] * p->wall_u[w][2]);
                 }
                 k.wterm[w][i] = (R)v;
+                if (k.wterm[w][i] != R(0)) k.wmove = 1;
             }
     }
     k.ihmu[0] = (R)(0.5 / p->muR0);
@@ -2354,7 +2384,8 @@ template <int LAT, class P> struct Impl {
         KP<R> &k = kp(h);
         for (long long t = 0; t < nsteps; ++t) {
             sync_levels(h);
-            LAUNCH(KC_COLLIDE, (k_collide<LAT, P>), h->grid, h->block, k);
+            if (k.wmove) LAUNCH(KC_COLLIDE, (k_collide<LAT, P, true>), h->grid, h->block, k);
+            else LAUNCH(KC_COLLIDE, (k_collide<LAT, P, false>), h->grid, h->block, k);
             LAUNCH_TY(h->rows, KC_MACRO, k_macro, h->grid, h->block, k);
             LAUNCH(KC_GEOM, (k_geom<LAT, P>), h->grid, h->block, k, 1 - k.lev);
             if (h->p.fd_enable && !h->fd_off) fd_block(h);
@@ -2374,6 +2405,8 @@ template <int LAT, class P> struct Impl {
         const KP<R> *tab = (const KP<R> *)b->tab;
         const int n = b->n;
         const dim3 blk(BX, b->rows, 1);
+        bool wmove = false;   // some instance has a moving wall
+        for (int i = 0; i < n; ++i) wmove = wmove || kp(b->inst[i]).wmove;
         for (long long t = 0; t < nsteps; ++t) {
             StepArgs sa;
             sa.lev = (int)(h->step & 1);
@@ -2381,7 +2414,8 @@ template <int LAT, class P> struct Impl {
             sa.pc = h->pc;
             sa.extrap = h->fd_hist >= 1 ? 1 : 0;
             sa.step = h->step;
-            LAUNCH(KC_COLLIDE, (kb_collide<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sa);
+            if (wmove) LAUNCH(KC_COLLIDE, (kb_collide<LAT, P, true>), b->grid_node, blk, tab, b->prefix_node, n, sa);
+            else LAUNCH(KC_COLLIDE, (kb_collide<LAT, P, false>), b->grid_node, blk, tab, b->prefix_node, n, sa);
             LAUNCH_TY(b->rows, KC_MACRO, kb_macro, b->grid_node, blk, tab, b->prefix_node, n, sa);
             LAUNCH(KC_GEOM, (kb_geom<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sa, 1 - sa.lev);
             const bool fd = h->p.fd_enable != 0;

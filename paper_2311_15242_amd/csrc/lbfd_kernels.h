@@ -227,6 +227,7 @@ template <class R> struct KP {
     int bc[3];
     R wall_u[6][3];
     R wterm[6][QMAX];   // 6 w_i (e_i . u_w) per wall (-x,+x,-y,+y,-z,+z) and direction
+    int wmove;          // some wterm is nonzero (a wall moves)
     R rhoR0, rhoB0;
     R irho0[2];         // 1/rhoR0, 1/rhoB0
     R muR0, muB0;
@@ -532,9 +533,16 @@ template <int LAT, class R>
 __device__ __forceinline__ R reference(const KP<R> &k, int i, R sgn, R rho, R a, const R *us)
 {
     using L = Lat<LAT>;
-    R eu = 0, uu = 0;
+    // zero components of e_i skipped: 0 * u and 0 + x are not folded in IEEE arithmetic
+    R eu = 0, uu = us[0] * us[0];
+    bool first = true;
 #pragma unroll
-    for (int d = 0; d < L::D; ++d) { eu += R(L::E[i][d]) * us[d]; uu += us[d] * us[d]; }
+    for (int d = 0; d < L::D; ++d) {
+        if (d > 0) uu += us[d] * us[d];
+        if (L::E[i][d] == 0) continue;
+        eu = first ? R(L::E[i][d]) * us[d] : eu + R(L::E[i][d]) * us[d];
+        first = false;
+    }
     eu *= sgn;
     R rest = a * k.rest[0][i] + (R(1) - a) * k.rest[1][i];
     return rho * (rest + R(L::W[i]) * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu));
