@@ -967,7 +967,10 @@ def class_rooflines(p, prof, steps, sor_half):
         if cls == "sor":
             nbytes = sor_half * algorithmic_bytes("sor", p) * N
         else:
-            nbytes = algorithmic_bytes(cls, p) * N * launches / steps
+            # the total class launches a pass over the nodes and a one-workgroup
+            # final reduction: its bytes count once per pair
+            passes = launches / 2 if cls == "total" else launches
+            nbytes = algorithmic_bytes(cls, p) * N * passes / steps
         ach = nbytes / per_step_s / 1e9
         r = dict(achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
                  ms_per_step=round(ms / steps, 4), algorithmic_bytes_per_step=nbytes)
