@@ -196,7 +196,7 @@ def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, seed=0):
     sg.set_params(sgtrain.initial_params(seed))
     bufs = sgtrain.feature_buffers(s)
     # the training set is filled in place (at 65,536 tiles it takes 168 GB of HBM)
-    T = 32
+    T = sg.cfg["tile"]
     X = torch.empty((snapshots * tiles_per_snap, T + 8, T + 8, T + 8, 16), dtype=torch.int16, device="cuda")
     Y = torch.empty((snapshots * tiles_per_snap, T, T, T, 4), dtype=torch.float32, device="cuda")
     t0 = time.time()
