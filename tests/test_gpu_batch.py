@@ -96,7 +96,9 @@ def test_batch_identical_to_single(lbfd, case, prec, steps):
     """Each instance of a batch is bit-identical to the same instance stepped
     alone: full-size 2-D columns of the sweep (the first eight draws), the 3-D
     boxes in the reduced-precision modes (BF16: the stochastic rounding draws
-    the same bits in a batch as alone), and a batch of one tiny grid."""
+    the same bits in a batch as alone; the first box's walls move, so the
+    batch runs the collision with the moving-wall term, which the other two
+    instances, run alone, skip), and a batch of one tiny grid."""
     if case == "manifest2d_8":
         inst = W.batch_instances(W.load_manifest()[:8], precision=prec)
     elif case == "mixed3d":
