@@ -158,7 +158,7 @@ def conv_flops(d, h, w, B=1):
     return float(f)
 
 
-def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, seed=0):
+def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, lr_final=None, seed=0):
     """The learned surrogate on the multi-bubble periodic box (D3Q19 n^3, 8 bubbles
     of diameter 24, Eo 10, Bi 1, FP32 solver): snapshot tiles from the solver,
     training on the GPU, the held-out error against the FD substeps it replaces,
@@ -210,7 +210,8 @@ def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, seed=0):
     t_data = time.time() - t0
     say(f"{X.shape[0]} training tiles in {t_data:.1f} s")
     e0, _ = sgtrain.tile_error(sg, Xh, Yh)
-    ms_train, hist = timed(lambda: sgtrain.train(sg, X, Y, train_steps, 8, rng, log_every=max(1, train_steps // 4)))
+    ms_train, hist = timed(lambda: sgtrain.train(sg, X, Y, train_steps, 8, rng, log_every=max(1, train_steps // 4),
+                                                 lr_final=lr_final))
     e1, _ = sgtrain.tile_error(sg, Xh, Yh)
     say(f"trained {train_steps} steps in {ms_train / 1e3:.1f} s: held-out error {e0:.3f} -> {e1:.3f}")
     del X, Y
@@ -271,7 +272,7 @@ def surrogate_bench(n, snapshots, tiles_per_snap, train_steps, blocks, seed=0):
         workload=f"multi_bubble {n}^3 periodic D3Q19, 8 bubbles D=24, Eo=10, Bi=1, FP32 solver; k={k} substeps",
         sor_sweeps_launched=p["sor_max_sweeps"],
         tiles_train=snapshots * tiles_per_snap, tiles_heldout=int(Xh.shape[0]), data_s=round(t_data, 2),
-        train_steps=train_steps, batch=8, train_ms=round(ms_train, 1),
+        train_steps=train_steps, batch=8, lr=1e-3, lr_final=lr_final, train_ms=round(ms_train, 1),
         train_tiles_per_s=round(train_steps * 8 / (ms_train / 1e3), 1),
         train_tflops=round(3.0 * conv_flops(40, 40, 40, 8) * train_steps / (ms_train / 1e3) / 1e12, 2),
         loss_first=hist[0][1], loss_last=hist[-1][1],
@@ -1370,6 +1371,8 @@ def main():
     ap.add_argument("--sg-tiles", type=int, default=512, help="training tiles per snapshot")
     ap.add_argument("--sg-train-steps", type=int, default=12000)
     ap.add_argument("--sg-blocks", type=int, default=4)
+    ap.add_argument("--sg-lr-final", type=float, default=1e-5,
+                    help="Adam step size at the end of a half-cosine decay from 1e-3 (negative: constant)")
     ap.add_argument("--omega", type=float, default=None, help="SOR relaxation factor (default: the workload's)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (scales rocprofv3 byte counters)")
@@ -1553,7 +1556,7 @@ def main():
         out["batched"] = batch_bench(args.batch_steps, args.warmup, args.sor_sweeps)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_bench(args.sg_size, args.sg_snapshots, args.sg_tiles, args.sg_train_steps,
-                                           args.sg_blocks)
+                                           args.sg_blocks, args.sg_lr_final if args.sg_lr_final > 0 else None)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, q, args.cpu_seconds)
     print(json.dumps(out), flush=True)

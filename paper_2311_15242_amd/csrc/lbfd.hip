@@ -3544,6 +3544,13 @@ int lbfd_sg_set_drift_tol(lbfd_sg *s, double tol)
     return LBFD_OK;
 }
 
+int lbfd_sg_set_lr(lbfd_sg *s, double lr)
+{
+    if (!s || !(lr > 0.0)) return LBFD_EINVAL;
+    s->p.lr = lr;
+    return LBFD_OK;
+}
+
 int lbfd_sg_advance(lbfd_handle *h, lbfd_sg *s, int64_t nblocks, lbfd_sg_report *rep)
 {
     if (!h || !s || nblocks < 0 || !h->p.fd_enable || !sg_periodic(h) || !sg_fits_field(s, h)) return LBFD_EINVAL;

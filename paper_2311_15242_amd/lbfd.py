@@ -28,7 +28,8 @@ EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_init_fields", "lbfd_set
             "lbfd_set_tuning", "lbfd_get_tuning", "lbfd_batch_set_tuning",
             "lbfd_sg_n_params", "lbfd_sg_workspace_bytes", "lbfd_sg_create", "lbfd_sg_set_params",
             "lbfd_sg_get_params", "lbfd_sg_forward", "lbfd_sg_gradient", "lbfd_sg_train_step", "lbfd_sg_features",
-            "lbfd_sg_snapshot", "lbfd_sg_tiles", "lbfd_sg_advance", "lbfd_sg_destroy", "lbfd_sg_set_drift_tol"]
+            "lbfd_sg_snapshot", "lbfd_sg_tiles", "lbfd_sg_advance", "lbfd_sg_destroy", "lbfd_sg_set_drift_tol",
+            "lbfd_sg_set_lr"]
 
 
 class LbfdError(RuntimeError):
@@ -190,6 +191,7 @@ def load(build_if_missing: bool = False):
     L.lbfd_sg_advance.argtypes = [vp, vp, i64, P(SgReport)]
     L.lbfd_sg_destroy.argtypes = [vp]
     L.lbfd_sg_set_drift_tol.argtypes = [vp, C.c_double]
+    L.lbfd_sg_set_lr.argtypes = [vp, C.c_double]
     L.lbfd_sg_destroy.restype = None
     _lib = L
     return L
@@ -585,6 +587,11 @@ class Surrogate:
         _check(load().lbfd_sg_tiles(solver.h, self.h, _dptr(feat), _dptr(snap),
                                     org.ctypes.data_as(C.POINTER(C.c_int32)), B, _dptr(x), _dptr(t)), "lbfd_sg_tiles")
         return x, t
+
+    def set_lr(self, lr: float):
+        _check(load().lbfd_sg_set_lr(self.h, float(lr)), "lbfd_sg_set_lr")
+        self.cfg["lr"] = float(lr)
+        return self
 
     def set_drift_tol(self, tol: float):
         _check(load().lbfd_sg_set_drift_tol(self.h, float(tol)), "lbfd_sg_set_drift_tol")

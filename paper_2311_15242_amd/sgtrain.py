@@ -79,14 +79,22 @@ def change_scales(solver, k: int, quantile: float = 0.999):
     return float(max(np.quantile(dpsi, quantile), 1e-12)), float(max(np.quantile(dphi, quantile), 1e-12))
 
 
-def train(sg, X, Y, steps: int, batch: int, rng, log_every: int = 0):
+def train(sg, X, Y, steps: int, batch: int, rng, log_every: int = 0, lr_final: float | None = None):
     """Adam steps on random minibatches of the tiles; returns the loss history
-    (one value per logged step, each read back from the device)."""
+    (one value per logged step, each read back from the device).
+
+    lr_final: the step size falls from the network's configured one to lr_final
+    along a half cosine over the run (None: constant)."""
+    import math
+
     import torch
 
     n = X.shape[0]
     hist = []
+    lr0 = sg.cfg["lr"]
     for it in range(steps):
+        if lr_final is not None:
+            sg.set_lr(lr_final + 0.5 * (lr0 - lr_final) * (1.0 + math.cos(math.pi * it / max(1, steps - 1))))
         idx = torch.as_tensor(rng.choice(n, size=min(batch, n), replace=False), device=X.device)
         xb = X.index_select(0, idx).contiguous()
         yb = Y.index_select(0, idx).contiguous()
@@ -94,6 +102,8 @@ def train(sg, X, Y, steps: int, batch: int, rng, log_every: int = 0):
         loss = sg.train_step(xb, yb, want_loss=want)
         if want:
             hist.append((it, loss))
+    if lr_final is not None:
+        sg.set_lr(lr0)   # the configured step size again for later calls
     return hist
 
 

@@ -162,6 +162,37 @@ def test_gradient_matches_reference(lbfd):
     assert o == g.size
 
 
+def test_step_size_setter_scales_the_first_adam_step(lbfd):
+    """lbfd_sg_set_lr: Adam's first step from fresh moments moves each weight by
+    lr g / (|g| + eps), so a quarter of the step size moves it a quarter as far;
+    a step size that is not positive is rejected."""
+    import torch
+
+    rng = np.random.default_rng(13)
+    T = 4
+    x6 = bf16(rng.uniform(-1.0, 1.0, (2, T + 8, T + 8, T + 8, 6)))
+    t = rng.standard_normal((2, T, T, T, 4)).astype(np.float32)
+    t[..., 2:] = rng.uniform(0.05, 2.0, (2, T, T, T, 2))
+    x, tt = bf16_tensor(padded_input(x6)), torch.from_numpy(t).cuda()
+    p0 = np.float32(OS.flatten(gpu_params(OS.init_params(4, out_scale=1.0))))
+    lr = 1e-3
+    sg = make_sg(lbfd, tile=T, max_batch=2, lr=lr, dpsi_s=0.02, dphi_s=0.005)
+    moves = []
+    for f in (1.0, 0.25):
+        sg.set_params(p0)   # fresh moments and step count
+        sg.set_lr(lr * f)
+        sg.train_step(x, tt, want_loss=False)
+        moves.append(sg.get_params().astype(np.float64) - p0)
+    d1, d2 = moves
+    big = np.abs(d1) > 0.5 * lr
+    say(f"{int(big.sum())} of {p0.size} weights moved by more than lr / 2")
+    assert big.sum() > 0.5 * p0.size
+    assert np.abs(d2[big] - 0.25 * d1[big]).max() <= 1e-3 * lr
+    for bad in (0.0, -1e-3):
+        with pytest.raises(lbfd.LbfdError):
+            sg.set_lr(bad)
+
+
 def _bubbles(lbfd, n=40, seed=1):
     p, q = W.multi_bubble(n=n, count=2, diameter=12.0, seed=seed, precision="fp32")
     return lbfd.Solver(p).init_fields(q), p
