@@ -311,3 +311,44 @@ def test_forward_wide_grid_matches_reference(lbfd, shape, batch):
     err = float(np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max())
     say(f"wide forward {shape} max rel err {err:.2e}")
     assert err < 5e-3
+
+
+def test_forward_full_grid_sampled(lbfd):
+    """The whole-grid forward at the benchmark's size (256^3 output nodes from a
+    264^3 input, the launch the surrogate benchmark times) against the reference
+    at sampled output nodes: the eight corners, points on the faces and edges
+    and random interior nodes, each from its own 9^3 input window."""
+    import torch
+
+    n, H = 256, 4
+    m = n + 2 * H
+    rng = np.random.default_rng(17)
+    x6 = rng.uniform(-1.0, 1.0, (m, m, m, 6)).astype(np.float32)
+    u = x6.view(np.uint32).astype(np.uint64)
+    bits = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    del u
+    full = np.zeros((m, m, m, 16), dtype=np.uint16)
+    full[..., :6] = bits
+    del bits
+    x = torch.from_numpy(full.view(np.int16)).cuda().view(1, m, m, m, 16)
+    del full
+    ps = gpu_params(OS.init_params(7, out_scale=1.0))
+    sg = make_sg(lbfd, tile=16, max_batch=1, field=(n, n, n))
+    sg.set_params(OS.flatten(ps))
+    out = torch.empty((1, n, n, n, OS.NOUT), dtype=torch.float32, device="cuda")
+    sg.forward(x, out)
+    torch.cuda.synchronize()
+    e = (0, n // 2, n - 1)
+    pts = {(a, b, c) for a in (0, n - 1) for b in (0, n - 1) for c in (0, n - 1)}
+    pts |= {(a, b, c) for a in e for b in e for c in e}
+    pts |= {tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(24)}
+    got, ref = [], []
+    for (z, y, xx) in sorted(pts):
+        win = bf16(x6[z:z + 2 * H + 1, y:y + 2 * H + 1, xx:xx + 2 * H + 1])[None]
+        r, _ = ref_forward(ps, win)
+        ref.append(r[0, 0, 0, 0])
+        got.append(out[0, z, y, xx].cpu().numpy())
+    got, ref = np.array(got), np.array(ref)
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    say(f"full-grid forward {n}^3, {len(pts)} sampled nodes: max rel err {err:.2e}")
+    assert err < 5e-3
