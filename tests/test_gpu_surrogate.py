@@ -135,16 +135,19 @@ def test_forward_matches_reference(lbfd):
     assert np.array_equal(sg.get_params(), np.float32(OS.flatten(ps)))
 
 
-def test_gradient_matches_reference(lbfd):
+@pytest.mark.parametrize("T,B", [(4, 2), (32, 8)])
+def test_gradient_matches_reference(lbfd, T, B):
+    """The full gradient of the conservative loss: a tiny tile, and the tiles of
+    the training launch the surrogate benchmark times (32^3 outputs, 8 tiles:
+    128 stages of 256 nodes per tile in the weight gradient)."""
     import torch
 
     rng = np.random.default_rng(12)
     ps = gpu_params(OS.init_params(4, out_scale=1.0))
-    T = 4
-    x6 = bf16(rng.uniform(-1.0, 1.0, (2, T + 8, T + 8, T + 8, 6)))
-    t = rng.standard_normal((2, T, T, T, 4)).astype(np.float32)
-    t[..., 2:] = rng.uniform(0.05, 2.0, (2, T, T, T, 2))     # the weights W, X
-    sg = make_sg(lbfd, tile=T, max_batch=2, dpsi_s=0.02, dphi_s=0.005)
+    x6 = bf16(rng.uniform(-1.0, 1.0, (B, T + 8, T + 8, T + 8, 6)))
+    t = rng.standard_normal((B, T, T, T, 4)).astype(np.float32)
+    t[..., 2:] = rng.uniform(0.05, 2.0, (B, T, T, T, 2))     # the weights W, X
+    sg = make_sg(lbfd, tile=T, max_batch=B, dpsi_s=0.02, dphi_s=0.005)
     sg.set_params(OS.flatten(ps))
     loss, g = sg.gradient(bf16_tensor(padded_input(x6)), torch.from_numpy(t).cuda())
     Lr, gr = ref_gradient(ps, x6, t.astype(np.float64), 0.02 / 0.005)
