@@ -59,6 +59,13 @@ def test_workspace_size_and_validation(lib):
         lbfd.workspace_bytes(dict(p, rhoR0=-1.0))
     with pytest.raises(lbfd.LbfdError):
         lbfd.workspace_bytes(dict(p, sor_max_sweeps=10_000))
+    # 32-bit byte offsets: the largest grids, 16-byte elements (FP64: 32-byte)
+    big = dict(p, nx=512, ny=512)
+    assert lbfd.workspace_bytes(dict(big, nz=1023)) < 70 * 2**30
+    for prec, nz in (("bf16dev", 1024), ("fp64", 512)):
+        with pytest.raises(lbfd.LbfdError):
+            lbfd.workspace_bytes(W.finalize(dict(big, nz=nz, precision=prec)))
+    lbfd.workspace_bytes(W.finalize(dict(big, nz=511, precision="fp64")))
     # alphaB from eq 42 must stay in (0, 1)
     with pytest.raises(lbfd.LbfdError):
         lbfd.workspace_bytes(dict(p, rhoR0=10.0, rhoB0=1.0))
