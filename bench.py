@@ -986,6 +986,7 @@ def class_rooflines(p, prof, steps, sor_half):
         if v:
             r["valu"] = v
         r["bound"] = "alu" if v and v["frac"] >= ALU_BOUND_ISSUE else "hbm"
+        r["bound_frac"] = v["frac"] if r["bound"] == "alu" else r["frac"]   # the labelled roof's fraction
         if cls == "sor":
             r["half_sweeps_with_work"] = sor_half
             r["launches_per_step"] = round(launches / steps, 2)
