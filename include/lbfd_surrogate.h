@@ -138,7 +138,7 @@ int lbfd_sg_advance(lbfd_handle *h, lbfd_sg *s, int64_t nblocks, lbfd_sg_report 
 int lbfd_sg_set_drift_tol(lbfd_sg *s, double tol);
 
 /* Change the Adam step size used by the following lbfd_sg_train_step calls
- * (lr > 0, else LBFD_EINVAL); the moments and the step count are kept, so a
+ * (finite lr > 0, else LBFD_EINVAL); the moments and the step count are kept, so a
  * caller can decay the step size over a training run. */
 int lbfd_sg_set_lr(lbfd_sg *s, double lr);
 

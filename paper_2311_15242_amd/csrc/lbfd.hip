@@ -3546,7 +3546,7 @@ int lbfd_sg_set_drift_tol(lbfd_sg *s, double tol)
 
 int lbfd_sg_set_lr(lbfd_sg *s, double lr)
 {
-    if (!s || !(lr > 0.0)) return LBFD_EINVAL;
+    if (!s || !(lr > 0.0) || !std::isfinite(lr)) return LBFD_EINVAL;
     s->p.lr = lr;
     return LBFD_OK;
 }

@@ -191,7 +191,7 @@ def test_step_size_setter_scales_the_first_adam_step(lbfd):
     say(f"{int(big.sum())} of {p0.size} weights moved by more than lr / 2")
     assert big.sum() > 0.5 * p0.size
     assert np.abs(d2[big] - 0.25 * d1[big]).max() <= 1e-3 * lr
-    for bad in (0.0, -1e-3):
+    for bad in (0.0, -1e-3, float("nan"), float("inf")):
         with pytest.raises(lbfd.LbfdError):
             sg.set_lr(bad)
 
