@@ -1295,6 +1295,56 @@ __global__ __launch_bounds__(256) void kb_sor(const KP<typename P::R> *tab, cons
     if (sweep == 0) block_max_to_slots(bloc[0], bloc[1], k.fld.sorres, RMAX_IDX);
 }
 
+// Sweeps of a batch past the third usually find most instances converged, and one
+// workgroup per tile of every instance then costs a dispatch of every tile. There,
+// kb_sor_live first records per instance (one wavefront each) which systems the
+// coming half-sweep still updates, and kb_sor_late runs that half-sweep on a narrow
+// grid over the live instances only: each workgroup strides over the tiles of each
+// live instance and feeds that instance's residual maxima once. The updates of a
+// colour half-sweep do not depend on their order and the maxima not on their
+// grouping, so every instance gets the result of kb_sor.
+template <int LAT, class P>
+__global__ __launch_bounds__(64) void kb_sor_live(const KP<typename P::R> *tab, int color, int sweep)
+{
+    const KP<typename P::R> &k = tab[blockIdx.x];
+    bool conv[2];
+    sor_conv<LAT, P>(k, color, sweep, conv);
+    if (threadIdx.x == 0) k.fld.sc->sor_live = (conv[0] ? 0u : 1u) | (conv[1] ? 0u : 2u);
+}
+template <int LAT, class P, bool SEAM>
+__global__ __launch_bounds__(256) void kb_sor_late(const KP<typename P::R> *tab, const int *prefix, int ninst,
+                                                  StepArgs sa, int color, int sweep)
+{
+    using R = typename P::R;
+    __shared__ uint32_t live[64];
+    __shared__ unsigned long long lmask;
+    for (int c0 = 0; c0 < ninst; c0 += 64) {
+        if (threadIdx.x < 64) {
+            const uint32_t v = c0 + (int)threadIdx.x < ninst ? tab[c0 + threadIdx.x].fld.sc->sor_live : 0u;
+            live[threadIdx.x] = v;
+            const unsigned long long m = __ballot(v != 0u);
+            if (threadIdx.x == 0) lmask = m;
+        }
+        __syncthreads();
+        unsigned long long m = lmask;
+        while (m) {
+            const int i = __builtin_ctzll(m);
+            m &= m - 1;
+            const int inst = c0 + i;
+            const int nt = prefix[inst + 1] - prefix[inst];
+            if ((int)blockIdx.x >= nt) continue;
+            const KP<R> &k = tab[inst];
+            const uint32_t v = live[i];
+            const bool conv[2] = {(v & 1u) == 0u, (v & 2u) == 0u};
+            const SorOps<R> a = sor_ops(k, sa);
+            R rloc[2] = {0, 0}, bloc[2] = {0, 0};
+            for (int t = blockIdx.x; t < nt; t += gridDim.x) sor_tile<LAT, P, SEAM>(k, a, t, color, conv, rloc, bloc);
+            block_max_to_slots(conv[0] ? R(-1) : rloc[0], conv[1] ? R(-1) : rloc[1], k.fld.sorres, 2 * sweep + color);
+        }
+        __syncthreads();   // live and lmask are rewritten for the next 64 instances
+    }
+}
+
 // One parity half-sweep of one seam level (one thread per entry of the seam index space).
 template <int LAT, class P>
 __global__ __launch_bounds__(256) void k_sor_seam(KP<typename P::R> k, int level, int color, int sweep)
@@ -2421,14 +2471,24 @@ template <int LAT, class P> struct Impl {
             const bool fd = h->p.fd_enable != 0;
             if (fd) {
                 LAUNCH(KC_FD, (kb_fd<LAT, P>), b->grid_node, blk, tab, b->prefix_node, n, sa);
+                const dim3 g_late((unsigned)std::min((int)b->grid_sor.x, h->sor_narrow));
                 for (int s = 0; s < h->sweeps_launch; ++s) {
-                    if (b->seam_levels == 0) {
-                        LAUNCH(KC_SOR, (kb_sor<LAT, P, false>), b->grid_sor, dim3(256), tab, b->prefix_sor, n, sa, 0, s);
-                        LAUNCH(KC_SOR, (kb_sor<LAT, P, false>), b->grid_sor, dim3(256), tab, b->prefix_sor, n, sa, 1, s);
-                        continue;
+                    for (int c = 0; c < 2; ++c) {
+                        if (s >= 3) {
+                            LAUNCH(KC_SOR, (kb_sor_live<LAT, P>), dim3(n), dim3(64), tab, c, s);
+                            if (b->seam_levels == 0)
+                                LAUNCH(KC_SOR, (kb_sor_late<LAT, P, false>), g_late, dim3(256), tab, b->prefix_sor, n, sa,
+                                       c, s);
+                            else
+                                LAUNCH(KC_SOR, (kb_sor_late<LAT, P, true>), g_late, dim3(256), tab, b->prefix_sor, n, sa,
+                                       c, s);
+                        } else if (b->seam_levels == 0) {
+                            LAUNCH(KC_SOR, (kb_sor<LAT, P, false>), b->grid_sor, dim3(256), tab, b->prefix_sor, n, sa, c, s);
+                        } else {
+                            LAUNCH(KC_SOR, (kb_sor<LAT, P, true>), b->grid_sor, dim3(256), tab, b->prefix_sor, n, sa, c, s);
+                        }
                     }
-                    LAUNCH(KC_SOR, (kb_sor<LAT, P, true>), b->grid_sor, dim3(256), tab, b->prefix_sor, n, sa, 0, s);
-                    LAUNCH(KC_SOR, (kb_sor<LAT, P, true>), b->grid_sor, dim3(256), tab, b->prefix_sor, n, sa, 1, s);
+                    if (b->seam_levels == 0) continue;
                     for (int lv = 1; lv <= b->seam_levels; ++lv) {
                         LAUNCH(KC_SOR, (kb_sor_seam<LAT, P>), b->grid_seam, dim3(256), tab, b->prefix_seam, n, sa, lv,
                                0, s);

@@ -172,6 +172,8 @@ struct DevScalars {
     uint32_t tick;                // geometry launches since the state was set (one per step):
                                   // the time input of the stochastic rounding
     uint32_t sg_bad;              // nodes where a surrogate candidate changed psi or phi implausibly
+    uint32_t sor_live;            // batched solve, sweeps past the third: systems of this instance
+                                  // not yet converged before the coming half-sweep (bit 0 psi, bit 1 phi)
     double Mref;                  // total of the state a surrogate candidate starts from
 };
 
@@ -614,6 +616,9 @@ __device__ __forceinline__ void block_max_to_slots(R v0, R v1, unsigned long lon
         for (int fi = 0; fi < 2; ++fi)
             if (m[fi] >= 0.0) atomic_max_nonneg(res_slot(base, fi, idx, slot), m[fi]);
     }
+    // thread 0 reads red above; a second call right after this one (the |rhs| maxima
+    // of sweep 0) may overwrite it only once that read is done
+    __syncthreads();
 }
 
 // Zero the slots of the 2 nsw half-sweeps and of max |rhs| (threads of one block).
