@@ -113,6 +113,37 @@ def algorithmic_bytes(kernel: str, p: dict) -> float:
     return float(table.get(kernel, 0.0))
 
 
+def hbm_probe(mib=1024, reps=20):
+    """Bandwidth a plain device copy and a plain fill of `mib` MiB reach on this GPU
+    (torch's own copy and fill kernels, HIP events, mean of `reps` launches after
+    one untimed launch): the practical ceiling of a streaming kernel, stated beside
+    the published peak the rooflines use."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            f()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / reps / 1e3
+
+    tc = timed(lambda: b.copy_(a))
+    tf = timed(lambda: b.fill_(2.0))
+    out = dict(bytes=4 * n, copy_GBps=round(8 * n / tc / 1e9, 1), fill_GBps=round(4 * n / tf / 1e9, 1),
+               peak=HBM_PEAK_GBS, note="copy counts bytes read and written")
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def build_solver(p, q, tuning="auto"):
     from paper_2311_15242_amd import lbfd
 
@@ -1396,6 +1427,8 @@ def main():
                     help="store VALU instructions per wave of every kernel class (SQ_INSTS_VALU, SQ_WAVES) and exit")
     ap.add_argument("--no-fixed-shape", action="store_true",
                     help="skip the comparison run in the default launch shape (profiler runs: one shape per kernel)")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="print the bandwidth of a plain 1 GiB device copy and fill, then exit")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the deviation modes' errors against the FP32 and FP64 GPU solvers")
     ap.add_argument("--accuracy-steps", type=int, default=500)
@@ -1441,6 +1474,9 @@ def main():
         return
     if args.autotune:
         print(json.dumps(autotune(args.autotune, args.workload, args.precision, args.warmup)), flush=True)
+        return
+    if args.hbm_probe:
+        print(json.dumps(hbm_probe()), flush=True)
         return
     if args.copy_calibration:
         import torch
@@ -1545,6 +1581,8 @@ def main():
                                   mlups=[round(N * args.steps / (r / 1e3) / 1e6, 1) for r in runs]),
                tuning=tuning, roofline=roof, rooflines=rooflines, step_bandwidth=step_bw, useful_bandwidth=useful,
                kernels=breakdown, ms_per_step_profiled=round(ms_prof / args.steps, 4))
+    out["hbm_probe"] = hbm_probe()
+    out["roofline"]["frac_of_copy"] = round(out["roofline"]["hbm"]["achieved"] / out["hbm_probe"]["copy_GBps"], 4)
     if not args.no_accuracy:
         out["accuracy"] = accuracy_report(args.workload, p["precision"], args.accuracy_steps)
 
