@@ -94,8 +94,8 @@ def algorithmic_bytes(kernel: str, p: dict) -> float:
     qc = [(1.0 - 1.5 * (1.0 - al)) if three else (1.8 * al - 0.8) for al in (p["alphaR"], alphaB)]
     qf = D if any(abs(c) > 1e-15 for c in qc) else 0
     table = {
-        # state in, Q populations out; rhoR rhoB, u, F, normal, G, qf in; descriptor out
-        "collide": (state + Q) * bf + (2 + 3 * D + 1 + qf) * br + desc_b,
+        # state in, Q populations out; rhoR rhoB, u, F, normal, qf in; descriptor out
+        "collide": (state + Q) * bf + (2 + 3 * D + qf) * br + desc_b,
         # Q populations in, descriptor in, rhoR rhoB rhoN j out (+ moment state out)
         "macro": (Q + (state if dev else 0)) * bf + (3 + D) * br + desc_b,
         # rhoN in; |grad rhoN|, normal and the colour-split weights of both implicit systems out

@@ -629,11 +629,14 @@ __device__ __forceinline__ void collide_body(const KP<typename P::R> &k, int til
         }
         m[r] = m[r] - sr * (m[r] - meq[r]) + (R(1) - R(0.5) * sr) * (C[r] + Fm[r]);
     }
-    // recolouring descriptor (eqs 11-12): colour share and c = beta rho^R rho^B / rho g/|g|,
-    // g/|g| = -n sqrt(|g|^2 + eps_n^2) / |g| with the geometry kernel's n and |g|
+    // recolouring descriptor (eqs 11-12): colour share and c = beta rho^R rho^B / rho g/|g|;
+    // the geometry kernel's n = -g / sqrt(|g|^2 + eps_n^2) is parallel to -g, so
+    // g/|g| = -n/|n| (n = 0 where g = 0)
     const R a = rR * irho;
-    const R Gm = ld(k.fld.G[sa.lev], n);
-    const R cf = Gm > R(0) ? -k.beta * (a * rB) * (sqrt(Gm * Gm + k.eps_n * k.eps_n) / Gm) : R(0);
+    R nn = nv[0] * nv[0];
+#pragma unroll
+    for (int d = 1; d < D; ++d) nn += nv[d] * nv[d];
+    const R cf = nn > R(0) ? -k.beta * (a * rB) / sqrt(nn) : R(0);
     R us[3] = {0, 0, 0};
     if constexpr (P::DEV) {
         // packed descriptor; the reference velocity is used as stored (FP16), so that
@@ -978,9 +981,10 @@ template <int LAT, class P> __device__ __forceinline__ void fd_body(const KP<typ
         for (int o = -2; o <= 2; ++o) {
             const uint32_t q = o == 0 ? n : n + (uint32_t)nb.d[a][slot_of(o)];
             const R sg = (o != 0 && ((nb.mir >> (a * 4 + slot_of(o))) & 1u)) ? R(-1) : R(1);
-            R ua = ld(uv + a * N, q);
-            Pp[o + 2] = sg * ((s * ld(psiA, q)) * (ld(G0, q) + k.fd_eps) * ua);
-            Pf[o + 2] = sg * ((s * ld(phiA, q)) * ((R(1) - ld(rN0, q)) + k.fd_eps) * ua);
+            // the lazy scale of the stored psi, phi and the mirror sign ride on u_a
+            const R su = sg * (s * ld(uv + a * N, q));
+            Pp[o + 2] = (ld(psiA, q) * (ld(G0, q) + k.fd_eps)) * su;
+            Pf[o + 2] = (ld(phiA, q) * ((R(1) - ld(rN0, q)) + k.fd_eps)) * su;
         }
         // H+ = u+/|u| and H- = |u-|/|u| are exactly 1 or 0 away from the +-upwind_eps band
         R Dm, Dp, ua = ld(uv + a * N, n);
@@ -999,7 +1003,8 @@ template <int LAT, class P> __device__ __forceinline__ void fd_body(const KP<typ
     const R Sn = -divP + Gn * jj, Bn = -divF - Gn * jj;
     const R eS = sa.step == 0 ? Sn : R(1.5) * Sn - R(0.5) * ld(k.fld.Sp, n);
     const R eB = sa.step == 0 ? Bn : R(1.5) * Bn - R(0.5) * ld(k.fld.Bp, n);
-    // diffusion operator of eq 28 with half-point weights, as printed
+    // diffusion operator of eq 28 with half-point weights, as printed (the neighbour sums
+    // over the stored psi, phi, scaled once)
     R swP = 0, swcP = 0, swF = 0, swcF = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a)
@@ -1008,13 +1013,13 @@ template <int LAT, class P> __device__ __forceinline__ void fd_body(const KP<typ
             const uint32_t q = n + (uint32_t)nb.d[a][slot_of(o)];
             R wP = R(0.5) * (Gn + (ld(G0, q) + k.fd_eps));
             R wF = R(0.5) * (Xn + ((R(1) - ld(rN0, q)) + k.fd_eps));
-            swcP += wP * (s * ld(psiA, q));
+            swcP += wP * ld(psiA, q);
             swP += wP;
-            swcF += wF * (s * ld(phiA, q));
+            swcF += wF * ld(phiA, q);
             swF += wF;
         }
-    const R rhP = Gn * psi + R(0.5) * k.Ds * (swcP - swP * psi) + eS;
-    const R rhF = Xn * phi + R(0.5) * k.Db * (swcF - swF * phi) + eB;
+    const R rhP = Gn * psi + R(0.5) * k.Ds * (s * swcP - swP * psi) + eS;
+    const R rhF = Xn * phi + R(0.5) * k.Db * (s * swcF - swF * phi) + eB;
     st(k.fld.Sp, n, Sn);
     st(k.fld.Bp, n, Bn);
     // initial guess of the implicit solve: linear extrapolation from the two
@@ -1385,6 +1390,8 @@ template <class R> __device__ __forceinline__ void sor_done_body(const KP<R> &k,
 {
     DevScalars *sc = k.fld.sc;
     const int lane = threadIdx.x & 63;
+    // residual maxima of the sweeps, four sweeps' slots loaded before any is reduced
+    const auto res = [&](int fi, int e) { return e <= 2 * nsw ? bits_to_double(*res_slot(k.fld.sorres, fi, e, lane)) : 0.0; };
     for (int fi = 0; fi < 2; ++fi) {
         const double rm = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, RMAX_IDX, lane)));
         const double lim = (double)k.tol * rm;
@@ -1392,15 +1399,31 @@ template <class R> __device__ __forceinline__ void sor_done_body(const KP<R> &k,
         bool ok = false;
         if (k.sor_exact) {
             // whole residual after s sweeps = red residual at the start of sweep s
-            for (int s = 1; s < nsw; ++s) {
-                const double r = wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, 2 * s, lane)));
-                if (r <= lim) { K = s; ok = true; break; }
+            for (int s0 = 1; s0 < nsw && !ok; s0 += 4) {
+                double v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = res(fi, 2 * (s0 + i));
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int s = s0 + i;
+                    if (ok || s >= nsw) continue;
+                    if (wave_max(v[i]) <= lim) { K = s; ok = true; }
+                }
             }
         } else {
-            for (int s = 1; s <= nsw; ++s) {
-                const double r = fmax(wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, 2 * (s - 1), lane))),
-                                      wave_max(bits_to_double(*res_slot(k.fld.sorres, fi, 2 * (s - 1) + 1, lane))));
-                if (r <= lim) { K = s; ok = true; break; }
+            for (int s0 = 1; s0 <= nsw && !ok; s0 += 4) {
+                double v[4], w[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    v[i] = res(fi, 2 * (s0 + i - 1));
+                    w[i] = res(fi, 2 * (s0 + i - 1) + 1);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int s = s0 + i;
+                    if (ok || s > nsw) continue;
+                    if (fmax(wave_max(v[i]), wave_max(w[i])) <= lim) { K = s; ok = true; }
+                }
             }
         }
         if (lane == 0) {
