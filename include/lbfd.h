@@ -300,9 +300,11 @@ lbfd_handle *lbfd_batch_instance(lbfd_batch *b, int32_t i);
  * (initialised, or set to the same step, together), else EINVAL. Asynchronous. */
 int lbfd_batch_step(lbfd_batch *b, int64_t n);
 
-/* Launch shape of every instance of a batch (the batch launches one workgroup
- * per SOR tile of each instance, so only `rows` changes its launches). Errors:
- * EINVAL, EHIP. */
+/* Launch shape of every instance of a batch: `rows` for the node kernels and
+ * `sor_narrow` for the SOR sweeps past the third, which run over the instances
+ * still converging (the first three sweeps launch one workgroup per SOR tile of
+ * every instance, so `sor_wg_per_cu` does not change the batch's launches).
+ * Errors: EINVAL, EHIP. */
 int lbfd_batch_set_tuning(lbfd_batch *b, const lbfd_tuning *t);
 
 /* Graph replay of lbfd_batch_step, as lbfd_set_graphs for one handle. */

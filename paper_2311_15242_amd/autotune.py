@@ -12,7 +12,8 @@ reductions keep a fixed shape):
 * ``sor_wg_per_cu``: the persistent grid of the SOR half-sweeps, in workgroups
   of 256 per compute unit;
 * ``sor_narrow``: the grid of sweeps past the third, which mostly find both
-  systems converged and return.
+  systems converged and return (in a batch: which run over the instances
+  still converging).
 
 Each candidate is timed over whole steps with HIP events on the solver's
 stream (median of several timed regions); the fastest is stored per workload
@@ -70,14 +71,16 @@ def tune_solver(params: dict, init: dict, steps: int = 20, warmup: int = 6, regi
 
 
 def tune_batch(params_list, inits, steps: int = 10, warmup: int = 4, regions: int = 3) -> dict:
-    """Sweep rows on a batch (its SOR launches one workgroup per tile)."""
+    """Sweep rows x narrow grid on a batch (its first three SOR sweeps launch one
+    workgroup per tile of every instance; the narrow grid runs the later sweeps
+    over the instances still converging)."""
     b = lbfd.Batch(params_list, tuning=None)
     for m, q in zip(b.members, inits):
         m.init_fields(q)
     b.step(warmup)
     table = []
-    for rows in ROWS:
-        t = dict(lbfd.DEFAULT_TUNING, rows=rows)
+    for rows, nar in itertools.product(ROWS, SOR_NARROW):
+        t = dict(lbfd.DEFAULT_TUNING, rows=rows, sor_narrow=nar)
         b.set_tuning(t).step(4)
         table.append((_time(b, steps, regions), t))
     b.set_tuning(lbfd.DEFAULT_TUNING).step(4)
