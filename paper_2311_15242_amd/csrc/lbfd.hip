@@ -1386,7 +1386,9 @@ __global__ __launch_bounds__(256) void kb_sor_seam(const KP<typename P::R> *tab,
 // Sweep counts of the last solve; LBFD_ESOR when a system never met its tolerance.
 // One wavefront: lane l reads residual slot l. Afterwards it clears the slots of
 // every half-sweep and of the |rhs| maxima for the next step.
-template <class R> __device__ __forceinline__ void sor_done_body(const KP<R> &k, int nsw)
+// One wavefront: the sweep counts and max |rhs| of the last solve, and LBFD_ESOR when a
+// system did not converge within the nsw sweeps launched.
+template <class R> __device__ __forceinline__ void sor_record(const KP<R> &k, int nsw)
 {
     DevScalars *sc = k.fld.sc;
     const int lane = threadIdx.x & 63;
@@ -1432,15 +1434,8 @@ template <class R> __device__ __forceinline__ void sor_done_body(const KP<R> &k,
             if (!ok && sc->status == 0) sc->status = LBFD_ESOR;
         }
     }
-    sor_slots_clear(k.fld.sorres, nsw);
 }
-template <class R> __global__ void k_sor_done(KP<R> k, int nsw) { sor_done_body(k, nsw); }
 // batch: one wavefront per instance
-template <class R> __global__ void kb_sor_done(const KP<R> *tab, int nsw)
-{
-    sor_done_body(tab[blockIdx.x], nsw);
-}
-
 // Clears the residual and |rhs| slots (set-up, before the first step).
 template <class R> __global__ void k_sor_clear(KP<R> k, int nsw) { sor_slots_clear(k.fld.sorres, nsw); }
 
@@ -1654,10 +1649,17 @@ __global__ __launch_bounds__(256) void kb_total_part(const KP<typename P::R> *ta
     batch_tile(prefix, ninst, inst, local);
     total_part_body<LAT, P>(tab[inst], level, buf, mult, local, prefix[inst + 1] - prefix[inst], from_split);
 }
-template <class R> __device__ __forceinline__ void total_final_body(const KP<R> &k, long long nblocks, int mode)
+template <class R> __device__ __forceinline__ void total_final_body(const KP<R> &k, long long nblocks, int mode, int nsw)
 {
     __shared__ double sh[256];
     const int t = threadIdx.x;
+    if (nsw > 0) {
+        // after a solve: record its sweeps (first wavefront), then clear its residual
+        // slots for the next one (the total's partial sums read none of them)
+        if (t < 64) sor_record(k, nsw);
+        __syncthreads();
+        sor_slots_clear(k.fld.sorres, nsw);
+    }
     double a = 0.0;
     for (long long b = t; b < nblocks; b += 256) a += k.fld.part[b];
     sh[t] = a;
@@ -1690,11 +1692,14 @@ template <class R> __device__ __forceinline__ void total_final_body(const KP<R> 
         }
     }
 }
-template <class R> __global__ void k_total_final(KP<R> k, long long nblocks, int mode) { total_final_body(k, nblocks, mode); }
-template <class R> __global__ void kb_total_final(const KP<R> *tab, const int *prefix, int mode)
+template <class R> __global__ void k_total_final(KP<R> k, long long nblocks, int mode, int nsw)
+{
+    total_final_body(k, nblocks, mode, nsw);
+}
+template <class R> __global__ void kb_total_final(const KP<R> *tab, const int *prefix, int mode, int nsw)
 {
     const int i = blockIdx.x;
-    total_final_body(tab[i], (long long)(prefix[i + 1] - prefix[i]), mode);
+    total_final_body(tab[i], (long long)(prefix[i + 1] - prefix[i]), mode, nsw);
 }
 
 // Observables, pass 0: sums and extrema; pass 1: central second moments.
@@ -2233,11 +2238,12 @@ template <int LAT, class P> struct Impl {
 
     // Total of level `level` with psi, phi of buffer `buf` (from_split: take them from
     // the solve's colour-split iterates and store them into `buf` on the way).
-    static void totals(lbfd_handle *h, int level, int buf, double mult, int mode, int from_split = 0)
+    static void totals(lbfd_handle *h, int level, int buf, double mult, int mode, int from_split = 0,
+                       int solve_sweeps = 0)
     {
         KP<R> &k = kp(h);
         LAUNCH(KC_TOTAL, (k_total_part<LAT, P>), dim3(h->tblocks), dim3(256), k, level, buf, mult, from_split);
-        LAUNCH(KC_TOTAL, (k_total_final<R>), dim3(1), dim3(256), k, (long long)h->tblocks, mode);
+        LAUNCH(KC_TOTAL, (k_total_final<R>), dim3(1), dim3(256), k, (long long)h->tblocks, mode, solve_sweeps);
     }
 
     static void derived(lbfd_handle *h)
@@ -2363,8 +2369,8 @@ template <int LAT, class P> struct Impl {
                 LAUNCH(KC_SOR, (k_sor_seam<LAT, P>), dim3(h->seam_tiles), dim3(256), k, lv, 1, s);
             }
         }
-        LAUNCH(KC_OTHER, (k_sor_done<R>), dim3(1), dim3(64), k, h->sweeps_launch);
-        totals(h, 1 - k.lev, 1 - k.pc, 1.0, 1, 1);
+        // the final reduction of the total also records the solve's sweeps and clears its slots
+        totals(h, 1 - k.lev, 1 - k.pc, 1.0, 1, 1, h->sweeps_launch);
         h->pc = 1 - h->pc;
         h->fd_hist += 1;
         sync_levels(h);
@@ -2519,10 +2525,9 @@ template <int LAT, class P> struct Impl {
                                1, s);
                     }
                 }
-                LAUNCH(KC_OTHER, (kb_sor_done<R>), dim3(n), dim3(64), tab, h->sweeps_launch);
                 LAUNCH(KC_TOTAL, (kb_total_part<LAT, P>), b->grid_total, dim3(256), tab, b->prefix_total, n,
                        1 - sa.lev, 1 - sa.pc, 1.0, 1);
-                LAUNCH(KC_TOTAL, (kb_total_final<R>), dim3(n), dim3(256), tab, b->prefix_total, 1);
+                LAUNCH(KC_TOTAL, (kb_total_final<R>), dim3(n), dim3(256), tab, b->prefix_total, 1, h->sweeps_launch);
             }
             for (lbfd_handle *x : b->inst) {
                 if (fd) {
